@@ -1,0 +1,104 @@
+"""Test infrastructure: ctypes binding of the plain CPU oracle.
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the device library
+and its binding) never calls it.  See ``sccg_oracle.c`` for what each function
+computes and the passage of the paper it follows.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsccg_oracle.so")
+_lib = None
+
+PURE = 0
+ROWS = 1
+
+
+class _Polys(ctypes.Structure):
+    _fields_ = [("n_polys", ctypes.c_int64), ("offsets", ctypes.c_void_p), ("xy", ctypes.c_void_p)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"oracle library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.sccg_oracle_pixel_inside.restype = ctypes.c_int
+    lib.sccg_oracle_pixel_inside.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+    lib.sccg_oracle_poly_area.restype = ctypes.c_int64
+    lib.sccg_oracle_poly_area.argtypes = [ctypes.POINTER(_Polys), ctypes.c_int64]
+    lib.sccg_oracle_area_pairs.restype = None
+    lib.sccg_oracle_area_pairs.argtypes = [ctypes.POINTER(_Polys), ctypes.POINTER(_Polys), ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int, ctypes.c_int]
+    lib.sccg_oracle_jaccard_sets.restype = None
+    lib.sccg_oracle_jaccard_sets.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+    _lib = lib
+    return lib
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _polys(P):
+    off = _c(P.off, np.int64)
+    xy = _c(P.xy, np.int32)
+    s = _Polys(len(off) - 1, off.ctypes.data, xy.ctypes.data)
+    return s, (off, xy)
+
+
+def pixel_inside(ring, x: int, y: int) -> int:
+    r = _c(ring, np.int32)
+    return int(_load().sccg_oracle_pixel_inside(r.ctypes.data, len(r), x, y))
+
+
+def poly_areas(P) -> np.ndarray:
+    lib = _load()
+    s, keep = _polys(P)
+    return np.array([lib.sccg_oracle_poly_area(ctypes.byref(s), k) for k in range(s.n_polys)], np.int64)
+
+
+def area_pairs(A, B, pa, pb, form: int = PURE, threads: int | None = None):
+    """Exact (I, U) int64 per pair; form PURE or ROWS."""
+    lib = _load()
+    sa, ka = _polys(A)
+    sb, kb = _polys(B)
+    pa = _c(pa, np.int32)
+    pb = _c(pb, np.int32)
+    n = len(pa)
+    I = np.zeros(n, np.int64)
+    U = np.zeros(n, np.int64)
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    lib.sccg_oracle_area_pairs(ctypes.byref(sa), ctypes.byref(sb), n, pa.ctypes.data, pb.ctypes.data,
+                               I.ctypes.data, U.ctypes.data, form, threads)
+    return I, U
+
+
+def jaccard_sets(set_off, I, U, include_zero: bool = False):
+    """Per set: (sum_i, sum_u, n_contrib, J, J')."""
+    lib = _load()
+    so = _c(set_off, np.int64)
+    I = _c(I, np.int64)
+    U = _c(U, np.int64)
+    ns = len(so) - 1
+    si = np.zeros(ns, np.int64)
+    su = np.zeros(ns, np.int64)
+    nn = np.zeros(ns, np.int64)
+    j = np.zeros(ns, np.float64)
+    jp = np.zeros(ns, np.float64)
+    lib.sccg_oracle_jaccard_sets(ns, so.ctypes.data, I.ctypes.data, U.ctypes.data, int(include_zero),
+                                 si.ctypes.data, su.ctypes.data, nn.ctypes.data, j.ctypes.data, jp.ctypes.data)
+    return si, su, nn, j, jp
