@@ -1,0 +1,196 @@
+/* sccg — exact pixel areas of intersection and union of rectilinear polygon
+ * pairs on AMD MI355X (gfx950), by PixelBox sampling-box subdivision.
+ *
+ * Method (Section 3 of "Accelerating Pathology Image Data Cross-Comparison
+ * on CPU-GPU Hybrid Systems", Wang et al.):
+ *   - polygons have integer vertices and axis-aligned edges (Section 3.1,
+ *     Figure 3), so a pixel is either wholly inside or wholly outside;
+ *   - |p ∩ q| counts the pixels inside both; |p ∪ q| = |p| + |q| − |p ∩ q|
+ *     with |p| from the shoelace formula (Section 3.2);
+ *   - the pair box is recursively split into sampling boxes; a box is
+ *     inside / outside / hovering each polygon (Lemma 1); boxes decided for
+ *     both polygons contribute at once, hovering boxes are split again until
+ *     they fall under the pixelization threshold, where every pixel is
+ *     tested by an even-odd ray-crossing count (Sections 3.1–3.3,
+ *     Algorithm 1);
+ *   - two polygon sets are compared by the Jaccard ratio of summed
+ *     intersections over summed unions (Section 2.1), and by the mean of the
+ *     per-pair ratios over pairs that intersect (Equation 1).
+ *
+ * Conventions for every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller; the library
+ *     borrows them until the work queued on the context's stream completes.
+ *   - Calls are asynchronous on the context's stream.  Argument errors are
+ *     returned at once and nothing is queued.  Errors found on the device
+ *     (see SCCG_E_RANGE) are latched in a device error word and returned by
+ *     sccg_sync().
+ *   - Return 0 (SCCG_OK) or a negative error code; sccg_last_error() gives a
+ *     message.  A context is used by one host thread at a time.
+ *
+ * Polygon storage (CSR): polygon k is the ring
+ *   xy[2*offsets[k]], xy[2*offsets[k]+1], ..., up to 2*offsets[k+1]-1
+ * as interleaved int32 (x, y) vertices.  The ring is implicitly closed,
+ * either orientation; a repeated closing vertex or collinear vertices are
+ * allowed (zero-length or split edges do not change any count).  Polygons
+ * must be simple, hole-free, with axis-aligned edges (sccg_validate_polys
+ * checks the last two); |x|, |y| <= 2^30.  Pixel (x, y) is the unit square
+ * [x, x+1) x [y, y+1).
+ */
+#ifndef SCCG_H
+#define SCCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ errors ---- */
+#define SCCG_OK 0
+#define SCCG_E_ARG -1    /* null pointer with a non-zero count, negative count, bad mode/flag/param */
+#define SCCG_E_RANGE -2  /* (device) pair index out of range, pair-box side > 32767, |coord| > 2^30 */
+#define SCCG_E_POLY -3   /* (validate) non-axis-aligned edge or ring of fewer than 4 vertices */
+#define SCCG_E_HIP -4    /* a HIP runtime call failed; message carries hipGetErrorString */
+#define SCCG_E_NOMEM -5  /* device allocation failed */
+#define SCCG_E_DEVICE -6 /* (device) a kernel's bounded wait ran out (watchdog) */
+#define SCCG_E_STATE -7  /* call not allowed in the context's current state */
+
+/* ------------------------------------------------------------- modes ---- */
+/* PLAIN: Algorithm 1 as printed: one pair per workgroup, a shared box stack,
+ * one sub-box per thread tested against every edge, one pixel per thread at
+ * the leaves tested against every edge. */
+#define SCCG_PLAIN 0u
+/* BATCHED: one persistent launch over all pairs with a device task queue
+ * that spreads the hovering sampling boxes of large pairs over workgroups;
+ * edge-parallel box classification, band-culled edges and bit-sliced
+ * 64x64-pixel leaves. */
+#define SCCG_BATCHED 1u
+
+/* sccg_params.flags (ablation switches; none changes any count) */
+#define SCCG_F_NO_LPT 0x1u          /* batched: no largest-first ordering of large pairs      */
+#define SCCG_F_NO_KNOWN_INSIDE 0x2u /* batched: re-test a polygon already known to contain a box */
+#define SCCG_F_NO_SPLIT_QUEUE 0x4u  /* batched: a large pair's boxes stay with the wave that split it */
+#define SCCG_F_NO_GRAPH 0x8u        /* batched: launch the kernels directly, no HIP graph      */
+
+/* sccg_jaccard_sets flags */
+#define SCCG_J_NONZERO_ONLY 0u /* default: only pairs with I > 0 contribute (Equation 1's filter) */
+#define SCCG_J_INCLUDE_ZERO 1u /* every pair contributes                                          */
+
+typedef struct sccg_ctx sccg_ctx;
+
+typedef struct {
+  int64_t n_polys;
+  const int64_t* offsets; /* [n_polys+1], offsets[0] = 0, non-decreasing (device)   */
+  const int32_t* xy;      /* [2*offsets[n_polys]] interleaved x, y (device)          */
+} sccg_polys;
+
+/* Tuning parameters.  0 in any field means "default or autotuned".  No value
+ * changes any count; out-of-range values give SCCG_E_ARG. */
+typedef struct {
+  int32_t wg_size;        /* PLAIN: threads per workgroup, 64/128/256 (default 64)                  */
+  int32_t box_threshold;  /* PLAIN: pixelize when BOXSIZE < T (default wg_size^2/2, Section 3.4)     */
+  int32_t split_gx;       /* PLAIN: sub-box grid; split_gx*split_gy == wg_size (default square-ish) */
+  int32_t split_gy;
+  int32_t queue_chunk;    /* BATCHED: small pairs claimed per queue access (default 8)                */
+  int32_t lds_vertex_cap; /* PLAIN: vertices of both rings staged in LDS, 1..4096 (default 1024; above
+                             it the rings are read from global memory)                               */
+  uint32_t flags;         /* SCCG_F_*                                                                 */
+  int32_t grid;           /* workgroups of the persistent (BATCHED) or grid-stride (PLAIN) launch    */
+  int32_t queue_cap;      /* BATCHED: slots per task queue, 1..2^26 (default 2^20); a full queue makes
+                             the producing wave process its boxes itself                             */
+  int32_t waves_per_wg;   /* BATCHED: waves per workgroup, 1..8 (default 4)                          */
+  int32_t min_queue_cells;/* BATCHED: a split publishes its boxes to the queue only when at least this
+                             many continue (default 8); fewer stay with the splitting wave          */
+  int32_t n_queues;       /* BATCHED: device queues, 1..8 (default 8, one per XCD)                   */
+  int32_t heavy_side;     /* BATCHED: large pairs whose box area is at least heavy_side^2 are claimed
+                             first (default 128)                                                    */
+} sccg_params;
+
+/* Create a context on HIP device `hip_device` using stream `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  `params` may be NULL.
+ * The context owns its scratch (polygon metadata, queues, counters). */
+int sccg_create(sccg_ctx** out, int hip_device, void* hip_stream, const sccg_params* params);
+
+/* Synchronize the context's stream and free everything the context owns. */
+int sccg_destroy(sccg_ctx* ctx);
+
+/* Replace the tuning parameters (same rules as sccg_create). */
+int sccg_set_params(sccg_ctx* ctx, const sccg_params* params);
+int sccg_get_params(const sccg_ctx* ctx, sccg_params* out);
+
+/* Pre-size the scratch so that later calls up to these sizes allocate
+ * nothing (needed before capturing calls into a HIP graph). */
+int sccg_reserve(sccg_ctx* ctx, int64_t max_polys_a, int64_t max_polys_b, int64_t max_pairs);
+
+/* Per pair k: out_inter[k] = |A[pair_a[k]] ∩ B[pair_b[k]]| and
+ * out_union[k] = |A[pair_a[k]] ∪ B[pair_b[k]]| in pixels (int64), exactly.
+ * Section 3's problem statement: an array of polygon pairs in, areas of
+ * intersection and union out.  mode = SCCG_PLAIN or SCCG_BATCHED; both give
+ * identical counts.  A pair whose index is out of range or whose pair box
+ * (MBR(p) ∩ MBR(q)) has a side above 32767 gets 0, 0 and latches
+ * SCCG_E_RANGE.  Output arrays must not alias inputs. */
+int sccg_area_pairs(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, int64_t n_pairs,
+                    const int32_t* pair_a, const int32_t* pair_b, int64_t* out_inter, int64_t* out_union,
+                    uint32_t mode);
+
+/* Per set s over pairs [set_pair_off[s], set_pair_off[s+1]) (Section 2.1 and
+ * Equation 1):
+ *   out_sum_i[s], out_sum_u[s] = sums of inter / union over contributing pairs (int64),
+ *   out_n_contrib[s]           = number of contributing pairs,
+ *   out_j[s]                   = (double)sum_i / (double)sum_u, one IEEE division (0 if sum_u == 0),
+ *   out_jprime[s] (nullable)   = mean of inter/union over contributing pairs: each ratio is one
+ *                                IEEE division, their sum is formed exactly and rounded once to
+ *                                binary64, then divided by n (0 if n == 0).
+ * Contributing = inter > 0 unless flags has SCCG_J_INCLUDE_ZERO.  set_pair_off
+ * must be non-decreasing with set_pair_off[0] >= 0 (all device pointers). */
+int sccg_jaccard_sets(sccg_ctx* ctx, int64_t n_sets, const int64_t* set_pair_off, const int64_t* inter,
+                      const int64_t* uni, uint32_t flags, int64_t* out_sum_i, int64_t* out_sum_u,
+                      int64_t* out_n_contrib, double* out_j, double* out_jprime);
+
+/* Check every ring of P: at least 4 vertices and every edge axis-aligned.
+ * Writes the smallest bad polygon index, or -1, to *out_first_bad (device
+ * int64).  Asynchronous; read the value after sccg_sync. */
+int sccg_validate_polys(sccg_ctx* ctx, const sccg_polys* P, int64_t* out_first_bad);
+
+/* Wait for the context's stream; return SCCG_E_RANGE / SCCG_E_DEVICE if the
+ * device latched an error since the last sync (and clear it), else SCCG_OK. */
+int sccg_sync(sccg_ctx* ctx);
+
+/* Work counters of the last sccg_area_pairs call, valid after sccg_sync.
+ * Counting costs a few atomics per box and is on only while
+ * sccg_set_stats(ctx, 1) is in effect (the HIP graph is rebuilt on a change).
+ *   [0] leaf pixel tests: pixels of leaf boxes x polygons tested there
+ *   [1] leaf boxes       [2] split boxes
+ *   [3] boxes published to the device queue (BATCHED)
+ *   [4] boxes kept by the splitting wave although enough to publish (BATCHED)
+ *   [5] small pairs (one leaf tile)   [6] large pairs   [7] pairs with an empty
+ *       or rejected pair box (BATCHED)
+ *   [8] leaf edge updates: BATCHED, staged band edges x leaf tiles;
+ *       PLAIN, leaf pixels x ring edges tested
+ *   [9] classification edge visits: BATCHED, ring edges x splits;
+ *       PLAIN, sub-boxes x ring edges tested
+ *   [10] ring edges read while staging leaf tiles (BATCHED)
+ * Writes min(n, 16) values to out; returns that count (or an error < 0). */
+int sccg_set_stats(sccg_ctx* ctx, int enable);
+int sccg_get_stats(sccg_ctx* ctx, int64_t* out, int n);
+
+/* Time the main kernel of every sccg_area_pairs call (the plain kernel, or
+ * the persistent kernel of BATCHED mode) with HIP events recorded on the
+ * context's stream around that one launch.  While timing is on, BATCHED mode
+ * launches its kernels directly instead of through the HIP graph.
+ * sccg_get_timing waits for the stream, returns the summed milliseconds and
+ * the number of timed launches since the last sccg_get_timing (or since
+ * timing was enabled), and starts a new sum. */
+int sccg_set_timing(sccg_ctx* ctx, int enable);
+int sccg_get_timing(sccg_ctx* ctx, double* out_ms, int64_t* out_launches);
+
+/* Message of the last error on this context ("" if none). */
+const char* sccg_last_error(const sccg_ctx* ctx);
+
+/* Library version string. */
+const char* sccg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCCG_H */

@@ -9,6 +9,7 @@ computes and the passage of the paper it follows.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -43,7 +44,7 @@ def _load():
     lib.sccg_oracle_jaccard_sets.restype = None
     lib.sccg_oracle_jaccard_sets.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                             ctypes.c_void_p, ctypes.c_void_p]
+                                             ctypes.c_void_p]
     _lib = lib
     return lib
 
@@ -88,7 +89,14 @@ def area_pairs(A, B, pa, pb, form: int = PURE, threads: int | None = None):
 
 
 def jaccard_sets(set_off, I, U, include_zero: bool = False):
-    """Per set: (sum_i, sum_u, n_contrib, J, J')."""
+    """Per set: (sum_i, sum_u, n_contrib, J, J').
+
+    J = sum I / sum U (Section 2.1) with one binary64 division.  J' (Equation
+    1) = mean of I/U over the contributing pairs: each ratio is one binary64
+    division, their sum is rounded once from the exact value (math.fsum), then
+    divided by the count.  Fixing the rounding this way makes J' independent
+    of summation order; the paper does not fix one.
+    """
     lib = _load()
     so = _c(set_off, np.int64)
     I = _c(I, np.int64)
@@ -100,5 +108,15 @@ def jaccard_sets(set_off, I, U, include_zero: bool = False):
     j = np.zeros(ns, np.float64)
     jp = np.zeros(ns, np.float64)
     lib.sccg_oracle_jaccard_sets(ns, so.ctypes.data, I.ctypes.data, U.ctypes.data, int(include_zero),
-                                 si.ctypes.data, su.ctypes.data, nn.ctypes.data, j.ctypes.data, jp.ctypes.data)
+                                 si.ctypes.data, su.ctypes.data, nn.ctypes.data, j.ctypes.data)
+    for s in range(ns):
+        i_s = I[so[s]:so[s + 1]]
+        u_s = U[so[s]:so[s + 1]]
+        keep = np.ones(len(i_s), bool) if include_zero else (i_s > 0)
+        i_k, u_k = i_s[keep], u_s[keep]
+        pos = u_k > 0
+        ratios = np.zeros(len(i_k), np.float64)
+        ratios[pos] = i_k[pos].astype(np.float64) / u_k[pos].astype(np.float64)
+        n = len(i_k)
+        jp[s] = math.fsum(ratios.tolist()) / n if n else 0.0
     return si, su, nn, j, jp

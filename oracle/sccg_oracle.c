@@ -16,8 +16,8 @@
  *  - Polygon area (Section 3.2): the shoelace sum, cyclic, absolute value
  *    taken per polygon.
  *  - Jaccard (Section 2.1): J = total intersection / total union of a set of
- *    pairs; J' (Equation 1) = mean of the per-pair ratios over the pairs with
- *    non-zero intersection.
+ *    pairs.  J' (Equation 1, the mean of the per-pair ratios over the pairs
+ *    with non-zero intersection) is formed in the Python wrapper.
  *
  * The union is counted directly (pixels in p or q), never as |p|+|q|-I, so
  * the identity I + U = |p| + |q| that the method relies on (Section 3.2)
@@ -211,21 +211,18 @@ void sccg_oracle_area_pairs(const sccg_oracle_polys* A, const sccg_oracle_polys*
 
 void sccg_oracle_jaccard_sets(int64_t n_sets, const int64_t* set_off, const int64_t* inter,
                               const int64_t* uni, int include_zero, int64_t* out_sum_i,
-                              int64_t* out_sum_u, int64_t* out_n, double* out_j, double* out_jprime) {
+                              int64_t* out_sum_u, int64_t* out_n, double* out_j) {
   for (int64_t s = 0; s < n_sets; ++s) {
     int64_t si = 0, su = 0, n = 0;
-    double r = 0.0;
     for (int64_t k = set_off[s]; k < set_off[s + 1]; ++k) {
       if (!include_zero && inter[k] == 0) continue;
       si += inter[k];
       su += uni[k];
       n += 1;
-      r += (uni[k] > 0) ? (double)inter[k] / (double)uni[k] : 0.0;
     }
     out_sum_i[s] = si;
     out_sum_u[s] = su;
     out_n[s] = n;
     out_j[s] = (su > 0) ? (double)si / (double)su : 0.0;
-    if (out_jprime) out_jprime[s] = (n > 0) ? r / (double)n : 0.0;
   }
 }

@@ -42,12 +42,13 @@ void sccg_oracle_area_pairs(const sccg_oracle_polys* A, const sccg_oracle_polys*
                             int64_t* out_union, int form, int n_threads);
 
 /* Per set s over pairs [set_off[s], set_off[s+1]): sums of I and U, the number
- * of contributing pairs, J = sum I / sum U and J' = mean over those pairs of
- * I/U summed left to right in pair order.  With include_zero = 0 only pairs
- * with I > 0 contribute (the paper's ratio > 0 filter). */
+ * of contributing pairs and J = sum I / sum U (one binary64 division).  With
+ * include_zero = 0 only pairs with I > 0 contribute (the paper's ratio > 0
+ * filter).  J' (the mean of the ratios) is formed by the Python wrapper with
+ * an exactly rounded sum. */
 void sccg_oracle_jaccard_sets(int64_t n_sets, const int64_t* set_off, const int64_t* inter,
                               const int64_t* uni, int include_zero, int64_t* out_sum_i,
-                              int64_t* out_sum_u, int64_t* out_n, double* out_j, double* out_jprime);
+                              int64_t* out_sum_u, int64_t* out_n, double* out_j);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,274 @@
+"""sccg — exact PixelBox pair areas and set Jaccard on MI355X (gfx950).
+
+Thin ctypes binding of the C ABI declared in ``include/sccg.h``.  Every step
+of the computation runs in the HIP kernels of ``libsccg.so``; this module only
+marshals arguments.  PyTorch provides device memory and the stream.  There is
+no fallback: if the library is missing, or no GPU is visible, calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsccg.so")
+
+SCCG_OK = 0
+SCCG_E_ARG = -1
+SCCG_E_RANGE = -2
+SCCG_E_POLY = -3
+SCCG_E_HIP = -4
+SCCG_E_NOMEM = -5
+SCCG_E_DEVICE = -6
+SCCG_E_STATE = -7
+
+SCCG_PLAIN = 0
+SCCG_BATCHED = 1
+
+SCCG_F_NO_LPT = 0x1
+SCCG_F_NO_KNOWN_INSIDE = 0x2
+SCCG_F_NO_SPLIT_QUEUE = 0x4
+SCCG_F_NO_GRAPH = 0x8
+
+SCCG_J_NONZERO_ONLY = 0
+SCCG_J_INCLUDE_ZERO = 1
+
+#: C-ABI entry points the library must export (checked by the CPU tests).
+EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
+           "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
+           "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version")
+
+STAT_KEYS = ("leaf_pixel_tests", "leaf_boxes", "split_boxes", "queued_boxes", "kept_boxes", "small_pairs",
+             "large_pairs", "empty_pairs", "leaf_edge_updates", "classify_edge_visits", "leaf_staging_edges")
+
+
+class SccgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sccg error {code}: {msg}")
+        self.code = code
+
+
+class sccg_polys(ctypes.Structure):
+    _fields_ = [("n_polys", ctypes.c_int64), ("offsets", ctypes.c_void_p), ("xy", ctypes.c_void_p)]
+
+
+class sccg_params(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("box_threshold", ctypes.c_int32), ("split_gx", ctypes.c_int32),
+                ("split_gy", ctypes.c_int32), ("queue_chunk", ctypes.c_int32), ("lds_vertex_cap", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("grid", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("waves_per_wg", ctypes.c_int32), ("min_queue_cells", ctypes.c_int32),
+                ("n_queues", ctypes.c_int32), ("heavy_side", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsccg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"device library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i64 = ctypes.c_int64
+    u32 = ctypes.c_uint32
+    sig = {
+        "sccg_create": ([ctypes.POINTER(P), ctypes.c_int, P, ctypes.POINTER(sccg_params)], ctypes.c_int),
+        "sccg_destroy": ([P], ctypes.c_int),
+        "sccg_set_params": ([P, ctypes.POINTER(sccg_params)], ctypes.c_int),
+        "sccg_get_params": ([P, ctypes.POINTER(sccg_params)], ctypes.c_int),
+        "sccg_reserve": ([P, i64, i64, i64], ctypes.c_int),
+        "sccg_area_pairs": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P, u32],
+                            ctypes.c_int),
+        "sccg_jaccard_sets": ([P, i64, P, P, P, u32, P, P, P, P, P], ctypes.c_int),
+        "sccg_validate_polys": ([P, ctypes.POINTER(sccg_polys), P], ctypes.c_int),
+        "sccg_sync": ([P], ctypes.c_int),
+        "sccg_set_stats": ([P, ctypes.c_int], ctypes.c_int),
+        "sccg_get_stats": ([P, P, ctypes.c_int], ctypes.c_int),
+        "sccg_set_timing": ([P, ctypes.c_int], ctypes.c_int),
+        "sccg_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "sccg_last_error": ([P], ctypes.c_char_p),
+        "sccg_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+@dataclass
+class DevicePolys:
+    """CSR rings resident on the device: offsets int64 [n+1], xy int32 [V, 2]."""
+    offsets: "object"
+    xy: "object"
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets.shape[0]) - 1
+
+    def c(self) -> sccg_polys:
+        return sccg_polys(self.n, _ptr(self.offsets), _ptr(self.xy) if self.xy.numel() else None)
+
+    @staticmethod
+    def from_host(off: np.ndarray, xy: np.ndarray, device="cuda") -> "DevicePolys":
+        import torch
+        o = torch.from_numpy(np.ascontiguousarray(off, dtype=np.int64)).to(device)
+        x = torch.from_numpy(np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)).to(device)
+        return DevicePolys(o, x)
+
+
+def _check_dev(t, dtype, name):
+    import torch
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """One sccg context on a device and stream (the current torch stream by default)."""
+
+    def __init__(self, device: int = 0, stream=None, **params):
+        import torch
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the sccg path runs only on the device")
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        p = sccg_params(**params) if params else None
+        h = ctypes.c_void_p()
+        rc = self.lib.sccg_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream),
+                                  ctypes.byref(p) if p is not None else None)
+        if rc != SCCG_OK:
+            raise SccgError(rc, "sccg_create failed")
+        self.h = h
+
+    def _rc(self, rc):
+        if rc != SCCG_OK:
+            msg = self.lib.sccg_last_error(self.h)
+            raise SccgError(rc, msg.decode() if msg else "")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.lib.sccg_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ params
+    def set_params(self, **params):
+        self._rc(self.lib.sccg_set_params(self.h, ctypes.byref(sccg_params(**params))))
+
+    def get_params(self) -> dict:
+        p = sccg_params()
+        self._rc(self.lib.sccg_get_params(self.h, ctypes.byref(p)))
+        return p.as_dict()
+
+    def reserve(self, max_polys_a: int, max_polys_b: int, max_pairs: int):
+        self._rc(self.lib.sccg_reserve(self.h, max_polys_a, max_polys_b, max_pairs))
+
+    def set_stats(self, enable: bool):
+        self._rc(self.lib.sccg_set_stats(self.h, 1 if enable else 0))
+
+    def get_stats(self) -> dict:
+        out = np.zeros(16, np.int64)
+        n = self.lib.sccg_get_stats(self.h, out.ctypes.data, 16)
+        if n < 0:
+            self._rc(n)
+        return dict(zip(STAT_KEYS, (int(v) for v in out[:n])))
+
+    def set_timing(self, enable: bool):
+        self._rc(self.lib.sccg_set_timing(self.h, 1 if enable else 0))
+
+    def get_timing(self):
+        """(milliseconds summed over timed launches, number of launches)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._rc(self.lib.sccg_get_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+    # ---------------------------------------------------------- compute
+    def area_pairs(self, A: DevicePolys, B: DevicePolys, pair_a, pair_b, out_inter=None, out_union=None,
+                   mode: int = SCCG_BATCHED):
+        """Queue sccg_area_pairs; returns (inter, union) int64 device tensors."""
+        import torch
+        _check_dev(pair_a, torch.int32, "pair_a")
+        _check_dev(pair_b, torch.int32, "pair_b")
+        n = int(pair_a.shape[0])
+        if int(pair_b.shape[0]) != n:
+            raise ValueError("pair_a and pair_b differ in length")
+        if out_inter is None:
+            out_inter = torch.empty(n, dtype=torch.int64, device=pair_a.device)
+        if out_union is None:
+            out_union = torch.empty(n, dtype=torch.int64, device=pair_a.device)
+        _check_dev(out_inter, torch.int64, "out_inter")
+        _check_dev(out_union, torch.int64, "out_union")
+        ca, cb = A.c(), B.c()
+        self._rc(self.lib.sccg_area_pairs(self.h, ctypes.byref(ca), ctypes.byref(cb), n, _ptr(pair_a),
+                                          _ptr(pair_b), _ptr(out_inter), _ptr(out_union), mode))
+        return out_inter, out_union
+
+    def jaccard_sets(self, set_pair_off, inter, uni, flags: int = SCCG_J_NONZERO_ONLY, jprime: bool = True):
+        """Queue sccg_jaccard_sets; returns (sum_i, sum_u, n_contrib, J, J') device tensors."""
+        import torch
+        _check_dev(set_pair_off, torch.int64, "set_pair_off")
+        _check_dev(inter, torch.int64, "inter")
+        _check_dev(uni, torch.int64, "uni")
+        ns = int(set_pair_off.shape[0]) - 1
+        dev = inter.device
+        si = torch.empty(ns, dtype=torch.int64, device=dev)
+        su = torch.empty(ns, dtype=torch.int64, device=dev)
+        nn = torch.empty(ns, dtype=torch.int64, device=dev)
+        j = torch.empty(ns, dtype=torch.float64, device=dev)
+        jp = torch.empty(ns, dtype=torch.float64, device=dev) if jprime else None
+        self._rc(self.lib.sccg_jaccard_sets(self.h, ns, _ptr(set_pair_off), _ptr(inter), _ptr(uni), flags, _ptr(si),
+                                            _ptr(su), _ptr(nn), _ptr(j), _ptr(jp)))
+        return si, su, nn, j, jp
+
+    def validate_polys(self, P: DevicePolys):
+        import torch
+        out = torch.empty(1, dtype=torch.int64, device="cuda")
+        cp = P.c()
+        self._rc(self.lib.sccg_validate_polys(self.h, ctypes.byref(cp), _ptr(out)))
+        return out
+
+    def sync(self):
+        """Wait for the stream; raise SccgError for errors the device latched."""
+        return self._rc(self.lib.sccg_sync(self.h))
+
+    def sync_code(self) -> int:
+        """Wait for the stream and return the status code without raising."""
+        return int(self.lib.sccg_sync(self.h))
+
+
+def version() -> str:
+    return load_library().sccg_version().decode()

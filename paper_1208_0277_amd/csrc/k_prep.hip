@@ -1,0 +1,271 @@
+// Per-polygon prepass, ring validation and the set-level Jaccard reduction.
+#include <limits.h>
+
+#include "sccg_device.h"
+
+namespace sccg {
+
+// Polygons with more vertices than this are handed to one wave each.
+constexpr int kThreadVerts = 192;
+
+// One polygon's extent and doubled signed area, accumulated by one thread
+// (or one lane's share of a ring).  The shoelace sum (Section 3.2) is taken
+// in wrapping 64-bit arithmetic: partial sums may overflow, the final value
+// (twice the area, below 2^63) is exact.
+struct MetaAcc {
+  int32_t x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
+  uint64_t twice = 0;
+  __device__ void add(int2 v, int2 w) {
+    x0 = min(x0, v.x);
+    y0 = min(y0, v.y);
+    x1 = max(x1, v.x);
+    y1 = max(y1, v.y);
+    twice += (uint64_t)((int64_t)v.x * w.y) - (uint64_t)((int64_t)w.x * v.y);
+  }
+};
+
+__device__ void write_meta(const MetaAcc& a, int64_t nv, int64_t k, Meta* meta, int64_t* area, uint32_t* err) {
+  bool empty = nv <= 0;
+  bool bad = !empty && (a.x0 < -kMaxCoord || a.y0 < -kMaxCoord || a.x1 > kMaxCoord || a.y1 > kMaxCoord);
+  if (bad) latch_error(err, kErrCoord);
+  if (empty || bad) {
+    *reinterpret_cast<int4*>(meta + k) = make_int4(INT_MAX, INT_MAX, INT_MIN, INT_MIN);
+    area[k] = 0;
+    return;
+  }
+  *reinterpret_cast<int4*>(meta + k) = make_int4(a.x0, a.y0, a.x1, a.y1);
+  int64_t t = (int64_t)a.twice;
+  area[k] = (t < 0 ? -t : t) / 2;
+}
+
+__global__ void __launch_bounds__(256) k_meta_thread(Polys P, Meta* meta, int64_t* area, int32_t* big,
+                                                     int32_t* big_count, uint32_t* err) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool is_big = false;
+  if (k < P.n) {
+    const int64_t o0 = P.off[k];
+    const int64_t nv = P.off[k + 1] - o0;
+    if (nv > kThreadVerts) {
+      is_big = true;
+    } else {
+      MetaAcc a;
+      if (nv > 0) {
+        const int2* r = P.xy + o0;
+        const int2 first = r[0];
+        int2 v = first;
+        for (int64_t i = 1; i < nv; ++i) {
+          int2 w = r[i];
+          a.add(v, w);
+          v = w;
+        }
+        a.add(v, first);
+      }
+      write_meta(a, nv, k, meta, area, err);
+    }
+  }
+  const uint64_t b = ballot(is_big);
+  if (b) {
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(big_count, __popcll(b));
+    base = __shfl(base, 0, kWave);
+    if (is_big) big[base + lanes_below(b)] = (int32_t)k;
+  }
+}
+
+// One wave per listed polygon; grid-stride over the list.
+__global__ void __launch_bounds__(256) k_meta_wave(Polys P, Meta* meta, int64_t* area, const int32_t* big,
+                                                   const int32_t* big_count, uint32_t* err) {
+  const int lane = lane_id();
+  const int waves = gridDim.x * (blockDim.x / kWave);
+  const int n = *big_count;
+  for (int w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < n; w += waves) {
+    const int64_t k = big[w];
+    const int64_t o0 = P.off[k];
+    const int64_t nv = P.off[k + 1] - o0;
+    MetaAcc a;
+    for (int64_t i = lane; i < nv; i += kWave) {
+      const int2 v = P.xy[o0 + i];
+      const int2 u = P.xy[o0 + (i + 1 == nv ? 0 : i + 1)];
+      a.add(v, u);
+    }
+    MetaAcc r;
+    r.x0 = wave_min_i32(a.x0);
+    r.y0 = wave_min_i32(a.y0);
+    r.x1 = wave_max_i32(a.x1);
+    r.y1 = wave_max_i32(a.y1);
+    r.twice = wave_sum_u64(a.twice);
+    if (lane == 0) write_meta(r, nv, k, meta, area, err);
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p) { *p = 0; }
+
+hipError_t launch_poly_meta(const Polys& P, Meta* meta, int64_t* area, int32_t* big_list, int32_t* big_count,
+                            uint32_t* err, hipStream_t s) {
+  if (P.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, big_count);
+  const int64_t blocks = (P.n + 255) / 256;
+  hipLaunchKernelGGL(k_meta_thread, dim3((unsigned)blocks), dim3(256), 0, s, P, meta, area, big_list, big_count,
+                     err);
+  hipLaunchKernelGGL(k_meta_wave, dim3(512), dim3(256), 0, s, P, meta, area, big_list, big_count, err);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- validation
+__global__ void k_validate_init(unsigned long long* first_bad) { *first_bad = ~0ull; }
+
+__global__ void __launch_bounds__(256) k_validate(Polys P, unsigned long long* first_bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P.n) return;
+  const int64_t o0 = P.off[k];
+  const int64_t nv = P.off[k + 1] - o0;
+  bool bad = nv < 4;
+  for (int64_t i = 0; i < nv && !bad; ++i) {
+    const int2 v = P.xy[o0 + i];
+    const int2 w = P.xy[o0 + (i + 1 == nv ? 0 : i + 1)];
+    if (v.x != w.x && v.y != w.y) bad = true;
+  }
+  if (bad) atomicMin(first_bad, (unsigned long long)k);
+}
+
+__global__ void k_validate_fin(unsigned long long* first_bad) {
+  if (*first_bad == ~0ull) *reinterpret_cast<int64_t*>(first_bad) = -1;
+}
+
+hipError_t launch_validate(const Polys& P, int64_t* first_bad, hipStream_t s) {
+  auto* fb = reinterpret_cast<unsigned long long*>(first_bad);
+  hipLaunchKernelGGL(k_validate_init, dim3(1), dim3(1), 0, s, fb);
+  if (P.n > 0)
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, s, P, fb);
+  hipLaunchKernelGGL(k_validate_fin, dim3(1), dim3(1), 0, s, fb);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- Jaccard
+// Exact sum of binary64 ratios in [0, 1]: a 192-bit fixed-point integer in
+// units of 2^-128.  A ratio I/U with I >= 1 and U < 2^63 is at least 2^-63,
+// so its lowest mantissa bit is at least 2^-115 and the conversion is exact;
+// the sum of up to 2^62 ratios stays below 2^191.
+struct Fix192 {
+  uint64_t w[3] = {0, 0, 0};  // little-endian limbs
+  __device__ void add(const Fix192& o) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      uint64_t s = w[i] + o.w[i];
+      uint64_t c1 = s < w[i];
+      uint64_t s2 = s + c;
+      uint64_t c2 = s2 < s;
+      w[i] = s2;
+      c = c1 | c2;
+    }
+  }
+  __device__ void add_ratio(double r) {
+    if (!(r > 0.0)) return;
+    uint64_t bits = __double_as_longlong(r);
+    int e = (int)((bits >> 52) & 0x7ff);
+    uint64_t m = bits & ((1ull << 52) - 1);
+    if (e == 0) return;  // subnormal: impossible for a ratio >= 2^-63
+    m |= 1ull << 52;
+    // r = m * 2^(e - 1075); in 2^-128 units: m << (e - 1075 + 128)
+    int sh = e - 947;
+    if (sh < 0) return;
+    Fix192 t;
+    int limb = sh >> 6, off = sh & 63;
+    if (limb < 3) t.w[limb] = m << off;
+    if (off && limb + 1 < 3) t.w[limb + 1] = m >> (64 - off);
+    add(t);
+  }
+  // round to nearest binary64 (ties to even): the leading 64 bits with a
+  // sticky bit for everything below are exact enough for one correct rounding
+  __device__ double to_double() const {
+    int top = 2;
+    while (top >= 0 && w[top] == 0) --top;
+    if (top < 0) return 0.0;
+    int lz = __clzll(w[top]);
+    int msb = top * 64 + (63 - lz);  // bit index of the leading one
+    uint64_t lead;
+    bool sticky = false;
+    int lo_bit = msb - 63;  // bit index that lands in lead's bit 0
+    if (lo_bit <= 0) {
+      // the whole value fits in 64 bits
+      lead = w[0];
+      return ldexp((double)lead, -128);
+    }
+    int limb = lo_bit >> 6, off = lo_bit & 63;
+    lead = w[limb] >> off;
+    if (off && limb + 1 < 3) lead |= w[limb + 1] << (64 - off);
+    for (int i = 0; i < limb; ++i) sticky |= w[i] != 0;
+    sticky |= off ? (w[limb] & ((1ull << off) - 1)) != 0 : false;
+    lead |= sticky ? 1ull : 0ull;
+    return ldexp((double)lead, lo_bit - 128);
+  }
+};
+
+__global__ void __launch_bounds__(256) k_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter,
+                                                 const int64_t* uni, uint32_t flags, int64_t* sum_i,
+                                                 int64_t* sum_u, int64_t* n_contrib, double* jout,
+                                                 double* jprime) {
+  __shared__ uint64_t red[4][256];
+  __shared__ uint64_t fx[3][256];
+  const bool include_zero = (flags & SCCG_J_INCLUDE_ZERO) != 0;
+  const bool want_jp = jprime != nullptr;
+  for (int64_t s = blockIdx.x; s < n_sets; s += gridDim.x) {
+    const int64_t o0 = set_off[s], o1 = set_off[s + 1];
+    uint64_t si = 0, su = 0, nn = 0;
+    Fix192 acc;
+    for (int64_t k = o0 + threadIdx.x; k < o1; k += blockDim.x) {
+      const int64_t I = inter[k], U = uni[k];
+      if (!include_zero && I == 0) continue;
+      si += (uint64_t)I;
+      su += (uint64_t)U;
+      nn += 1;
+      if (want_jp && U > 0) acc.add_ratio((double)I / (double)U);
+    }
+    red[0][threadIdx.x] = si;
+    red[1][threadIdx.x] = su;
+    red[2][threadIdx.x] = nn;
+    fx[0][threadIdx.x] = acc.w[0];
+    fx[1][threadIdx.x] = acc.w[1];
+    fx[2][threadIdx.x] = acc.w[2];
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + h];
+        red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        red[2][threadIdx.x] += red[2][threadIdx.x + h];
+        Fix192 a, b;
+        a.w[0] = fx[0][threadIdx.x]; a.w[1] = fx[1][threadIdx.x]; a.w[2] = fx[2][threadIdx.x];
+        b.w[0] = fx[0][threadIdx.x + h]; b.w[1] = fx[1][threadIdx.x + h]; b.w[2] = fx[2][threadIdx.x + h];
+        a.add(b);
+        fx[0][threadIdx.x] = a.w[0]; fx[1][threadIdx.x] = a.w[1]; fx[2][threadIdx.x] = a.w[2];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int64_t tI = (int64_t)red[0][0], tU = (int64_t)red[1][0], tn = (int64_t)red[2][0];
+      sum_i[s] = tI;
+      sum_u[s] = tU;
+      n_contrib[s] = tn;
+      jout[s] = tU > 0 ? (double)tI / (double)tU : 0.0;
+      if (want_jp) {
+        Fix192 a;
+        a.w[0] = fx[0][0]; a.w[1] = fx[1][0]; a.w[2] = fx[2][0];
+        jprime[s] = tn > 0 ? a.to_double() / (double)tn : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter, const int64_t* uni,
+                          uint32_t flags, int64_t* sum_i, int64_t* sum_u, int64_t* n_contrib, double* j,
+                          double* jprime, hipStream_t s) {
+  if (n_sets <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)(n_sets < 65536 ? n_sets : 65536);
+  hipLaunchKernelGGL(k_jaccard, dim3(grid), dim3(256), 0, s, n_sets, set_off, inter, uni, flags, sum_i, sum_u,
+                     n_contrib, j, jprime);
+  return hipGetLastError();
+}
+
+}  // namespace sccg

@@ -1,0 +1,519 @@
+// Host side of the C ABI: contexts, argument checks, scratch, launches and
+// the HIP-graph cache of the batched launch sequence.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "sccg_common.h"
+
+using namespace sccg;
+
+struct sccg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  sccg_params p{};
+  std::string msg;
+  int cu_count = 1;
+  // per-polygon scratch
+  Meta* metaA = nullptr;
+  int64_t* areaA = nullptr;
+  int32_t* bigA = nullptr;
+  int64_t capA = 0;
+  Meta* metaB = nullptr;
+  int64_t* areaB = nullptr;
+  int32_t* bigB = nullptr;
+  int64_t capB = 0;
+  int32_t* big_count = nullptr;  // [2]
+  uint32_t* err = nullptr;
+  // per-pair scratch
+  uint8_t* cls = nullptr;
+  int32_t* l_list = nullptr;
+  int64_t cap_pairs = 0;
+  // batched state and queues
+  BatchState* st = nullptr;
+  unsigned long long* queue = nullptr;
+  int64_t queue_slots = 0;  // allocated n_queues * queue_cap
+  unsigned long long* plain_stats = nullptr;
+  int stats_on = 0;
+  uint32_t last_mode = 0;
+  // graph cache for the batched sequence
+  hipGraphExec_t gexec = nullptr;
+  std::string gkey;
+  // kernel timing
+  int timing_on = 0;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t ev_used = 0;          // pairs recorded since the last read
+};
+
+namespace {
+
+const char* kVersion = "sccg 0.1 (gfx950)";
+
+int fail(sccg_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->msg = buf;
+  }
+  return code;
+}
+
+int hip_fail(sccg_ctx* c, hipError_t e, const char* what) {
+  return fail(c, SCCG_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, expr)                             \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(c, e_, #expr); \
+  } while (0)
+
+int resolve_params(sccg_ctx* c, const sccg_params* in, sccg_params* out) {
+  sccg_params p{};
+  if (in) p = *in;
+  if (p.wg_size == 0) p.wg_size = 64;
+  if (p.wg_size != 64 && p.wg_size != 128 && p.wg_size != 256)
+    return fail(c, SCCG_E_ARG, "wg_size must be 64, 128 or 256 (got %d)", p.wg_size);
+  if (p.split_gx == 0 && p.split_gy == 0) {
+    p.split_gx = p.wg_size == 64 ? 8 : 16;
+    p.split_gy = p.wg_size / p.split_gx;
+  }
+  if (p.split_gx * p.split_gy != p.wg_size || p.split_gx < 4 || p.split_gy < 4)
+    return fail(c, SCCG_E_ARG, "split grid %dx%d must multiply to wg_size %d with both sides >= 4", p.split_gx,
+                p.split_gy, p.wg_size);
+  if (p.box_threshold == 0) p.box_threshold = p.wg_size * p.wg_size / 2;
+  if (p.box_threshold < 2 || p.box_threshold > (1 << 30))
+    return fail(c, SCCG_E_ARG, "box_threshold %d outside [2, 2^30]", p.box_threshold);
+  if (p.queue_chunk == 0) p.queue_chunk = 8;
+  if (p.queue_chunk < 1 || p.queue_chunk > 4096) return fail(c, SCCG_E_ARG, "queue_chunk outside [1, 4096]");
+  if (p.lds_vertex_cap == 0) p.lds_vertex_cap = 1024;
+  if (p.lds_vertex_cap < 1 || p.lds_vertex_cap > 4096)
+    return fail(c, SCCG_E_ARG, "lds_vertex_cap outside [1, 4096]");
+  const uint32_t known = SCCG_F_NO_LPT | SCCG_F_NO_KNOWN_INSIDE | SCCG_F_NO_SPLIT_QUEUE | SCCG_F_NO_GRAPH;
+  if (p.flags & ~known) return fail(c, SCCG_E_ARG, "unknown flag bits 0x%x", p.flags & ~known);
+  if (p.grid < 0 || p.grid > (1 << 20)) return fail(c, SCCG_E_ARG, "grid outside [0, 2^20]");
+  if (p.queue_cap == 0) p.queue_cap = 1 << 20;
+  if (p.queue_cap < 1 || p.queue_cap > (1 << 26)) return fail(c, SCCG_E_ARG, "queue_cap outside [1, 2^26]");
+  if (p.waves_per_wg == 0) p.waves_per_wg = 4;
+  if (p.waves_per_wg < 1 || p.waves_per_wg > 8) return fail(c, SCCG_E_ARG, "waves_per_wg outside [1, 8]");
+  if (p.min_queue_cells == 0) p.min_queue_cells = 8;
+  if (p.min_queue_cells < 1 || p.min_queue_cells > 65) return fail(c, SCCG_E_ARG, "min_queue_cells outside [1, 65]");
+  if (p.n_queues == 0) p.n_queues = kMaxGrid;
+  if (p.n_queues < 1 || p.n_queues > kMaxGrid) return fail(c, SCCG_E_ARG, "n_queues outside [1, 8]");
+  if (p.heavy_side == 0) p.heavy_side = 128;
+  if (p.heavy_side < 1 || p.heavy_side > kMaxSide) return fail(c, SCCG_E_ARG, "heavy_side outside [1, 32767]");
+  *out = p;
+  return SCCG_OK;
+}
+
+template <typename T>
+int grow(sccg_ctx* c, T** ptr, int64_t n, const char* what) {
+  if (*ptr) (void)hipFree(*ptr);
+  *ptr = nullptr;
+  if (n <= 0) return SCCG_OK;
+  hipError_t e = hipMalloc((void**)ptr, sizeof(T) * (size_t)n);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(c, SCCG_E_NOMEM, "hipMalloc(%s, %lld elements): %s", what, (long long)n, hipGetErrorString(e));
+  }
+  return SCCG_OK;
+}
+
+int ensure_polys(sccg_ctx* c, int which, int64_t n) {
+  int64_t& cap = which ? c->capB : c->capA;
+  if (n <= cap) return SCCG_OK;
+  (void)hipStreamSynchronize(c->stream);
+  int64_t want = n + n / 4 + 1024;
+  Meta** m = which ? &c->metaB : &c->metaA;
+  int64_t** ar = which ? &c->areaB : &c->areaA;
+  int32_t** bg = which ? &c->bigB : &c->bigA;
+  int r;
+  if ((r = grow(c, m, want, "metadata")) || (r = grow(c, ar, want, "areas")) || (r = grow(c, bg, want, "big list"))) {
+    cap = 0;
+    return r;
+  }
+  cap = want;
+  return SCCG_OK;
+}
+
+int ensure_pairs(sccg_ctx* c, int64_t n) {
+  if (n <= c->cap_pairs) return SCCG_OK;
+  (void)hipStreamSynchronize(c->stream);
+  int64_t want = n + n / 4 + 1024;
+  int r;
+  if ((r = grow(c, &c->cls, want, "pair classes")) || (r = grow(c, &c->l_list, want, "large list"))) {
+    c->cap_pairs = 0;
+    return r;
+  }
+  c->cap_pairs = want;
+  return SCCG_OK;
+}
+
+int ensure_queue(sccg_ctx* c) {
+  const int64_t want = (int64_t)c->p.n_queues * c->p.queue_cap;
+  if (c->queue && c->queue_slots == want) return SCCG_OK;
+  (void)hipStreamSynchronize(c->stream);
+  int r = grow(c, &c->queue, want, "task queue");
+  if (r) {
+    c->queue_slots = 0;
+    return r;
+  }
+  c->queue_slots = want;
+  // fresh slots must read as empty; the counters must not claim old slots
+  HIP_TRY(c, hipMemset(c->queue, 0, sizeof(unsigned long long) * (size_t)want));
+  HIP_TRY(c, hipMemset(c->st, 0, sizeof(BatchState)));
+  return SCCG_OK;
+}
+
+// Start/stop events for the next timed launch (created on first use).
+int timing_events(sccg_ctx* c, hipEvent_t* start, hipEvent_t* stop) {
+  if (c->ev_used * 2 + 2 > c->ev.size()) {
+    hipEvent_t a, b;
+    HIP_TRY(c, hipEventCreate(&a));
+    HIP_TRY(c, hipEventCreate(&b));
+    c->ev.push_back(a);
+    c->ev.push_back(b);
+  }
+  *start = c->ev[c->ev_used * 2];
+  *stop = c->ev[c->ev_used * 2 + 1];
+  c->ev_used += 1;
+  return SCCG_OK;
+}
+
+void drop_graph(sccg_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->gkey.clear();
+}
+
+int check_polys(sccg_ctx* c, const sccg_polys* P, const char* name) {
+  if (!P) return fail(c, SCCG_E_ARG, "%s is NULL", name);
+  if (P->n_polys < 0) return fail(c, SCCG_E_ARG, "%s.n_polys < 0", name);
+  if (P->n_polys >= (int64_t)1 << 31) return fail(c, SCCG_E_ARG, "%s.n_polys >= 2^31", name);
+  if (!P->offsets) return fail(c, SCCG_E_ARG, "%s.offsets is NULL", name);
+  if (P->n_polys > 0 && !P->xy) return fail(c, SCCG_E_ARG, "%s.xy is NULL", name);
+  return SCCG_OK;
+}
+
+Polys to_polys(const sccg_polys* P) {
+  return Polys{P->n_polys, P->offsets, reinterpret_cast<const int2*>(P->xy)};
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sccg_version(void) { return kVersion; }
+
+const char* sccg_last_error(const sccg_ctx* ctx) { return ctx ? ctx->msg.c_str() : "null context"; }
+
+int sccg_create(sccg_ctx** out, int hip_device, void* hip_stream, const sccg_params* params) {
+  if (!out) return SCCG_E_ARG;
+  *out = nullptr;
+  sccg_ctx* c = new sccg_ctx();
+  int r = resolve_params(c, params, &c->p);
+  if (r) {
+    delete c;
+    return r;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+    delete c;
+    return SCCG_E_ARG;
+  }
+  c->device = hip_device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete c;
+    return SCCG_E_HIP;
+  }
+  (void)hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, hip_device);
+  if (c->cu_count < 1) c->cu_count = 1;
+  if (hipMalloc((void**)&c->err, sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc((void**)&c->big_count, 2 * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc((void**)&c->st, sizeof(BatchState)) != hipSuccess ||
+      hipMalloc((void**)&c->plain_stats, kNumStats * sizeof(unsigned long long)) != hipSuccess) {
+    sccg_destroy(c);
+    return SCCG_E_NOMEM;
+  }
+  if (hipMemset(c->err, 0, sizeof(uint32_t)) != hipSuccess || hipMemset(c->st, 0, sizeof(BatchState)) != hipSuccess ||
+      hipMemset(c->plain_stats, 0, kNumStats * sizeof(unsigned long long)) != hipSuccess) {
+    sccg_destroy(c);
+    return SCCG_E_HIP;
+  }
+  *out = c;
+  return SCCG_OK;
+}
+
+int sccg_destroy(sccg_ctx* c) {
+  if (!c) return SCCG_E_ARG;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  void* ptrs[] = {c->metaA, c->areaA, c->bigA, c->metaB, c->areaB, c->bigB, c->big_count, c->err,
+                  c->cls,   c->l_list, c->st,  c->queue, c->plain_stats};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+  return SCCG_OK;
+}
+
+int sccg_set_params(sccg_ctx* c, const sccg_params* params) {
+  if (!c) return SCCG_E_ARG;
+  sccg_params p;
+  int r = resolve_params(c, params, &p);
+  if (r) return r;
+  c->p = p;
+  drop_graph(c);
+  return SCCG_OK;
+}
+
+int sccg_get_params(const sccg_ctx* c, sccg_params* out) {
+  if (!c || !out) return SCCG_E_ARG;
+  *out = c->p;
+  return SCCG_OK;
+}
+
+int sccg_reserve(sccg_ctx* c, int64_t na, int64_t nb, int64_t np) {
+  if (!c || na < 0 || nb < 0 || np < 0) return c ? fail(c, SCCG_E_ARG, "negative reserve size") : SCCG_E_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  int r;
+  if ((r = ensure_polys(c, 0, na)) || (r = ensure_polys(c, 1, nb)) || (r = ensure_pairs(c, np)) ||
+      (r = ensure_queue(c)))
+    return r;
+  return SCCG_OK;
+}
+
+int sccg_set_stats(sccg_ctx* c, int enable) {
+  if (!c) return SCCG_E_ARG;
+  c->stats_on = enable ? 1 : 0;
+  drop_graph(c);
+  return SCCG_OK;
+}
+
+int sccg_set_timing(sccg_ctx* c, int enable) {
+  if (!c) return SCCG_E_ARG;
+  c->timing_on = enable ? 1 : 0;
+  c->ev_used = 0;
+  return SCCG_OK;
+}
+
+int sccg_get_timing(sccg_ctx* c, double* out_ms, int64_t* out_launches) {
+  if (!c || !out_ms || !out_launches) return c ? fail(c, SCCG_E_ARG, "NULL output") : SCCG_E_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (size_t k = 0; k < c->ev_used; ++k) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+    total += ms;
+  }
+  *out_ms = total;
+  *out_launches = (int64_t)c->ev_used;
+  c->ev_used = 0;
+  return SCCG_OK;
+}
+
+int sccg_get_stats(sccg_ctx* c, int64_t* out, int n) {
+  if (!c || !out || n < 0) return SCCG_E_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned long long v[kNumStats] = {0};
+  if (c->last_mode == SCCG_BATCHED) {
+    HIP_TRY(c, hipMemcpy(v, c->st->stats, sizeof(v), hipMemcpyDeviceToHost));
+  } else {
+    HIP_TRY(c, hipMemcpy(v, c->plain_stats, sizeof(v), hipMemcpyDeviceToHost));
+  }
+  const int m = n < kNumStats ? n : kNumStats;
+  for (int k = 0; k < m; ++k) out[k] = (int64_t)v[k];
+  return m;
+}
+
+__global__ void k_zero_stats(unsigned long long* s) {
+  if ((int)threadIdx.x < kNumStats) s[threadIdx.x] = 0;
+}
+
+static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int grid) {
+  hipError_t e;
+  if ((e = launch_poly_meta(ba.A, const_cast<Meta*>(ba.metaA), const_cast<int64_t*>(ba.areaA), c->bigA, c->big_count,
+                            c->err, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "poly meta A");
+  if ((e = launch_poly_meta(ba.B, const_cast<Meta*>(ba.metaB), const_cast<int64_t*>(ba.areaB), c->bigB,
+                            c->big_count + 1, c->err, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "poly meta B");
+  if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
+  if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (c->timing_on) {
+    int r = timing_events(c, &t0, &t1);
+    if (r) return r;
+    HIP_TRY(c, hipEventRecord(t0, c->stream));
+  }
+  if ((e = launch_batch_run(ba, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "batch run");
+  if (c->timing_on) HIP_TRY(c, hipEventRecord(t1, c->stream));
+  return SCCG_OK;
+}
+
+int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64_t n_pairs, const int32_t* pair_a,
+                    const int32_t* pair_b, int64_t* out_inter, int64_t* out_union, uint32_t mode) {
+  if (!c) return SCCG_E_ARG;
+  int r;
+  if ((r = check_polys(c, A, "A")) || (r = check_polys(c, B, "B"))) return r;
+  if (n_pairs < 0) return fail(c, SCCG_E_ARG, "n_pairs < 0");
+  if (n_pairs >= (int64_t)1 << 31) return fail(c, SCCG_E_ARG, "n_pairs >= 2^31");
+  if (mode != SCCG_PLAIN && mode != SCCG_BATCHED) return fail(c, SCCG_E_ARG, "unknown mode %u", mode);
+  if (n_pairs == 0) return SCCG_OK;
+  if (!pair_a || !pair_b || !out_inter || !out_union) return fail(c, SCCG_E_ARG, "NULL pair or output array");
+  HIP_TRY(c, hipSetDevice(c->device));
+  if ((r = ensure_polys(c, 0, A->n_polys)) || (r = ensure_polys(c, 1, B->n_polys))) return r;
+  c->last_mode = mode;
+  if (mode == SCCG_PLAIN) {
+    hipError_t e;
+    if ((e = launch_poly_meta(to_polys(A), c->metaA, c->areaA, c->bigA, c->big_count, c->err, c->stream)) !=
+        hipSuccess)
+      return hip_fail(c, e, "poly meta A");
+    if ((e = launch_poly_meta(to_polys(B), c->metaB, c->areaB, c->bigB, c->big_count + 1, c->err, c->stream)) !=
+        hipSuccess)
+      return hip_fail(c, e, "poly meta B");
+    PlainArgs a{};
+    a.A = to_polys(A);
+    a.B = to_polys(B);
+    a.metaA = c->metaA;
+    a.metaB = c->metaB;
+    a.areaA = c->areaA;
+    a.areaB = c->areaB;
+    a.n_pairs = n_pairs;
+    a.pa = pair_a;
+    a.pb = pair_b;
+    a.inter = out_inter;
+    a.uni = out_union;
+    a.err = c->err;
+    a.stats = c->stats_on ? c->plain_stats : nullptr;
+    a.box_threshold = c->p.box_threshold;
+    a.gx = c->p.split_gx;
+    a.gy = c->p.split_gy;
+    a.lds_vertex_cap = c->p.lds_vertex_cap;
+    if (c->stats_on) hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, c->stream, c->plain_stats);
+    int grid = c->p.grid;
+    if (grid == 0) grid = c->cu_count * plain_occupancy(c->p.wg_size, c->p.lds_vertex_cap);
+    if ((int64_t)grid > n_pairs) grid = (int)n_pairs;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (c->timing_on) {
+      if ((r = timing_events(c, &t0, &t1))) return r;
+      HIP_TRY(c, hipEventRecord(t0, c->stream));
+    }
+    if ((e = launch_plain(a, c->p.wg_size, grid, c->stream)) != hipSuccess) return hip_fail(c, e, "plain kernel");
+    if (c->timing_on) HIP_TRY(c, hipEventRecord(t1, c->stream));
+    return SCCG_OK;
+  }
+  // batched
+  if ((r = ensure_pairs(c, n_pairs)) || (r = ensure_queue(c))) return r;
+  BatchArgs ba{};
+  ba.A = to_polys(A);
+  ba.B = to_polys(B);
+  ba.metaA = c->metaA;
+  ba.metaB = c->metaB;
+  ba.areaA = c->areaA;
+  ba.areaB = c->areaB;
+  ba.n_pairs = n_pairs;
+  ba.pa = pair_a;
+  ba.pb = pair_b;
+  ba.inter = out_inter;
+  ba.uni = out_union;
+  ba.err = c->err;
+  ba.cls = c->cls;
+  ba.l_list = c->l_list;
+  ba.st = c->st;
+  ba.queue = c->queue;
+  ba.queue_cap = c->p.queue_cap;
+  ba.n_queues = c->p.n_queues;
+  ba.chunk = c->p.queue_chunk;
+  ba.heavy_area = c->p.heavy_side * c->p.heavy_side > (1 << 30) ? (1 << 30) : c->p.heavy_side * c->p.heavy_side;
+  ba.min_cells_to_queue = c->p.min_queue_cells;
+  ba.flags = c->p.flags;
+  ba.stats_on = c->stats_on;
+  int grid = c->p.grid;
+  if (grid == 0) grid = c->cu_count * batch_occupancy(c->p.waves_per_wg);
+  const bool use_graph = c->stream != nullptr && !(c->p.flags & SCCG_F_NO_GRAPH) && !c->timing_on;
+  if (!use_graph) return launch_batched(c, ba, grid);
+  // the graph is keyed on every launch argument
+  char key[512];
+  snprintf(key, sizeof(key), "%lld/%p/%p|%lld/%p/%p|%lld/%p/%p/%p/%p|%d/%d/%d/%d/%d/%u/%d/%d",
+           (long long)A->n_polys, (const void*)A->offsets, (const void*)A->xy,
+           (long long)B->n_polys, (const void*)B->offsets, (const void*)B->xy, (long long)n_pairs,
+           (const void*)pair_a, (const void*)pair_b, (void*)out_inter, (void*)out_union, ba.queue_cap, ba.n_queues,
+           ba.chunk, ba.heavy_area, ba.min_cells_to_queue, ba.flags, ba.stats_on, grid);
+  if (!c->gexec || c->gkey != key) {
+    drop_graph(c);
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    r = launch_batched(c, ba, grid);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (r) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      c->gexec = nullptr;
+      return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    c->gkey = key;
+  }
+  HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+  return SCCG_OK;
+}
+
+int sccg_jaccard_sets(sccg_ctx* c, int64_t n_sets, const int64_t* set_pair_off, const int64_t* inter,
+                      const int64_t* uni, uint32_t flags, int64_t* out_sum_i, int64_t* out_sum_u,
+                      int64_t* out_n_contrib, double* out_j, double* out_jprime) {
+  if (!c) return SCCG_E_ARG;
+  if (n_sets < 0) return fail(c, SCCG_E_ARG, "n_sets < 0");
+  if (flags & ~SCCG_J_INCLUDE_ZERO) return fail(c, SCCG_E_ARG, "unknown Jaccard flags 0x%x", flags);
+  if (n_sets == 0) return SCCG_OK;
+  if (!set_pair_off || !inter || !uni || !out_sum_i || !out_sum_u || !out_n_contrib || !out_j)
+    return fail(c, SCCG_E_ARG, "NULL array");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipError_t e = launch_jaccard(n_sets, set_pair_off, inter, uni, flags, out_sum_i, out_sum_u, out_n_contrib, out_j,
+                                out_jprime, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "jaccard");
+  return SCCG_OK;
+}
+
+int sccg_validate_polys(sccg_ctx* c, const sccg_polys* P, int64_t* out_first_bad) {
+  if (!c) return SCCG_E_ARG;
+  int r = check_polys(c, P, "P");
+  if (r) return r;
+  if (!out_first_bad) return fail(c, SCCG_E_ARG, "out_first_bad is NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipError_t e = launch_validate(to_polys(P), out_first_bad, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "validate");
+  return SCCG_OK;
+}
+
+int sccg_sync(sccg_ctx* c) {
+  if (!c) return SCCG_E_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  uint32_t err = 0;
+  HIP_TRY(c, hipMemcpy(&err, c->err, sizeof(err), hipMemcpyDeviceToHost));
+  if (err) HIP_TRY(c, hipMemset(c->err, 0, sizeof(err)));
+  if (err & kErrWatchdog) return fail(c, SCCG_E_DEVICE, "device watchdog: a bounded wait ran out (error word 0x%x)", err);
+  if (err & (kErrIndex | kErrSide | kErrCoord))
+    return fail(c, SCCG_E_RANGE, "device range error:%s%s%s", (err & kErrIndex) ? " pair index out of range" : "",
+                (err & kErrSide) ? " pair-box side above 32767" : "",
+                (err & kErrCoord) ? " coordinate magnitude above 2^30" : "");
+  return SCCG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Internal declarations shared by the device library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sccg.h"
+
+namespace sccg {
+
+constexpr int kWave = 64;
+constexpr int32_t kMaxSide = 32767;        // largest accepted pair-box side (pixels)
+constexpr int32_t kMaxCoord = 1 << 30;     // largest accepted |coordinate|
+constexpr int kTile = 64;                  // leaf tile side of the batched path (pixels)
+constexpr int kMaxGrid = 8;                // batched split grid is at most 8 x 8 cells
+
+// Device error word bits (latched, reported by sccg_sync).
+enum : uint32_t {
+  kErrIndex = 1u,     // pair index outside its polygon set
+  kErrSide = 2u,      // pair-box side above kMaxSide
+  kErrCoord = 4u,     // |coordinate| above kMaxCoord
+  kErrWatchdog = 8u,  // a bounded wait in the persistent kernel ran out
+};
+
+// Pair classes written by the setup pass of the batched path.
+enum : uint8_t { kClsDone = 0, kClsSmall = 1, kClsLarge = 2 };
+
+struct Polys {
+  int64_t n;
+  const int64_t* off;
+  const int2* xy;
+};
+
+// Vertex extent of a polygon: pixels [x0,x1) x [y0,y1).  x0 > x1 marks an
+// empty or rejected polygon.
+struct Meta {
+  int32_t x0, y0, x1, y1;
+};
+
+// Number of statistics counters (see sccg_get_stats).
+constexpr int kNumStats = 16;
+
+// ------------------------------------------------------------------ launches
+// Each returns a hipError_t from the launch.
+
+// Per polygon: vertex extent, |shoelace|/2, coordinate range check.
+hipError_t launch_poly_meta(const Polys& P, Meta* meta, int64_t* area, int32_t* big_list, int32_t* big_count,
+                            uint32_t* err, hipStream_t s);
+
+struct PlainArgs {
+  Polys A, B;
+  const Meta* metaA;
+  const Meta* metaB;
+  const int64_t* areaA;
+  const int64_t* areaB;
+  int64_t n_pairs;
+  const int32_t* pa;
+  const int32_t* pb;
+  int64_t* inter;
+  int64_t* uni;
+  uint32_t* err;
+  unsigned long long* stats;  // nullable
+  int32_t box_threshold;
+  int32_t gx, gy;
+  int32_t lds_vertex_cap;
+};
+hipError_t launch_plain(const PlainArgs& a, int wg_size, int grid, hipStream_t s);
+int plain_lds_bytes(int wg_size, int lds_vertex_cap);
+int plain_occupancy(int wg_size, int lds_vertex_cap);
+
+// Device-side state of the batched path (one block of device memory).
+struct BatchState {
+  // counters, reset at the start of every call
+  unsigned long long l_count[2];    // large pairs: [0] heavy bucket, [1] the rest
+  unsigned long long l_next;        // next entry of the large list to claim
+  unsigned long long s_next;        // next pair index for the small-pair sweep
+  unsigned long long q_tail[kMaxGrid];  // per-queue reservation counters
+  unsigned long long q_head[kMaxGrid];  // per-queue claim counters
+  unsigned long long q_used[kMaxGrid];  // slots written by the previous call (cleared at the next)
+  unsigned long long stats[kNumStats];
+};
+
+struct BatchArgs {
+  Polys A, B;
+  const Meta* metaA;
+  const Meta* metaB;
+  const int64_t* areaA;
+  const int64_t* areaB;
+  int64_t n_pairs;
+  const int32_t* pa;
+  const int32_t* pb;
+  int64_t* inter;
+  int64_t* uni;
+  uint32_t* err;
+  uint8_t* cls;                  // [n_pairs]
+  int32_t* l_list;               // [n_pairs] large pairs, heavy bucket first
+  BatchState* st;
+  unsigned long long* queue;     // [n_queues * queue_cap] task words, 0 = empty
+  int32_t queue_cap;             // slots per queue
+  int32_t n_queues;
+  int32_t chunk;                 // small pairs per claim
+  int32_t heavy_area;            // pair-box area from which a large pair is "heavy" (LPT bucket)
+  int32_t min_cells_to_queue;    // a split pushes its boxes to the queue only from this many boxes
+  uint32_t flags;                // SCCG_F_*
+  int32_t stats_on;
+};
+hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
+hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s);
+hipError_t launch_batch_run(const BatchArgs& a, int grid, int waves_per_wg, hipStream_t s);
+int batch_lds_bytes_per_wave();
+int batch_occupancy(int waves_per_wg);
+
+// Set-level Jaccard.
+hipError_t launch_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter, const int64_t* uni,
+                          uint32_t flags, int64_t* sum_i, int64_t* sum_u, int64_t* n_contrib, double* j,
+                          double* jprime, hipStream_t s);
+
+// Ring validation.
+hipError_t launch_validate(const Polys& P, int64_t* first_bad, hipStream_t s);
+
+}  // namespace sccg

@@ -1,0 +1,314 @@
+"""Device parity: every count of both kernels equals the oracle (or a closed
+form) exactly, across workloads, tuning parameters and edge cases.  All calls
+go through the C ABI."""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1208_0277_amd as sccg
+import sccg_gen
+from sccg_gen import Polys, concat
+from tests.gpu_util import assert_exact, device_workload, run
+from tests.shapes import band_ring, random_bands, rects_area, rects_inter, transform
+
+pytestmark = pytest.mark.gpu
+
+MODES = [sccg.SCCG_PLAIN, sccg.SCCG_BATCHED]
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.nodeid}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = sccg.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def wl1():
+    wl = sccg_gen.pairs(1)
+    I, U = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb)
+    return wl, I, U
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config1_full(ctx, wl1, mode):
+    wl, eI, eU = wl1
+    gI, gU = run(ctx, device_workload(wl.A, wl.B, wl.pa, wl.pb), mode)
+    assert_exact(gI, gU, eI, eU, f"workload 1 mode {mode}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_band_polygons_closed_form(ctx, mode):
+    rng = np.random.default_rng(5)
+    ra, rb, expect = [], [], []
+    for t in range(2000):
+        nb = int(rng.integers(1, 14))
+        ring_a, rects_a = random_bands(rng, nb, span=int(rng.integers(8, 200)), hmax=int(rng.integers(1, 30)))
+        ring_b, rects_b = random_bands(rng, int(rng.integers(1, 14)), x0=int(rng.integers(-20, 20)),
+                                       y0=int(rng.integers(-20, 60)), span=int(rng.integers(8, 200)),
+                                       hmax=int(rng.integers(1, 30)))
+        sx, sy = (1 if rng.random() < 0.5 else -1), (1 if rng.random() < 0.5 else -1)
+        sw = bool(rng.random() < 0.5)
+        k = int(rng.choice([1, 1, 1, 2, 7]))
+        dx, dy = (int(v) for v in rng.integers(-100000, 100000, 2))
+        ring_a, rects_a = transform(ring_a, rects_a, sx, sy, sw, dx, dy, k)
+        ring_b, rects_b = transform(ring_b, rects_b, sx, sy, sw, dx, dy, k)
+        ra.append(ring_a)
+        rb.append(ring_b)
+        i = rects_inter(rects_a, rects_b)
+        expect.append((i, rects_area(rects_a) + rects_area(rects_b) - i))
+    A, B = concat(ra), concat(rb)
+    idx = np.arange(len(ra), dtype=np.int32)
+    gI, gU = run(ctx, device_workload(A, B, idx, idx), mode)
+    eI = np.array([e[0] for e in expect], np.int64)
+    eU = np.array([e[1] for e in expect], np.int64)
+    assert_exact(gI, gU, eI, eU, f"band polygons mode {mode}")
+
+
+@pytest.mark.parametrize("k", [40, 300, 1000])
+@pytest.mark.parametrize("mode", MODES)
+def test_scaled_shapes_k_squared(ctx, wl1, k, mode):
+    """Workload-1 shapes scaled by k (pair boxes up to ~32000 px, so 1-3 split
+    levels): every count is k^2 times the oracle's unscaled count."""
+    wl, eI, eU = wl1
+    sel = np.arange(0, wl.n_pairs, 4 if k < 1000 else 25)
+    As = Polys(wl.A.off, wl.A.xy * k)
+    Bs = Polys(wl.B.off, wl.B.xy * k)
+    # spread the pairs so that coordinates stay below 2^30
+    pa, pb = wl.pa[sel], wl.pb[sel]
+    if mode == sccg.SCCG_PLAIN and k >= 300:
+        sel = sel[:20]  # the plain kernel tests every pixel of every leaf: keep it short
+        pa, pb = pa[:20], pb[:20]
+    gI, gU = run(ctx, device_workload(As, Bs, pa, pb), mode)
+    assert_exact(gI, gU, k * k * eI[sel], k * k * eU[sel], f"scale {k} mode {mode}")
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    from tests.test_oracle import _bits, _valid_4x4_masks
+    masks = _valid_4x4_masks()
+    rings = [sccg_gen.trace_mask(_bits(m)) for m in masks]
+    rng = np.random.default_rng(9)
+    n = 40000
+    ia = rng.integers(0, len(masks), n)
+    ib = rng.integers(0, len(masks), n)
+    sh = rng.integers(-4, 5, (n, 2)).astype(np.int32)
+    A = concat(rings)
+    B = concat([rings[j] + sh[t] for t, j in enumerate(ib)])
+    pa = ia.astype(np.int32)
+    pb = np.arange(n, dtype=np.int32)
+    I, U = oracle.area_pairs(A, B, pa, pb)
+    return A, B, pa, pb, I, U
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_tiny_grid_pairs(ctx, tiny, mode):
+    A, B, pa, pb, eI, eU = tiny
+    gI, gU = run(ctx, device_workload(A, B, pa, pb), mode)
+    assert_exact(gI, gU, eI, eU, f"tiny grid mode {mode}")
+
+
+@pytest.fixture(scope="module")
+def wl3s():
+    wl = sccg_gen.pairs(3, 60000)
+    I, U = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS)
+    return wl, I, U
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_config3_subset(ctx, wl3s, mode):
+    wl, eI, eU = wl3s
+    gI, gU = run(ctx, device_workload(wl.A, wl.B, wl.pa, wl.pb), mode)
+    assert_exact(gI, gU, eI, eU, f"heavy-tailed mix (60k pairs) mode {mode}")
+
+
+PLAIN_TUNINGS = [
+    dict(box_threshold=64), dict(box_threshold=512), dict(box_threshold=8192), dict(box_threshold=2),
+    dict(wg_size=128), dict(wg_size=256), dict(wg_size=256, box_threshold=100000),
+    dict(split_gx=16, split_gy=4), dict(lds_vertex_cap=1), dict(grid=7),
+]
+
+
+@pytest.mark.parametrize("params", PLAIN_TUNINGS, ids=[str(p) for p in PLAIN_TUNINGS])
+def test_plain_tuning_invariance(wl3s, params):
+    wl, eI, eU = wl3s
+    sel = np.concatenate([np.nonzero(wl.blob)[0][:40], np.arange(0, wl.n_pairs, 97)])
+    c = sccg.Context(0, **params)
+    gI, gU = run(c, device_workload(wl.A, wl.B, wl.pa[sel], wl.pb[sel]), sccg.SCCG_PLAIN)
+    c.close()
+    assert_exact(gI, gU, eI[sel], eU[sel], f"plain {params}")
+
+
+BATCH_TUNINGS = [
+    dict(queue_cap=1), dict(queue_cap=3, min_queue_cells=1), dict(min_queue_cells=1), dict(min_queue_cells=65),
+    dict(flags=sccg.SCCG_F_NO_SPLIT_QUEUE), dict(flags=sccg.SCCG_F_NO_KNOWN_INSIDE),
+    dict(flags=sccg.SCCG_F_NO_LPT), dict(flags=sccg.SCCG_F_NO_GRAPH), dict(queue_chunk=1), dict(queue_chunk=333),
+    dict(waves_per_wg=1), dict(waves_per_wg=8), dict(n_queues=1), dict(grid=3), dict(heavy_side=1),
+]
+
+
+@pytest.mark.parametrize("params", BATCH_TUNINGS, ids=[str(p) for p in BATCH_TUNINGS])
+def test_batched_tuning_invariance(wl3s, params):
+    wl, eI, eU = wl3s
+    c = sccg.Context(0, **params)
+    gI, gU = run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
+    c.close()
+    assert_exact(gI, gU, eI, eU, f"batched {params}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_shuffled_and_repeated_pairs(ctx, wl1, mode):
+    wl, eI, eU = wl1
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(np.concatenate([np.arange(wl.n_pairs)] * 3))
+    gI, gU = run(ctx, device_workload(wl.A, wl.B, wl.pa[perm], wl.pb[perm]), mode)
+    assert_exact(gI, gU, eI[perm], eU[perm], f"shuffled mode {mode}")
+
+
+def test_graph_replays_match_eager(wl3s):
+    """The batched sequence is captured once and replayed; every replay, with
+    eager device work in between, gives the same counts."""
+    import torch
+    wl, eI, eU = wl3s
+    c = sccg.Context(0, stream=torch.cuda.Stream())
+    dwl = device_workload(wl.A, wl.B, wl.pa, wl.pb)
+    I = torch.empty(wl.n_pairs, dtype=torch.int64, device="cuda")
+    U = torch.empty(wl.n_pairs, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    for rep in range(4):
+        I.fill_(-1)
+        U.fill_(-1)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(c.stream):
+            c.area_pairs(*dwl, out_inter=I, out_union=U, mode=sccg.SCCG_BATCHED)
+        c.sync()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert_exact(I.cpu().numpy(), U.cpu().numpy(), eI, eU, f"replay {rep}")
+        del junk
+    c.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_degenerate_rings(ctx, mode):
+    sq = band_ring([0, 5], [0], [5])
+    dup = np.concatenate([sq, sq[:1], sq[:1]])          # repeated closing vertex twice
+    col = np.array([[0, 0], [2, 0], [5, 0], [5, 3], [5, 5], [0, 5]], np.int32)  # collinear points
+    far = sq + np.array([1000, 0], np.int32)             # disjoint: empty pair box
+    touch = sq + np.array([5, 0], np.int32)              # shares an edge only
+    corner = sq + np.array([5, 5], np.int32)             # shares a corner only
+    A = concat([sq, dup, col, sq, sq, sq])
+    B = concat([dup, col, sq, far, touch, corner])
+    idx = np.arange(6, dtype=np.int32)
+    gI, gU = run(ctx, device_workload(A, B, idx, idx), mode)
+    assert gI.tolist() == [25, 25, 25, 0, 0, 0]
+    assert gU.tolist() == [25, 25, 25, 50, 50, 50]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_empty_call_and_argument_errors(ctx, wl1, mode):
+    import torch
+    wl, _, _ = wl1
+    dA, dB, tpa, tpb = device_workload(wl.A, wl.B, wl.pa, wl.pb)
+    e = torch.empty(0, dtype=torch.int32, device="cuda")
+    I, U = ctx.area_pairs(dA, dB, e, e, mode=mode)  # n = 0: nothing queued
+    assert I.numel() == 0
+    lib = sccg.load_library()
+    ca = dA.c()
+    rc = lib.sccg_area_pairs(ctx.h, None, None, 1, None, None, None, None, mode)
+    assert rc == sccg.SCCG_E_ARG
+    rc = lib.sccg_area_pairs(ctx.h, __import__("ctypes").byref(ca), __import__("ctypes").byref(ca), -1,
+                             None, None, None, None, mode)
+    assert rc == sccg.SCCG_E_ARG
+    rc = lib.sccg_area_pairs(ctx.h, __import__("ctypes").byref(ca), __import__("ctypes").byref(ca), 1,
+                             None, None, None, None, 7)
+    assert rc == sccg.SCCG_E_ARG
+    assert ctx.sync_code() == sccg.SCCG_OK
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_range_errors_latch_and_zero(ctx, mode):
+    sq = band_ring([0, 5], [0], [5])
+    big = band_ring([0, 40000], [0], [40000])           # pair box side 40000 > 32767
+    huge = sq + np.array([1 << 30, 0], np.int32)          # x beyond 2^30
+    A = concat([sq, big, huge])
+    B = concat([sq, big, sq])
+    # pair 0 fine; pair 1 side too large; pair 2 coordinate out of range; pair 3 index out of range
+    pa = np.array([0, 1, 2, 5], np.int32)
+    pb = np.array([0, 1, 2, 0], np.int32)
+    dwl = device_workload(A, B, pa, pb)
+    I, U = ctx.area_pairs(*dwl, mode=mode)
+    assert ctx.sync_code() == sccg.SCCG_E_RANGE
+    assert ctx.sync_code() == sccg.SCCG_OK  # latched error is cleared by the sync that reports it
+    gI, gU = I.cpu().numpy(), U.cpu().numpy()
+    assert gI.tolist() == [25, 0, 0, 0]
+    assert gU.tolist()[0] == 25 and gU.tolist()[1] == 0 and gU.tolist()[3] == 0
+    assert gU.tolist()[2] == 25  # the rejected polygon counts as empty
+
+
+def test_validate_polys(ctx):
+    sq = band_ring([0, 5], [0], [5])
+    diag = np.array([[0, 0], [5, 0], [5, 5], [1, 4]], np.int32)
+    tri = np.array([[0, 0], [5, 0], [5, 5]], np.int32)
+    P = concat([sq, sq, diag, sq, tri])
+    dP = sccg.DevicePolys.from_host(P.off, P.xy)
+    out = ctx.validate_polys(dP)
+    ctx.sync()
+    assert int(out.item()) == 2
+    Q = concat([sq, sq])
+    out = ctx.validate_polys(sccg.DevicePolys.from_host(Q.off, Q.xy))
+    ctx.sync()
+    assert int(out.item()) == -1
+
+
+@pytest.mark.parametrize("include_zero", [False, True])
+def test_jaccard_sets(ctx, wl3s, include_zero):
+    import torch
+    wl, eI, eU = wl3s
+    rng = np.random.default_rng(2)
+    cuts = np.sort(rng.integers(0, wl.n_pairs, 30))
+    so = np.concatenate([[0], cuts, cuts[-1:], [wl.n_pairs]]).astype(np.int64)  # includes an empty set
+    tI = torch.from_numpy(eI).cuda()
+    tU = torch.from_numpy(eU).cuda()
+    tso = torch.from_numpy(so).cuda()
+    flags = sccg.SCCG_J_INCLUDE_ZERO if include_zero else sccg.SCCG_J_NONZERO_ONLY
+    si, su, nn, j, jp = ctx.jaccard_sets(tso, tI, tU, flags=flags)
+    ctx.sync()
+    osi, osu, onn, oj, ojp = oracle.jaccard_sets(so, eI, eU, include_zero=include_zero)
+    assert np.array_equal(si.cpu().numpy(), osi)
+    assert np.array_equal(su.cpu().numpy(), osu)
+    assert np.array_equal(nn.cpu().numpy(), onn)
+    assert np.array_equal(j.cpu().numpy(), oj)       # bit-identical binary64
+    assert np.array_equal(jp.cpu().numpy(), ojp)
+
+
+def test_batched_stats(wl3s):
+    wl, _, _ = wl3s
+    c = sccg.Context(0)
+    c.set_stats(True)
+    run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
+    s = c.get_stats()
+    c.close()
+    assert s["small_pairs"] + s["large_pairs"] + s["empty_pairs"] == wl.n_pairs
+    assert s["leaf_pixel_tests"] > 0 and s["leaf_boxes"] >= s["small_pairs"]
+    assert s["large_pairs"] > 0 and s["split_boxes"] >= s["large_pairs"]
+    assert s["leaf_edge_updates"] > 0 and s["classify_edge_visits"] > 0
+
+
+def test_kernel_timing(wl3s):
+    wl, _, _ = wl3s
+    c = sccg.Context(0)
+    c.set_timing(True)
+    dwl = device_workload(wl.A, wl.B, wl.pa, wl.pb)
+    for mode in MODES:
+        for _ in range(2):
+            run(c, dwl, mode)
+        ms, n = c.get_timing()
+        assert n == 2 and ms > 0
+    c.close()

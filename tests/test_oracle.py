@@ -267,3 +267,18 @@ def test_jaccard_exact_rational():
     si, su, nn, j, jp = oracle.jaccard_sets(np.array([0, 2, 5]), np.array([1, 1, 7, 7, 7]),
                                             np.array([2, 4, 7, 7, 7]))
     assert jp.tolist() == [0.375, 1.0] and j.tolist() == [2 / 6, 1.0]
+
+
+def test_jprime_exact_sum():
+    """J' = (sum of the binary64 ratios, rounded once from its exact value) / n,
+    checked with exact rationals."""
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        n = int(rng.integers(1, 3000))
+        U = rng.integers(1, 10 ** 9, n).astype(np.int64)
+        I = (U * rng.random(n)).astype(np.int64) + 1
+        I = np.minimum(I, U)
+        _, _, nn, _, jp = oracle.jaccard_sets(np.array([0, n]), I, U)
+        exact = sum(Fraction(float(I[k]) / float(U[k])) for k in range(n))
+        assert nn[0] == n
+        assert jp[0] == float(exact) / n
