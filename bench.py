@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the PixelBox hot path on one MI355X.
+
+Workload (default): the heavy-tailed mix -- 2,000,000 polygon pairs whose MBR
+side is lognormal (median 24 px, clipped to 8-400 px), 1% of them merged
+blobs of 10-40 ellipses -- synthetic and seeded, resident in HBM before the
+timed region.  One step = one sccg_area_pairs call in BATCHED mode over all
+pairs (per-pair MBRs and areas, pair boxes, sampling-box splits, leaf
+crossing tests, int64 intersection and union counts), launched as one
+captured HIP graph around one persistent kernel.
+
+Printed: one JSON line with pairs/s (the value), pixel-tests/s, the plain
+one-pair-per-workgroup kernel's pairs/s on the same pairs, the roofline of
+the persistent kernel, and the CPU oracle's rate on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "polygon pairs/sec and pixel-tests/sec, bit-exact; batched vs plain kernel"
+
+WORKLOADS = {
+    3: "heavy-tailed mix: 2,000,000 pairs, MBR side lognormal (median 24 px, clipped 8-400 px), "
+       "1% merged blobs of 10-40 ellipses, one persistent launch",
+    2: "uniform mix: 200,000 pairs of 10-60 px shapes (16-120 vertices) on 16384^2 tiles",
+    1: "small: 1,000 pairs of <=32 px shapes (8-40 vertices) on a 4096^2 tile",
+}
+
+# Algorithmic integer work of the persistent kernel, in int32 lane-ops per
+# counted unit (the counters come from an instrumented call):
+#   leaf_edge_updates:    one staged vertical edge applied to one 64x64 leaf
+#                         tile: per column lane a compare, a select and an
+#                         and-xor on each half of the 64-bit row mask -> 4 x 64
+#   leaf_staging_edges:   one ring edge tested for a tile's band: vertical
+#                         test, span clip (4), X test (2), keep (2), row mask (3)
+#   classify_edge_visits: one ring edge against a split grid: hover test and
+#                         cell masks (12), first-pixel parity range and masks (12)
+#   ring_scan_vertices:   one vertex of a pair's rings: extent (4 min/max),
+#                         shoelace term (2 multiplies and a subtract in 64 bits: 6)
+#   leaf_boxes:           one leaf tile: and + popcount of both halves per lane (3 x 64)
+ALGO_OPS = {
+    "leaf_edge_updates": 4 * 64,
+    "leaf_staging_edges": 12,
+    "classify_edge_visits": 24,
+    "ring_scan_vertices": 10,
+    "leaf_boxes": 3 * 64,
+}
+# int32 VALU peak of MI355X: 256 CUs x 4 SIMD16 = 64 lanes per CU per clock at 2.4 GHz
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1208_0277_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1208_0277_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload: int):
+    """HBM bytes per launch of the persistent kernel from the committed
+    counter summary, or None when it is missing or older than the kernel."""
+    path = os.path.join(ROOT, "profiles", f"traffic_k_batch_run_workload{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, I_gpu, U_gpu, seconds: float, seed: int):
+    """The oracle (row-bucketed form, all host cores) on a bounded random
+    sample of the same pairs; also checks the GPU counts of that sample."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(wl.n_pairs)
+    done, t_total, pos, exact = 0, 0.0, 0, True
+    chunk = 2000
+    while t_total < seconds and pos < wl.n_pairs:
+        sel = np.sort(order[pos:pos + chunk])
+        pos += chunk
+        t = time.perf_counter()
+        eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa[sel], wl.pb[sel], form=oracle.ROWS, threads=threads)
+        t_total += time.perf_counter() - t
+        done += len(sel)
+        if not (np.array_equal(eI, I_gpu[sel]) and np.array_equal(eU, U_gpu[sel])):
+            exact = False
+    return {"value": done / t_total, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} pairs drawn uniformly (seed {seed}) from the same workload, row-bucketed "
+                      f"oracle form, {t_total:.1f} s of CPU time"}, exact, done
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3])
+    ap.add_argument("--pairs", type=int, default=None, help="override the pair count (not the headline)")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the pair path has no cross-GPU "
+              f"exchange in this build; see DESIGN.md for how it would shard.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1208_0277_amd as sccg
+    import sccg_gen
+    from paper_1208_0277_amd import autotune
+
+    t0 = time.perf_counter()
+    n_pairs = args.pairs or sccg_gen.DEFAULT_PAIRS[args.workload]
+    wl = sccg_gen.pairs(args.workload, n_pairs)
+    log(f"generated workload {args.workload}: {wl.n_pairs} pairs, {len(wl.A.xy) + len(wl.B.xy)} vertices, "
+        f"{int(wl.blob.sum())} blobs in {time.perf_counter() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    dA = sccg.DevicePolys.from_host(wl.A.off, wl.A.xy, dev)
+    dB = sccg.DevicePolys.from_host(wl.B.off, wl.B.xy, dev)
+    pa = torch.from_numpy(wl.pa).to(dev)
+    pb = torch.from_numpy(wl.pb).to(dev)
+    I = torch.empty(wl.n_pairs, dtype=torch.int64, device=dev)
+    U = torch.empty(wl.n_pairs, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    ctx = sccg.Context(0, stream=stream)
+    ctx.reserve(dA.n, dB.n, wl.n_pairs)
+    wkey = f"w{args.workload}/{wl.n_pairs}"
+
+    with torch.cuda.stream(stream):
+        tuned = {}
+        if not args.no_autotune:
+            t = time.perf_counter()
+            tuned = autotune.tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key=wkey,
+                                  use_cache=False, log=log)
+            log(f"autotuned batched parameters {tuned} in {time.perf_counter() - t:.1f} s")
+
+        def step():
+            ctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=sccg.SCCG_BATCHED)
+
+        for _ in range(args.warmup):
+            step()
+        ctx.sync()
+        torch.cuda.synchronize()
+        # ---------------- timed region: exactly `steps` steps -----------------
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t_end = time.perf_counter()
+        # -----------------------------------------------------------------------
+        ctx.sync()
+        ms_per_step = (t_end - t_start) * 1e3 / args.steps
+        value = wl.n_pairs / (ms_per_step / 1e3)
+        gI, gU = I.cpu().numpy(), U.cpu().numpy()
+        log(f"batched: {ms_per_step:.3f} ms/step, {value / 1e6:.1f} Mpairs/s")
+
+        # kernel duration of the persistent kernel: HIP events on its stream
+        ctx.set_timing(True)
+        for _ in range(args.steps):
+            step()
+        k_ms, k_n = ctx.get_timing()
+        ctx.set_timing(False)
+        k_avg_ms = k_ms / max(k_n, 1)
+        # work counters (instrumented call, not timed)
+        ctx.set_stats(True)
+        step()
+        ctx.sync()
+        st = ctx.get_stats()
+        ctx.set_stats(False)
+        same = np.array_equal(I.cpu().numpy(), gI) and np.array_equal(U.cpu().numpy(), gU)
+
+        # plain one-pair-per-workgroup kernel on the same pairs
+        plain = {}
+        if not args.no_plain:
+            pctx = sccg.Context(0, stream=stream)
+            ptuned = {}
+            if not args.no_autotune:
+                t = time.perf_counter()
+                ptuned = autotune.tune(pctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_PLAIN, workload_key=wkey,
+                                       steps=1, use_cache=False, log=log)
+                log(f"autotuned plain parameters {ptuned} in {time.perf_counter() - t:.1f} s")
+            pctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=sccg.SCCG_PLAIN)
+            pctx.sync()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.plain_steps):
+                pctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=sccg.SCCG_PLAIN)
+            pctx.sync()
+            p_ms = (time.perf_counter() - t) * 1e3 / args.plain_steps
+            p_same = np.array_equal(I.cpu().numpy(), gI) and np.array_equal(U.cpu().numpy(), gU)
+            plain = {"plain_pairs_per_s": wl.n_pairs / (p_ms / 1e3), "plain_ms_per_step": p_ms,
+                     "plain_params": ptuned, "plain_equals_batched": bool(p_same),
+                     "batched_vs_plain": (wl.n_pairs / (ms_per_step / 1e3)) / (wl.n_pairs / (p_ms / 1e3))}
+            log(f"plain: {p_ms:.1f} ms/step; batched/plain = {plain['batched_vs_plain']:.1f}x")
+            pctx.close()
+
+    # roofline of the persistent kernel
+    algo_ops = sum(ALGO_OPS[k] * st.get(k, 0) for k in ALGO_OPS)
+    achieved = algo_ops / (k_avg_ms / 1e3)
+    algo_bytes = 8 * wl.n_pairs + 32 * wl.n_pairs + 8 * (len(wl.A.xy) + len(wl.B.xy)) + 16 * wl.n_pairs
+    traffic = traffic_from_profile(args.workload)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                "frac": achieved / VALU_PEAK_OPS, "traffic": traffic, "kernel": "k_batch_run",
+                "kernel_ms": k_avg_ms, "algorithmic_ops_per_launch": algo_ops,
+                "algorithmic_bytes_per_launch": algo_bytes,
+                "hbm_frac_algorithmic": (algo_bytes / (k_avg_ms / 1e3)) / HBM_PEAK}
+
+    cpu, exact_sample, n_sample = (None, None, 0)
+    if not args.no_cpu:
+        cpu, exact_sample, n_sample = cpu_baseline(wl, gI, gU, args.cpu_seconds, seed=1234)
+        log(f"cpu oracle: {cpu['value']:.0f} pairs/s on {n_sample} pairs, bit-exact sample: {exact_sample}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "n_pairs": wl.n_pairs, "seed": wl.seed,
+                   "mode": "batched", "params": tuned, "parallelism": "none (1 GPU)"},
+        "pixel_tests_per_s": st["leaf_pixel_tests"] / (ms_per_step / 1e3),
+        "covered_pixels_per_s": st["covered_pixels"] / (ms_per_step / 1e3),
+        **plain,
+        "bit_exact_oracle_sample": exact_sample,
+        "oracle_sample_pairs": n_sample,
+        "repeat_identical": bool(same),
+        "stats": st,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -67,7 +67,7 @@ extern "C" {
 #define SCCG_BATCHED 1u
 
 /* sccg_params.flags (ablation switches; none changes any count) */
-#define SCCG_F_NO_LPT 0x1u          /* batched: no largest-first ordering of large pairs      */
+#define SCCG_F_NO_LPT 0x1u          /* batched: no heavy-first ordering (and no box sharing)  */
 #define SCCG_F_NO_KNOWN_INSIDE 0x2u /* batched: re-test a polygon already known to contain a box */
 #define SCCG_F_NO_SPLIT_QUEUE 0x4u  /* batched: a large pair's boxes stay with the wave that split it */
 #define SCCG_F_NO_GRAPH 0x8u        /* batched: launch the kernels directly, no HIP graph      */
@@ -91,7 +91,7 @@ typedef struct {
   int32_t box_threshold;  /* PLAIN: pixelize when BOXSIZE < T (default wg_size^2/2, Section 3.4)     */
   int32_t split_gx;       /* PLAIN: sub-box grid; split_gx*split_gy == wg_size (default square-ish) */
   int32_t split_gy;
-  int32_t queue_chunk;    /* BATCHED: small pairs claimed per queue access (default 8)                */
+  int32_t queue_chunk;    /* BATCHED: small pairs claimed per counter access (default 32)             */
   int32_t lds_vertex_cap; /* PLAIN: vertices of both rings staged in LDS, 1..4096 (default 1024; above
                              it the rings are read from global memory)                               */
   uint32_t flags;         /* SCCG_F_*                                                                 */
@@ -102,8 +102,8 @@ typedef struct {
   int32_t min_queue_cells;/* BATCHED: a split publishes its boxes to the queue only when at least this
                              many continue (default 8); fewer stay with the splitting wave          */
   int32_t n_queues;       /* BATCHED: device queues, 1..8 (default 8, one per XCD)                   */
-  int32_t heavy_side;     /* BATCHED: large pairs whose box area is at least heavy_side^2 are claimed
-                             first (default 128)                                                    */
+  int32_t heavy_verts;    /* BATCHED: pairs with at least this many vertices (both rings) are claimed
+                             first and may share their boxes through the queue (default 512)        */
 } sccg_params;
 
 /* Create a context on HIP device `hip_device` using stream `hip_stream`
@@ -170,6 +170,8 @@ int sccg_sync(sccg_ctx* ctx);
  *   [9] classification edge visits: BATCHED, ring edges x splits;
  *       PLAIN, sub-boxes x ring edges tested
  *   [10] ring edges read while staging leaf tiles (BATCHED)
+ *   [11] covered pixels: sum of the non-empty pair-box areas (BATCHED)
+ *   [12] vertices reduced for MBRs and areas inside the persistent kernel (BATCHED)
  * Writes min(n, 16) values to out; returns that count (or an error < 0). */
 int sccg_set_stats(sccg_ctx* ctx, int enable);
 int sccg_get_stats(sccg_ctx* ctx, int64_t* out, int n);

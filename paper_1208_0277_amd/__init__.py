@@ -43,7 +43,8 @@ EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", 
            "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version")
 
 STAT_KEYS = ("leaf_pixel_tests", "leaf_boxes", "split_boxes", "queued_boxes", "kept_boxes", "small_pairs",
-             "large_pairs", "empty_pairs", "leaf_edge_updates", "classify_edge_visits", "leaf_staging_edges")
+             "large_pairs", "empty_pairs", "leaf_edge_updates", "classify_edge_visits", "leaf_staging_edges",
+             "covered_pixels", "ring_scan_vertices")
 
 
 class SccgError(RuntimeError):
@@ -61,7 +62,7 @@ class sccg_params(ctypes.Structure):
                 ("split_gy", ctypes.c_int32), ("queue_chunk", ctypes.c_int32), ("lds_vertex_cap", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("grid", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("waves_per_wg", ctypes.c_int32), ("min_queue_cells", ctypes.c_int32),
-                ("n_queues", ctypes.c_int32), ("heavy_side", ctypes.c_int32)]
+                ("n_queues", ctypes.c_int32), ("heavy_verts", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -24,14 +24,23 @@
 //     edges whose span meets the tile's rows and that lie right of its left
 //     side are staged (band culling); a polygon known to contain a tile is
 //     not tested again (its mask is all ones).
-//   - One persistent grid.  Waves claim, in this order: queued boxes, large
-//     pairs (largest bucket first, an LPT ordering), chunks of small pairs.
-//     A split with many hovering cells publishes them to a device queue so
-//     other waves share the work of large pairs; queue words are single
-//     64-bit atomics, so no cache flushes are needed.  Every wave that
-//     reserves queue slots fills them before anything else, so the only wait
-//     (a consumer reading a slot just reserved) always ends; it is bounded
-//     anyway and latches SCCG_E_DEVICE if the bound is hit.
+//   - The pair's MBRs and shoelace areas are reduced by the wave that takes
+//     the pair, from the same coalesced ring loads it needs anyway; only the
+//     pairs with many vertices ("heavy", claimed first: a largest-first
+//     order) get them from a prepass, so that any wave can take one of their
+//     boxes.
+//   - One persistent grid.  Waves claim, in this order: boxes from their
+//     queue, heavy pairs, chunks of the other pairs, boxes from any queue.
+//     Claims go through per-stream counters (one stream per XCD) on cache
+//     lines of their own.  A heavy pair's split publishes its continuing
+//     boxes to a device queue when there are enough of them, so that idle
+//     waves share the pair.  Queue slots are single 64-bit words written and
+//     taken with atomics, so no cache flushes are needed; a consumer that
+//     overshoots the tail marks the slot skipped and the producer keeps that
+//     box, so every box is processed exactly once and nobody waits on work
+//     that may never come.  The one remaining wait (a slot reserved but not
+//     yet written) is on a producer that writes right after reserving; it is
+//     bounded anyway and latches SCCG_E_DEVICE if the bound is hit.
 #include <limits.h>
 
 #include "sccg_device.h"
@@ -41,26 +50,27 @@ namespace sccg {
 constexpr int kLeafCap = 128;   // staged band edges per flush (per wave)
 constexpr int kLocalCap = 256;  // per-wave stack of boxes to process inline
 constexpr uint32_t kSpinLimit = 1u << 22;
-
 constexpr int kLdsPerWave = kLeafCap * 16 + kLocalCap * 8;
+constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
+
 int batch_lds_bytes_per_wave() { return kLdsPerWave; }
 
 // ---------------------------------------------------------------- task words
 // [63] valid | [56:55] level | [54] p inside | [53] q inside | [52:44] ty |
-// [43:35] tx | [30:0] pair index.  tx, ty: cell origin in 64-px units from
-// the pair-box origin; level l: cell side 64 * 8^l (0 = leaf tile).
-__device__ __forceinline__ uint64_t task_word(int64_t pair, int level, int tx, int ty, bool kp, bool kq) {
+// [43:35] tx | [30:0] heavy-list index.  tx, ty: cell origin in 64-px units
+// from the pair-box origin; level l: cell side 64 * 8^l (0 = leaf tile).
+__device__ __forceinline__ uint64_t task_word(int64_t hidx, int level, int tx, int ty, bool kp, bool kq) {
   return (1ull << 63) | ((uint64_t)level << 55) | ((uint64_t)kp << 54) | ((uint64_t)kq << 53) |
-         ((uint64_t)ty << 44) | ((uint64_t)tx << 35) | (uint64_t)pair;
+         ((uint64_t)ty << 44) | ((uint64_t)tx << 35) | (uint64_t)hidx;
 }
 struct Task {
-  int64_t pair;
+  int64_t hidx;
   int level, tx, ty;
   bool kp, kq;
 };
 __device__ __forceinline__ Task task_decode(uint64_t w) {
   Task t;
-  t.pair = (int64_t)(w & 0x7fffffffull);
+  t.hidx = (int64_t)(w & 0x7fffffffull);
   t.tx = (int)((w >> 35) & 0x1ff);
   t.ty = (int)((w >> 44) & 0x1ff);
   t.kq = (w >> 53) & 1;
@@ -86,35 +96,62 @@ __device__ __forceinline__ uint64_t row_range(int lo, int hi) {
 struct Ctx {
   const BatchArgs* a;
   int lane;
-  uint4* edges;       // per-wave staging, kLeafCap entries
-  uint64_t* local;    // per-wave inline stack, kLocalCap entries
-  int lsp;            // inline stack depth (wave-uniform)
-  int home;           // preferred queue
-  unsigned long long st_leaf_tests, st_leaf, st_split, st_queued, st_inline;
+  uint4* edges;     // per-wave staging, kLeafCap entries
+  uint64_t* local;  // per-wave inline stack, kLocalCap entries
+  int lsp;          // inline stack depth (wave-uniform)
+  int home;         // preferred queue
+  int xcd;          // first claim stream (the workgroup's XCD under round-robin dispatch)
+  unsigned long long st_leaf_tests, st_leaf, st_split, st_queued, st_kept;
   unsigned long long st_edge_updates, st_class_edges, st_stage_edges;
 };
 
+// What a wave needs to work on one pair.
 struct PairInfo {
-  int64_t op, np, oq, nq;  // ring offsets and vertex counts
-  Meta box;                // pair box
+  int64_t pair;     // index into the pair arrays
+  int64_t hidx;     // heavy-list index, or -1 when the pair is not shared
+  int64_t op, np, oq, nq;
+  Meta box;
+  int64_t area_sum;  // |p| + |q|
 };
-
-__device__ __forceinline__ PairInfo pair_info(const BatchArgs& a, int64_t i) {
-  PairInfo r;
-  const int64_t ia = a.pa[i], ib = a.pb[i];
-  const Meta mp = load_meta(a.metaA, ia), mq = load_meta(a.metaB, ib);
-  r.box = pair_box(mp, mq);
-  r.op = a.A.off[ia];
-  r.np = a.A.off[ia + 1] - r.op;
-  r.oq = a.B.off[ib];
-  r.nq = a.B.off[ib + 1] - r.oq;
-  return r;
-}
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Extent and |shoelace|/2 of one ring, reduced across the wave from
+// coalesced loads (Section 3.2's area formula, wrapping 64-bit sum).
+__device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv, int lane, Meta& m, int64_t& area) {
+  int32_t x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
+  uint64_t twice = 0;
+  for (int64_t base = 0; base < nv; base += kWave) {
+    const int64_t k = base + lane;
+    if (k < nv) {
+      const int2 v = xy[o + k];
+      const int2 w = xy[o + (k + 1 == nv ? 0 : k + 1)];
+      x0 = min(x0, v.x);
+      y0 = min(y0, v.y);
+      x1 = max(x1, v.x);
+      y1 = max(y1, v.y);
+      twice += (uint64_t)((int64_t)v.x * w.y) - (uint64_t)((int64_t)w.x * v.y);
+    }
+  }
+  m.x0 = wave_min_i32(x0);
+  m.y0 = wave_min_i32(y0);
+  m.x1 = wave_max_i32(x1);
+  m.y1 = wave_max_i32(y1);
+  const int64_t t = (int64_t)wave_sum_u64(twice);
+  area = (t < 0 ? -t : t) / 2;
+  if (nv <= 0 || m.x0 < -kMaxCoord || m.y0 < -kMaxCoord || m.x1 > kMaxCoord || m.y1 > kMaxCoord) {
+    // empty or rejected ring: covers nothing
+    m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+    area = 0;
+  }
+}
+
+__device__ __forceinline__ bool coords_bad(const Meta& m, int64_t nv) {
+  return nv > 0 && m.x0 == INT_MAX;
 }
 
 // XOR the staged edges into this lane's column mask: an edge at relative
@@ -145,7 +182,7 @@ __device__ __forceinline__ void flush_edges(const uint4* e, int cnt, int lane, u
 // Column masks of polygon ring xy[o .. o+nv) over the leaf tile
 // [tx0, tx0+64) x [ty0, ty0+th): bit r of lane x is the crossing parity of
 // pixel (tx0 + x, ty0 + r).
-__device__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o, int64_t nv, int tx0, int ty0, int th) {
+__device__ __forceinline__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o, int64_t nv, int tx0, int ty0, int th) {
   const int lane = c.lane;
   uint64_t m = 0;
   int cnt = 0;
@@ -184,7 +221,7 @@ __device__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o, int64_t nv, in
 }
 
 // Pixels of the tile [tx0, tx0+tw) x [ty0, ty0+th) inside both polygons.
-__device__ uint32_t leaf_count(Ctx& c, const PairInfo& pi, int tx0, int ty0, int tw, int th, bool kp, bool kq) {
+__device__ __forceinline__ uint32_t leaf_count(Ctx& c, const PairInfo& pi, int tx0, int ty0, int tw, int th, bool kp, bool kq) {
   const BatchArgs& a = *c.a;
   const uint64_t full = row_range(0, th);
   const uint64_t mp = kp ? full : leaf_masks(c, a.A.xy, pi.op, pi.np, tx0, ty0, th);
@@ -199,8 +236,8 @@ __device__ uint32_t leaf_count(Ctx& c, const PairInfo& pi, int tx0, int ty0, int
 
 // One pass over the ring: hover mask H and first-pixel parity mask P of the
 // gx x gy cells of side 2^ls covering [bx0,bx1) x [by0,by1).
-__device__ void classify(Ctx& c, const int2* xy, int64_t o, int64_t nv, int bx0, int by0, int bx1, int by1,
-                         int ls, int gx, int gy, uint64_t& H, uint64_t& P) {
+__device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int64_t nv, int bx0, int by0, int bx1, int by1, int ls,
+                         int gx, int gy, uint64_t& H, uint64_t& P) {
   const int S = 1 << ls;
   uint64_t h = 0, p = 0;
   for (int64_t base = 0; base < nv; base += kWave) {
@@ -248,78 +285,95 @@ __device__ __forceinline__ void add_counts(const BatchArgs& a, int64_t pair, uin
 }
 
 // ------------------------------------------------------------------- queue
-// Reserve up to k slots of queue q; returns the first slot and how many fit.
-__device__ bool queue_claim(Ctx& c, uint64_t* out) {
+// Queue q is a head counter, a tail counter and queue_cap slots.  A producer
+// reserves slots with one atomic add on the tail and fills each with a
+// compare-and-swap from 0; a consumer takes a ticket with one atomic add on
+// the head.  A ticket below the tail is a reserved slot: the consumer waits
+// for its word.  A ticket at or past the tail tries to mark its slot skipped;
+// if it wins, the producer that later reserves the slot finds it taken and
+// keeps the box; if it loses, the word is there and the consumer takes it.
+__device__ __forceinline__ bool queue_claim_one(Ctx& c, int q, uint64_t* out) {
   const BatchArgs& a = *c.a;
   uint64_t word = 0;
-  int found = 0;
   if (c.lane == 0) {
-    for (int r = 0; r < a.n_queues && !found; ++r) {
-      const int q = (c.home + r) % a.n_queues;
-      unsigned long long t =
-          __hip_atomic_load(&a.st->q_tail[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (t > (unsigned long long)a.queue_cap) t = (unsigned long long)a.queue_cap;
-      unsigned long long h =
-          __hip_atomic_load(&a.st->q_head[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      while (h < t) {
-        const unsigned long long prev = atomicCAS(&a.st->q_head[q], h, h + 1);
-        if (prev == h) {
-          unsigned long long* slot = a.queue + (size_t)q * a.queue_cap + h;
+    unsigned long long* head = &a.st->q_head[q].v;
+    unsigned long long* tail = &a.st->q_tail[q].v;
+    const unsigned long long cap = (unsigned long long)a.queue_cap;
+    const unsigned long long h0 = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long t = __hip_atomic_load(tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (h0 < cap && h0 < t) {
+      const unsigned long long h = atomicAdd(head, 1ull);
+      if (h < cap) {
+        unsigned long long* slot = a.queue + (size_t)q * a.queue_cap + h;
+        t = __hip_atomic_load(tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (h < t) {
           uint32_t spins = 0;
           while ((word = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0) {
-            if (++spins > kSpinLimit) break;
+            if (++spins > kSpinLimit) {
+              latch_error(a.err, kErrWatchdog);
+              break;
+            }
             __builtin_amdgcn_s_sleep(1);
           }
-          if (word == 0) latch_error(a.err, kErrWatchdog);
-          found = 1;
-          break;
+        } else {
+          const unsigned long long prev = atomicCAS(slot, 0ull, kSkip);
+          word = (prev == 0ull) ? 0ull : prev;
         }
-        h = prev;
+        if (word == kSkip) word = 0;
       }
     }
   }
-  found = __shfl(found, 0, kWave);
   const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)word, 0, kWave);
   const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(word >> 32), 0, kWave);
   *out = ((uint64_t)hi << 32) | lo;
-  return found && (*out != 0);
+  return *out != 0;
+}
+
+// Claim from the home queue only, or from every queue (home first).
+__device__ __forceinline__ bool queue_claim(Ctx& c, bool all, uint64_t* out) {
+  const int nq = all ? c.a->n_queues : 1;
+  for (int r = 0; r < nq; ++r)
+    if (queue_claim_one(c, (c.home + r) % c.a->n_queues, out)) return true;
+  return false;
 }
 
 // Children of one split: lane j (< n) holds word j.  Publish them to the
-// queue when there are enough, else (or for what does not fit) keep them on
-// the wave's inline stack.
-__device__ void emit_children(Ctx& c, uint64_t word, bool has, int n) {
+// queue when the pair is shared and there are enough, else (and for what a
+// full queue or a skip-marked slot refuses) keep them on the wave's stack.
+__device__ __forceinline__ void emit_children(Ctx& c, const PairInfo& pi, uint64_t word, bool has, int n) {
   const BatchArgs& a = *c.a;
   const uint64_t b = ballot(has);
   const int rank = lanes_below(b);
-  int queued = 0;
-  if (!(a.flags & SCCG_F_NO_SPLIT_QUEUE) && n >= a.min_cells_to_queue) {
+  bool keep = has;
+  if (pi.hidx >= 0 && !(a.flags & SCCG_F_NO_SPLIT_QUEUE) && n >= a.min_cells_to_queue) {
     unsigned long long t = 0;
-    if (c.lane == 0) t = atomicAdd(&a.st->q_tail[c.home], (unsigned long long)n);
+    if (c.lane == 0) t = atomicAdd(&a.st->q_tail[c.home].v, (unsigned long long)n);
     t = (unsigned long long)uniform64((int64_t)__shfl((long long)t, 0, kWave));
-    const long long room = (long long)a.queue_cap - (long long)t;
-    queued = room <= 0 ? 0 : (room < n ? (int)room : n);
-    if (has && rank < queued) {
+    if (has && t + rank < (unsigned long long)a.queue_cap) {
       unsigned long long* slot = a.queue + (size_t)c.home * a.queue_cap + t + rank;
-      __hip_atomic_store(slot, (unsigned long long)word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long prev = atomicCAS(slot, 0ull, (unsigned long long)word);
+      keep = prev != 0ull;  // skip-marked: the box stays here
     }
     if (a.stats_on) {
-      c.st_queued += queued;
-      c.st_inline += n - queued;
+      const int kept = __popcll(ballot(keep));
+      c.st_queued += n - kept;
+      c.st_kept += kept;
     }
   }
-  const int rest = n - queued;
-  if (rest > 0) {
-    if (has && rank >= queued) c.local[c.lsp + rank - queued] = word;
-    c.lsp += rest;
+  const uint64_t bk = ballot(keep);
+  const int nk = __popcll(bk);
+  if (nk > 0) {
+    if (keep) c.local[c.lsp + lanes_below(bk)] = word;
+    c.lsp += nk;
     wave_sync_lds();
   }
 }
 
-// Split box [bx0,bx1) x [by0,by1) of pair `pair` (already known to be a
-// continuing box) into cells of level `cl` (side 64*8^cl) and handle them.
-__device__ void split_box(Ctx& c, int64_t pair, const PairInfo& pi, int bx0, int by0, int bx1, int by1, int cl,
-                          bool kp, bool kq) {
+// Split box [bx0,bx1) x [by0,by1) of a pair (already known to be a
+// continuing box) into cells of level `cl` (side 64*8^cl).  Cells inside
+// both polygons add their size to `acc`; continuing cells become tasks.
+__device__ __forceinline__ void split_box(Ctx& c, const PairInfo& pi, int bx0, int by0, int bx1, int by1, int cl, bool kp, bool kq,
+                          uint64_t& acc) {
   const BatchArgs& a = *c.a;
   const int ls = 6 + 3 * cl;
   const int S = 1 << ls;
@@ -333,9 +387,9 @@ __device__ void split_box(Ctx& c, int64_t pair, const PairInfo& pi, int bx0, int
   const uint64_t both = in_p & in_q;
   const uint64_t cont = valid & ~out_p & ~out_q & ~both;
   // cells inside both polygons contribute their size at once
-  uint64_t add = 0;
   if (both) {
     const int lw = (bx1 - bx0) - (gx - 1) * S, lh = (by1 - by0) - (gy - 1) * S;
+    uint64_t add = 0;
     for (int j = 0; j < gy; ++j) {
       const uint32_t row = (uint32_t)(both >> (8 * j)) & 0xFFu;
       if (!row) continue;
@@ -343,75 +397,121 @@ __device__ void split_box(Ctx& c, int64_t pair, const PairInfo& pi, int bx0, int
       const uint32_t last = (row >> (gx - 1)) & 1u;
       add += hgt * ((uint64_t)(__popc(row) - last) * S + (uint64_t)last * lw);
     }
+    acc += add;
   }
-  if (c.lane == 0) add_counts(a, pair, add);
   if (a.stats_on) c.st_split += 1;
   // one lane per continuing cell
   const int n = __popcll(cont);
   bool has = false;
   uint64_t word = 0;
-  if (c.lane < 64 && ((cont >> c.lane) & 1ull)) {
+  if ((cont >> c.lane) & 1ull) {
     const int i = c.lane & 7, j = c.lane >> 3;
-    const Meta& B = pi.box;
-    const int tx = ((bx0 - B.x0) >> 6) + (i << (3 * cl));
-    const int ty = ((by0 - B.y0) >> 6) + (j << (3 * cl));
+    const int tx = ((bx0 - pi.box.x0) >> 6) + (i << (3 * cl));
+    const int ty = ((by0 - pi.box.y0) >> 6) + (j << (3 * cl));
     has = true;
-    word = task_word(pair, cl, tx, ty, (in_p >> c.lane) & 1ull, (in_q >> c.lane) & 1ull);
+    word = task_word(pi.hidx < 0 ? 0 : pi.hidx, cl, tx, ty, (in_p >> c.lane) & 1ull, (in_q >> c.lane) & 1ull);
   }
-  if (n) emit_children(c, word, has, n);
+  if (n) emit_children(c, pi, word, has, n);
 }
 
-__device__ void run_task(Ctx& c, uint64_t w) {
+// Process one box task of pair `pi`: a leaf tile or a further split.
+__device__ __forceinline__ void run_box(Ctx& c, const PairInfo& pi, uint64_t w, uint64_t& acc) {
   const BatchArgs& a = *c.a;
   const Task t = task_decode(w);
-  if (t.pair >= a.n_pairs) {
-    latch_error(a.err, kErrWatchdog);
-    return;
-  }
-  const PairInfo pi = pair_info(a, t.pair);
   const int side = kTile << (3 * t.level);
   const int x0 = pi.box.x0 + t.tx * kTile, y0 = pi.box.y0 + t.ty * kTile;
   const int x1 = min(x0 + side, pi.box.x1), y1 = min(y0 + side, pi.box.y1);
   const bool kp = t.kp && !(a.flags & SCCG_F_NO_KNOWN_INSIDE);
   const bool kq = t.kq && !(a.flags & SCCG_F_NO_KNOWN_INSIDE);
-  if (t.level == 0) {
-    const uint32_t n = leaf_count(c, pi, x0, y0, x1 - x0, y1 - y0, kp, kq);
-    if (c.lane == 0) add_counts(a, t.pair, n);
-  } else {
-    split_box(c, t.pair, pi, x0, y0, x1, y1, t.level - 1, kp, kq);
-  }
+  if (t.level == 0)
+    acc += leaf_count(c, pi, x0, y0, x1 - x0, y1 - y0, kp, kq);
+  else
+    split_box(c, pi, x0, y0, x1, y1, t.level - 1, kp, kq, acc);
 }
 
-__device__ void drain_local(Ctx& c) {
+__device__ __forceinline__ void drain_local(Ctx& c, const PairInfo& pi, uint64_t& acc) {
   while (c.lsp > 0) {
     c.lsp -= 1;
     wave_sync_lds();
     const uint64_t w = c.local[c.lsp];
     wave_sync_lds();
-    run_task(c, uniform64((int64_t)w));
+    run_box(c, pi, uniform64((int64_t)w), acc);
   }
 }
 
-__device__ void run_large(Ctx& c, int64_t pair) {
-  const BatchArgs& a = *c.a;
-  const PairInfo pi = pair_info(a, pair);
+// The whole of a pair whose box is larger than one tile: the root split and
+// every box this wave keeps.  Returns the intersection it counted.
+__device__ __forceinline__ uint64_t run_large(Ctx& c, const PairInfo& pi) {
   const int w = pi.box.x1 - pi.box.x0, h = pi.box.y1 - pi.box.y0;
   const int side = max(w, h);
   int cl = 0;
   while ((kTile << (3 * cl)) * kMaxGrid < side) ++cl;
-  split_box(c, pair, pi, pi.box.x0, pi.box.y0, pi.box.x1, pi.box.y1, cl, false, false);
-  drain_local(c);
+  uint64_t acc = 0;
+  split_box(c, pi, pi.box.x0, pi.box.y0, pi.box.x1, pi.box.y1, cl, false, false, acc);
+  drain_local(c, pi, acc);
+  return acc;
 }
 
-__device__ void run_small(Ctx& c, int64_t pair) {
+__device__ __forceinline__ PairInfo heavy_info(const BatchArgs& a, int64_t hidx) {
+  PairInfo pi;
+  pi.hidx = hidx;
+  pi.pair = a.l_list[hidx];
+  const int64_t ia = a.pa[pi.pair], ib = a.pb[pi.pair];
+  pi.op = a.A.off[ia];
+  pi.np = a.A.off[ia + 1] - pi.op;
+  pi.oq = a.B.off[ib];
+  pi.nq = a.B.off[ib + 1] - pi.oq;
+  pi.box = load_meta(a.hbox, hidx);
+  pi.area_sum = 0;
+  return pi;
+}
+
+// A pair from the sweep: MBRs and areas from its own rings, then one leaf
+// tile, or the large path kept entirely by this wave.
+__device__ __forceinline__ void run_pair(Ctx& c, int64_t i) {
   const BatchArgs& a = *c.a;
-  const PairInfo pi = pair_info(a, pair);
+  PairInfo pi;
+  pi.pair = i;
+  pi.hidx = -1;
+  const int64_t ia = a.pa[i], ib = a.pb[i];
+  pi.op = a.A.off[ia];
+  pi.np = a.A.off[ia + 1] - pi.op;
+  pi.oq = a.B.off[ib];
+  pi.nq = a.B.off[ib + 1] - pi.oq;
+  Meta mp, mq;
+  int64_t ap, aq;
+  ring_scan(a.A.xy, pi.op, pi.np, c.lane, mp, ap);
+  ring_scan(a.B.xy, pi.oq, pi.nq, c.lane, mq, aq);
+  if (c.lane == 0 && (coords_bad(mp, pi.np) || coords_bad(mq, pi.nq))) latch_error(a.err, kErrCoord);
+  if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[12], (unsigned long long)(pi.np + pi.nq));
+  pi.area_sum = ap + aq;
+  pi.box = pair_box(mp, mq);
   const int w = pi.box.x1 - pi.box.x0, h = pi.box.y1 - pi.box.y0;
-  const uint32_t n = leaf_count(c, pi, pi.box.x0, pi.box.y0, w, h, false, false);
+  uint64_t I = 0;
+  int64_t U = pi.area_sum;
+  if (pi.box.x0 >= pi.box.x1 || pi.box.y0 >= pi.box.y1) {
+    // empty pair box: nothing in common
+    if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
+  } else if (w > kMaxSide || h > kMaxSide) {
+    if (c.lane == 0) latch_error(a.err, kErrSide);
+    if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
+    U = 0;
+  } else if (w <= kTile && h <= kTile) {
+    I = leaf_count(c, pi, pi.box.x0, pi.box.y0, w, h, false, false);
+    if (a.stats_on && c.lane == 0) {
+      atomicAdd(&a.st->stats[5], 1ull);
+      atomicAdd(&a.st->stats[11], (unsigned long long)w * h);
+    }
+  } else {
+    I = run_large(c, pi);
+    if (a.stats_on && c.lane == 0) {
+      atomicAdd(&a.st->stats[6], 1ull);
+      atomicAdd(&a.st->stats[11], (unsigned long long)w * h);
+    }
+  }
   if (c.lane == 0) {
-    const int64_t ap = a.areaA[a.pa[pair]], aq = a.areaB[a.pb[pair]];
-    a.inter[pair] = (int64_t)n;
-    a.uni[pair] = ap + aq - (int64_t)n;
+    a.inter[i] = (int64_t)I;
+    a.uni[i] = U - (int64_t)I;
   }
 }
 
@@ -424,34 +524,86 @@ __global__ void __launch_bounds__(512) k_batch_run(BatchArgs args) {
   c.edges = reinterpret_cast<uint4*>(smem + (size_t)wave * kLdsPerWave);
   c.local = reinterpret_cast<uint64_t*>(smem + (size_t)wave * kLdsPerWave + kLeafCap * 16);
   c.lsp = 0;
-  c.home = (int)(blockIdx.x % (unsigned)args.n_queues);
-  c.st_leaf_tests = c.st_leaf = c.st_split = c.st_queued = c.st_inline = 0;
+  c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
+  c.home = c.xcd % args.n_queues;
+  c.st_leaf_tests = c.st_leaf = c.st_split = c.st_queued = c.st_kept = 0;
   c.st_edge_updates = c.st_class_edges = c.st_stage_edges = 0;
   const BatchArgs& a = args;
-  const unsigned long long n_heavy = a.st->l_count[0];
-  const unsigned long long n_large = n_heavy + a.st->l_count[1];
+  const unsigned long long n_heavy = a.st->l_count.v;
+  const unsigned long long n_chunks = ((unsigned long long)a.n_pairs + a.chunk - 1) / a.chunk;
+  uint32_t l_empty = 0, s_empty = 0;  // streams this wave found exhausted (wave-uniform)
   for (;;) {
     uint64_t w;
-    if (queue_claim(c, &w)) {
-      run_task(c, uniform64((int64_t)w));
-      drain_local(c);
+    if (queue_claim(c, false, &w)) {
+      const Task t = task_decode(w);
+      const PairInfo pi = heavy_info(a, t.hidx);
+      uint64_t acc = 0;
+      run_box(c, pi, w, acc);
+      drain_local(c, pi, acc);
+      if (c.lane == 0) add_counts(a, pi.pair, acc);
       continue;
     }
-    unsigned long long k = 0;
-    if (c.lane == 0) k = atomicAdd(&a.st->l_next, 1ull);
-    k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
-    if (k < n_large) {
-      const int64_t idx = (k < n_heavy) ? (int64_t)k : (int64_t)(a.n_pairs - 1 - (int64_t)(k - n_heavy));
-      run_large(c, (int64_t)a.l_list[idx]);
-      continue;
+    bool worked = false;
+    // heavy pairs first: a largest-first order over the pairs with most vertices
+    while (l_empty != 0xffu && !worked) {
+      int st = c.xcd;
+      while ((l_empty >> st) & 1u) st = (st + 1) % kStreams;
+      unsigned long long k = 0;
+      if (c.lane == 0) k = atomicAdd(&a.st->l_next[st].v, 1ull);
+      k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
+      const unsigned long long e = k * kStreams + st;
+      if (e < n_heavy) {
+        const PairInfo pi = heavy_info(a, (int64_t)e);
+        const unsigned long long area = (unsigned long long)(pi.box.x1 - pi.box.x0) * (pi.box.y1 - pi.box.y0);
+        if (a.cls[pi.pair] == kClsLarge) {
+          const uint64_t acc = run_large(c, pi);
+          if (c.lane == 0) add_counts(a, pi.pair, acc);
+          if (a.stats_on && c.lane == 0) {
+            atomicAdd(&a.st->stats[6], 1ull);
+            atomicAdd(&a.st->stats[11], area);
+          }
+        } else if (a.cls[pi.pair] == kClsSmall) {
+          const int bw = pi.box.x1 - pi.box.x0, bh = pi.box.y1 - pi.box.y0;
+          const uint32_t n = leaf_count(c, pi, pi.box.x0, pi.box.y0, bw, bh, false, false);
+          if (c.lane == 0) add_counts(a, pi.pair, n);
+          if (a.stats_on && c.lane == 0) {
+            atomicAdd(&a.st->stats[5], 1ull);
+            atomicAdd(&a.st->stats[11], area);
+          }
+        }
+        worked = true;
+      } else {
+        l_empty |= 1u << st;
+      }
     }
-    unsigned long long s0 = 0;
-    if (c.lane == 0) s0 = atomicAdd(&a.st->s_next, (unsigned long long)a.chunk);
-    s0 = (unsigned long long)uniform64((int64_t)__shfl((long long)s0, 0, kWave));
-    if (s0 < (unsigned long long)a.n_pairs) {
-      const int64_t e = min((int64_t)s0 + a.chunk, a.n_pairs);
-      for (int64_t i = (int64_t)s0; i < e; ++i)
-        if (a.cls[i] == kClsSmall) run_small(c, i);
+    if (worked) continue;
+    // chunks of the other pairs, in index order
+    while (s_empty != 0xffu && !worked) {
+      int st = c.xcd;
+      while ((s_empty >> st) & 1u) st = (st + 1) % kStreams;
+      unsigned long long k = 0;
+      if (c.lane == 0) k = atomicAdd(&a.st->s_next[st].v, 1ull);
+      k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
+      const unsigned long long g = k * kStreams + st;
+      if (g < n_chunks) {
+        const int64_t i0 = (int64_t)g * a.chunk;
+        const int64_t i1 = min(i0 + a.chunk, a.n_pairs);
+        for (int64_t i = i0; i < i1; ++i)
+          if (a.cls[i] == kClsSweep) run_pair(c, i);
+        worked = true;
+      } else {
+        s_empty |= 1u << st;
+      }
+    }
+    if (worked) continue;
+    // nothing of its own left: help with every queue, then stop
+    if (queue_claim(c, true, &w)) {
+      const Task t = task_decode(w);
+      const PairInfo pi = heavy_info(a, t.hidx);
+      uint64_t acc = 0;
+      run_box(c, pi, w, acc);
+      drain_local(c, pi, acc);
+      if (c.lane == 0) add_counts(a, pi.pair, acc);
       continue;
     }
     break;
@@ -461,7 +613,7 @@ __global__ void __launch_bounds__(512) k_batch_run(BatchArgs args) {
     atomicAdd(&a.st->stats[1], c.st_leaf);
     atomicAdd(&a.st->stats[2], c.st_split);
     atomicAdd(&a.st->stats[3], c.st_queued);
-    atomicAdd(&a.st->stats[4], c.st_inline);
+    atomicAdd(&a.st->stats[4], c.st_kept);
     atomicAdd(&a.st->stats[8], c.st_edge_updates);
     atomicAdd(&a.st->stats[9], c.st_class_edges);
     atomicAdd(&a.st->stats[10], c.st_stage_edges);
@@ -469,10 +621,10 @@ __global__ void __launch_bounds__(512) k_batch_run(BatchArgs args) {
 }
 
 // ------------------------------------------------------------ setup / reset
-// Clear the queue slots the previous call wrote, then the counters.
+// Clear the queue slots the previous call touched, then the counters.
 __global__ void __launch_bounds__(256) k_batch_clear_slots(BatchArgs a) {
   for (int q = 0; q < a.n_queues; ++q) {
-    unsigned long long used = a.st->q_tail[q];
+    unsigned long long used = max(a.st->q_tail[q].v, a.st->q_head[q].v);
     if (used > (unsigned long long)a.queue_cap) used = (unsigned long long)a.queue_cap;
     unsigned long long* base = a.queue + (size_t)q * a.queue_cap;
     for (unsigned long long j = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; j < used;
@@ -482,68 +634,78 @@ __global__ void __launch_bounds__(256) k_batch_clear_slots(BatchArgs a) {
 }
 
 __global__ void k_batch_clear_counters(BatchArgs a) {
-  const int t = threadIdx.x;
   unsigned long long* p = reinterpret_cast<unsigned long long*>(a.st);
   const int n = (int)(sizeof(BatchState) / sizeof(unsigned long long));
-  for (int k = t; k < n; k += blockDim.x) p[k] = 0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0;
 }
 
+// Per pair: index check; pairs with many vertices go to the heavy list.
 __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool large = false, heavy = false;
+  bool heavy = false;
   if (i < a.n_pairs) {
     const int64_t ia = a.pa[i], ib = a.pb[i];
-    uint8_t cls = kClsDone;
+    uint8_t cls = kClsSweep;
     if (ia < 0 || ia >= a.A.n || ib < 0 || ib >= a.B.n) {
       latch_error(a.err, kErrIndex);
       a.inter[i] = 0;
       a.uni[i] = 0;
-    } else {
-      const Meta bx = pair_box(load_meta(a.metaA, ia), load_meta(a.metaB, ib));
-      const int64_t ap = a.areaA[ia], aq = a.areaB[ib];
-      if (bx.x0 >= bx.x1 || bx.y0 >= bx.y1) {
-        a.inter[i] = 0;
-        a.uni[i] = ap + aq;
-      } else {
-        const int w = bx.x1 - bx.x0, h = bx.y1 - bx.y0;
-        if (w > kMaxSide || h > kMaxSide) {
-          latch_error(a.err, kErrSide);
-          a.inter[i] = 0;
-          a.uni[i] = 0;
-        } else if (w <= kTile && h <= kTile) {
-          cls = kClsSmall;
-        } else {
-          cls = kClsLarge;
-          large = true;
-          heavy = !(a.flags & SCCG_F_NO_LPT) && (int64_t)w * h >= (int64_t)a.heavy_area;
-          a.inter[i] = 0;
-          a.uni[i] = ap + aq;
-        }
+      cls = kClsDone;
+    } else if (!(a.flags & SCCG_F_NO_LPT)) {
+      const int64_t nv = (a.A.off[ia + 1] - a.A.off[ia]) + (a.B.off[ib + 1] - a.B.off[ib]);
+      if (nv >= a.heavy_verts) {
+        heavy = true;
+        cls = kClsHeavy;
       }
     }
     a.cls[i] = cls;
   }
-  // heavy pairs fill the list from the front, the other large pairs from the back
-  const uint64_t bh = ballot(large && heavy), bl = ballot(large && !heavy);
-  unsigned long long baseh = 0, basel = 0;
-  if (lane_id() == 0) {
-    if (bh) baseh = atomicAdd(&a.st->l_count[0], (unsigned long long)__popcll(bh));
-    if (bl) basel = atomicAdd(&a.st->l_count[1], (unsigned long long)__popcll(bl));
-  }
-  baseh = (unsigned long long)__shfl((long long)baseh, 0, kWave);
-  basel = (unsigned long long)__shfl((long long)basel, 0, kWave);
-  if (large && heavy) a.l_list[baseh + lanes_below(bh)] = (int32_t)i;
-  if (large && !heavy) a.l_list[a.n_pairs - 1 - (int64_t)(basel + lanes_below(bl))] = (int32_t)i;
+  const uint64_t bh = ballot(heavy);
+  unsigned long long base = 0;
+  if (lane_id() == 0 && bh) base = atomicAdd(&a.st->l_count.v, (unsigned long long)__popcll(bh));
+  base = (unsigned long long)__shfl((long long)base, 0, kWave);
+  if (heavy) a.l_list[base + lanes_below(bh)] = (int32_t)i;
 }
 
-__global__ void k_batch_stats_classes(BatchArgs a) {
-  // small / large / done-with-empty-box counts (stats only)
+// One wave per heavy pair: MBRs and areas of both rings, the pair box and the
+// pair's class; the outputs start at I = 0, U = |p| + |q| (boxes add to I and
+// subtract from U atomically).
+__global__ void __launch_bounds__(256) k_batch_heavy_meta(BatchArgs a) {
+  const int lane = lane_id();
+  const int waves = gridDim.x * (blockDim.x / kWave);
+  const int64_t n = (int64_t)a.st->l_count.v;
+  for (int64_t k = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; k < n; k += waves) {
+    const int64_t i = a.l_list[k];
+    const int64_t ia = a.pa[i], ib = a.pb[i];
+    const int64_t op = a.A.off[ia], oq = a.B.off[ib];
+    Meta mp, mq;
+    int64_t ap, aq;
+    ring_scan(a.A.xy, op, a.A.off[ia + 1] - op, lane, mp, ap);
+    ring_scan(a.B.xy, oq, a.B.off[ib + 1] - oq, lane, mq, aq);
+    if (lane != 0) continue;
+    if (coords_bad(mp, a.A.off[ia + 1] - op) || coords_bad(mq, a.B.off[ib + 1] - oq)) latch_error(a.err, kErrCoord);
+    const Meta b = pair_box(mp, mq);
+    *reinterpret_cast<int4*>(a.hbox + k) = make_int4(b.x0, b.y0, b.x1, b.y1);
+    const int64_t w = (int64_t)b.x1 - b.x0, h = (int64_t)b.y1 - b.y0;
+    uint8_t cls = kClsDone;
+    a.inter[i] = 0;
+    a.uni[i] = ap + aq;
+    if (b.x0 >= b.x1 || b.y0 >= b.y1) {
+      cls = kClsDone;
+    } else if (w > kMaxSide || h > kMaxSide) {
+      latch_error(a.err, kErrSide);
+      a.uni[i] = 0;
+    } else {
+      cls = (w <= kTile && h <= kTile) ? kClsSmall : kClsLarge;
+    }
+    a.cls[i] = cls;
+  }
+}
+
+__global__ void k_batch_stats_empty(BatchArgs a) {
+  // pairs that ended in setup or in the heavy prepass (stats only)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n_pairs) return;
-  const uint8_t c = a.cls[i];
-  if (c == kClsSmall) atomicAdd(&a.st->stats[5], 1ull);
-  else if (c == kClsLarge) atomicAdd(&a.st->stats[6], 1ull);
-  else atomicAdd(&a.st->stats[7], 1ull);
+  if (i < a.n_pairs && a.cls[i] == kClsDone) atomicAdd(&a.st->stats[7], 1ull);
 }
 
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s) {
@@ -556,7 +718,7 @@ hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((a.n_pairs + 255) / 256);
   hipLaunchKernelGGL(k_batch_setup, dim3(blocks), dim3(256), 0, s, a);
-  if (a.stats_on) hipLaunchKernelGGL(k_batch_stats_classes, dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_batch_heavy_meta, dim3(2048), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -572,6 +734,8 @@ hipError_t launch_batch_run(const BatchArgs& a, int grid, int waves_per_wg, hipS
   if (a.n_pairs <= 0) return hipSuccess;
   const size_t lds = (size_t)waves_per_wg * batch_lds_bytes_per_wave();
   hipLaunchKernelGGL(k_batch_run, dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
+  if (a.stats_on)
+    hipLaunchKernelGGL(k_batch_stats_empty, dim3((unsigned)((a.n_pairs + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

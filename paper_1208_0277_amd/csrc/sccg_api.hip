@@ -31,6 +31,7 @@ struct sccg_ctx {
   // per-pair scratch
   uint8_t* cls = nullptr;
   int32_t* l_list = nullptr;
+  Meta* hbox = nullptr;
   int64_t cap_pairs = 0;
   // batched state and queues
   BatchState* st = nullptr;
@@ -90,7 +91,7 @@ int resolve_params(sccg_ctx* c, const sccg_params* in, sccg_params* out) {
   if (p.box_threshold == 0) p.box_threshold = p.wg_size * p.wg_size / 2;
   if (p.box_threshold < 2 || p.box_threshold > (1 << 30))
     return fail(c, SCCG_E_ARG, "box_threshold %d outside [2, 2^30]", p.box_threshold);
-  if (p.queue_chunk == 0) p.queue_chunk = 8;
+  if (p.queue_chunk == 0) p.queue_chunk = 32;
   if (p.queue_chunk < 1 || p.queue_chunk > 4096) return fail(c, SCCG_E_ARG, "queue_chunk outside [1, 4096]");
   if (p.lds_vertex_cap == 0) p.lds_vertex_cap = 1024;
   if (p.lds_vertex_cap < 1 || p.lds_vertex_cap > 4096)
@@ -106,8 +107,8 @@ int resolve_params(sccg_ctx* c, const sccg_params* in, sccg_params* out) {
   if (p.min_queue_cells < 1 || p.min_queue_cells > 65) return fail(c, SCCG_E_ARG, "min_queue_cells outside [1, 65]");
   if (p.n_queues == 0) p.n_queues = kMaxGrid;
   if (p.n_queues < 1 || p.n_queues > kMaxGrid) return fail(c, SCCG_E_ARG, "n_queues outside [1, 8]");
-  if (p.heavy_side == 0) p.heavy_side = 128;
-  if (p.heavy_side < 1 || p.heavy_side > kMaxSide) return fail(c, SCCG_E_ARG, "heavy_side outside [1, 32767]");
+  if (p.heavy_verts == 0) p.heavy_verts = 512;
+  if (p.heavy_verts < 1) return fail(c, SCCG_E_ARG, "heavy_verts < 1");
   *out = p;
   return SCCG_OK;
 }
@@ -147,7 +148,8 @@ int ensure_pairs(sccg_ctx* c, int64_t n) {
   (void)hipStreamSynchronize(c->stream);
   int64_t want = n + n / 4 + 1024;
   int r;
-  if ((r = grow(c, &c->cls, want, "pair classes")) || (r = grow(c, &c->l_list, want, "large list"))) {
+  if ((r = grow(c, &c->cls, want, "pair classes")) || (r = grow(c, &c->l_list, want, "heavy list")) ||
+      (r = grow(c, &c->hbox, want, "heavy boxes"))) {
     c->cap_pairs = 0;
     return r;
   }
@@ -258,7 +260,7 @@ int sccg_destroy(sccg_ctx* c) {
   drop_graph(c);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   void* ptrs[] = {c->metaA, c->areaA, c->bigA, c->metaB, c->areaB, c->bigB, c->big_count, c->err,
-                  c->cls,   c->l_list, c->st,  c->queue, c->plain_stats};
+                  c->cls,   c->l_list, c->hbox, c->st, c->queue, c->plain_stats};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -342,12 +344,6 @@ __global__ void k_zero_stats(unsigned long long* s) {
 
 static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int grid) {
   hipError_t e;
-  if ((e = launch_poly_meta(ba.A, const_cast<Meta*>(ba.metaA), const_cast<int64_t*>(ba.areaA), c->bigA, c->big_count,
-                            c->err, c->stream)) != hipSuccess)
-    return hip_fail(c, e, "poly meta A");
-  if ((e = launch_poly_meta(ba.B, const_cast<Meta*>(ba.metaB), const_cast<int64_t*>(ba.areaB), c->bigB,
-                            c->big_count + 1, c->err, c->stream)) != hipSuccess)
-    return hip_fail(c, e, "poly meta B");
   if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
   if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -373,9 +369,9 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   if (n_pairs == 0) return SCCG_OK;
   if (!pair_a || !pair_b || !out_inter || !out_union) return fail(c, SCCG_E_ARG, "NULL pair or output array");
   HIP_TRY(c, hipSetDevice(c->device));
-  if ((r = ensure_polys(c, 0, A->n_polys)) || (r = ensure_polys(c, 1, B->n_polys))) return r;
   c->last_mode = mode;
   if (mode == SCCG_PLAIN) {
+    if ((r = ensure_polys(c, 0, A->n_polys)) || (r = ensure_polys(c, 1, B->n_polys))) return r;
     hipError_t e;
     if ((e = launch_poly_meta(to_polys(A), c->metaA, c->areaA, c->bigA, c->big_count, c->err, c->stream)) !=
         hipSuccess)
@@ -419,10 +415,6 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   BatchArgs ba{};
   ba.A = to_polys(A);
   ba.B = to_polys(B);
-  ba.metaA = c->metaA;
-  ba.metaB = c->metaB;
-  ba.areaA = c->areaA;
-  ba.areaB = c->areaB;
   ba.n_pairs = n_pairs;
   ba.pa = pair_a;
   ba.pb = pair_b;
@@ -431,12 +423,13 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   ba.err = c->err;
   ba.cls = c->cls;
   ba.l_list = c->l_list;
+  ba.hbox = c->hbox;
   ba.st = c->st;
   ba.queue = c->queue;
   ba.queue_cap = c->p.queue_cap;
   ba.n_queues = c->p.n_queues;
   ba.chunk = c->p.queue_chunk;
-  ba.heavy_area = c->p.heavy_side * c->p.heavy_side > (1 << 30) ? (1 << 30) : c->p.heavy_side * c->p.heavy_side;
+  ba.heavy_verts = c->p.heavy_verts;
   ba.min_cells_to_queue = c->p.min_queue_cells;
   ba.flags = c->p.flags;
   ba.stats_on = c->stats_on;
@@ -450,7 +443,7 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
            (long long)A->n_polys, (const void*)A->offsets, (const void*)A->xy,
            (long long)B->n_polys, (const void*)B->offsets, (const void*)B->xy, (long long)n_pairs,
            (const void*)pair_a, (const void*)pair_b, (void*)out_inter, (void*)out_union, ba.queue_cap, ba.n_queues,
-           ba.chunk, ba.heavy_area, ba.min_cells_to_queue, ba.flags, ba.stats_on, grid);
+           ba.chunk, ba.heavy_verts, ba.min_cells_to_queue, ba.flags, ba.stats_on, grid);
   if (!c->gexec || c->gkey != key) {
     drop_graph(c);
     hipGraph_t g = nullptr;

@@ -22,8 +22,9 @@ enum : uint32_t {
   kErrWatchdog = 8u,  // a bounded wait in the persistent kernel ran out
 };
 
-// Pair classes written by the setup pass of the batched path.
-enum : uint8_t { kClsDone = 0, kClsSmall = 1, kClsLarge = 2 };
+// Pair classes of the batched path: done in a prepass, swept in index
+// order, or heavy (claimed first); heavy pairs are then marked by their box.
+enum : uint8_t { kClsDone = 0, kClsSweep = 1, kClsHeavy = 2, kClsSmall = 3, kClsLarge = 4 };
 
 struct Polys {
   int64_t n;
@@ -68,24 +69,31 @@ hipError_t launch_plain(const PlainArgs& a, int wg_size, int grid, hipStream_t s
 int plain_lds_bytes(int wg_size, int lds_vertex_cap);
 int plain_occupancy(int wg_size, int lds_vertex_cap);
 
-// Device-side state of the batched path (one block of device memory).
+// A device counter on a cache line of its own, so that claims on different
+// counters never contend for one line.
+struct alignas(128) Counter {
+  unsigned long long v;
+  unsigned long long pad[15];
+};
+
+// Work is claimed from kStreams interleaved streams (one per XCD): stream s
+// owns entries s, s + kStreams, s + 2 kStreams, ... of a list.
+constexpr int kStreams = 8;
+
+// Device-side state of the batched path (one block of device memory), reset
+// at the start of every call after the slots the previous call touched
+// (below max(head, tail) of each queue) are cleared.
 struct BatchState {
-  // counters, reset at the start of every call
-  unsigned long long l_count[2];    // large pairs: [0] heavy bucket, [1] the rest
-  unsigned long long l_next;        // next entry of the large list to claim
-  unsigned long long s_next;        // next pair index for the small-pair sweep
-  unsigned long long q_tail[kMaxGrid];  // per-queue reservation counters
-  unsigned long long q_head[kMaxGrid];  // per-queue claim counters
-  unsigned long long q_used[kMaxGrid];  // slots written by the previous call (cleared at the next)
+  Counter l_count;            // heavy pairs listed by the setup pass
+  Counter l_next[kStreams];   // per-stream claim counters over the heavy list
+  Counter s_next[kStreams];   // per-stream claim counters over pair chunks
+  Counter q_head[kMaxGrid];   // per-queue ticket counters
+  Counter q_tail[kMaxGrid];   // per-queue reservation counters
   unsigned long long stats[kNumStats];
 };
 
 struct BatchArgs {
   Polys A, B;
-  const Meta* metaA;
-  const Meta* metaB;
-  const int64_t* areaA;
-  const int64_t* areaB;
   int64_t n_pairs;
   const int32_t* pa;
   const int32_t* pb;
@@ -93,13 +101,14 @@ struct BatchArgs {
   int64_t* uni;
   uint32_t* err;
   uint8_t* cls;                  // [n_pairs]
-  int32_t* l_list;               // [n_pairs] large pairs, heavy bucket first
+  int32_t* l_list;               // [n_pairs] heavy pairs
+  Meta* hbox;                    // [n_pairs] pair box of heavy-list entry k
   BatchState* st;
   unsigned long long* queue;     // [n_queues * queue_cap] task words, 0 = empty
   int32_t queue_cap;             // slots per queue
   int32_t n_queues;
   int32_t chunk;                 // small pairs per claim
-  int32_t heavy_area;            // pair-box area from which a large pair is "heavy" (LPT bucket)
+  int32_t heavy_verts;           // pairs with at least this many vertices are claimed first
   int32_t min_cells_to_queue;    // a split pushes its boxes to the queue only from this many boxes
   uint32_t flags;                // SCCG_F_*
   int32_t stats_on;
