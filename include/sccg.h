@@ -91,7 +91,7 @@ typedef struct {
   int32_t box_threshold;  /* PLAIN: pixelize when BOXSIZE < T (default wg_size^2/2, Section 3.4)     */
   int32_t split_gx;       /* PLAIN: sub-box grid; split_gx*split_gy == wg_size (default square-ish) */
   int32_t split_gy;
-  int32_t queue_chunk;    /* BATCHED: small pairs claimed per counter access (default 32)             */
+  int32_t queue_chunk;    /* BATCHED: pairs claimed per counter access, 1..64 (default 16)            */
   int32_t lds_vertex_cap; /* PLAIN: vertices of both rings staged in LDS, 1..4096 (default 1024; above
                              it the rings are read from global memory)                               */
   uint32_t flags;         /* SCCG_F_*                                                                 */

@@ -21,7 +21,7 @@ import paper_1208_0277_amd as sccg
 #: batched-mode candidates, swept in this order
 BATCHED_SPACE = [
     ("min_queue_cells", [24, 8, 65]),
-    ("queue_chunk", [8, 16, 32]),
+    ("queue_chunk", [16, 8, 32, 64]),
     ("waves_per_wg", [4, 2, 8]),
     ("heavy_verts", [512, 1024, 2048]),
 ]

@@ -47,10 +47,16 @@
 
 namespace sccg {
 
-constexpr int kLeafCap = 128;   // staged band edges per flush (per wave)
+constexpr int kLeafCap = 256;   // staged band edges per flush (per wave)
 constexpr int kLocalCap = 256;  // per-wave stack of boxes to process inline
 constexpr uint32_t kSpinLimit = 1u << 22;
-constexpr int kLdsPerWave = kLeafCap * 16 + kLocalCap * 8;
+// per-wave LDS: staged edges, the inline box stack, the metadata of one chunk
+struct ChunkMeta {
+  int64_t op, oq;
+  int32_t np, nq;
+  int32_t cls, pad;
+};
+constexpr int kLdsPerWave = kLeafCap * 16 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta);
 constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
 
 int batch_lds_bytes_per_wave() { return kLdsPerWave; }
@@ -98,6 +104,7 @@ struct Ctx {
   int lane;
   uint4* edges;     // per-wave staging, kLeafCap entries
   uint64_t* local;  // per-wave inline stack, kLocalCap entries
+  ChunkMeta* meta;  // per-wave metadata of the pairs of one chunk
   int lsp;          // inline stack depth (wave-uniform)
   int home;         // preferred queue
   int xcd;          // first claim stream (the workgroup's XCD under round-robin dispatch)
@@ -114,97 +121,197 @@ struct PairInfo {
   int64_t area_sum;  // |p| + |q|
 };
 
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Extent and |shoelace|/2 of one ring, reduced across the wave from
-// coalesced loads (Section 3.2's area formula, wrapping 64-bit sum).
-__device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv, int lane, Meta& m, int64_t& area) {
-  int32_t x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
-  uint64_t twice = 0;
+// ------------------------------------------------------------- ring scans
+// A lane's view of the first two 64-vertex chunks of a ring: vertex k and its
+// successor for k = lane and k = lane + 64.  Loaded once (coalesced), used for
+// the extent, the area and the leaf edges.
+struct RingRegs {
+  int2 v0, w0, v1, w1;
+};
+
+__device__ __forceinline__ void load_edge(const int2* xy, int64_t o, int64_t nv, int64_t k, int2& v, int2& w) {
+  if (k < nv) {
+    v = xy[o + k];
+    w = xy[o + (k + 1 == nv ? 0 : k + 1)];
+  } else {
+    v = w = make_int2(0, 0);
+  }
+}
+
+// The value of the next lane (DPP wave shift left by one; lane 63 reads 0).
+__device__ __forceinline__ int2 next_lane(int2 v) {
+  return make_int2(__builtin_amdgcn_update_dpp(0, v.x, 0x130, 0xf, 0xf, false),
+                   __builtin_amdgcn_update_dpp(0, v.y, 0x130, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ int2 lane_value(int2 v, int l) {
+  return make_int2(__builtin_amdgcn_readlane(v.x, l), __builtin_amdgcn_readlane(v.y, l));
+}
+
+// Load the first two 64-vertex chunks of a ring with one coalesced load each;
+// each vertex's successor comes from the neighbouring lane, lane 63's from
+// the next chunk, and the last vertex's is vertex 0.
+__device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int64_t nv, int lane, RingRegs& r,
+                                           int2& first) {
+  const int64_t k0 = lane, k1 = lane + kWave;
+  r.v0 = k0 < nv ? xy[o + k0] : make_int2(0, 0);
+  r.v1 = k1 < nv ? xy[o + k1] : make_int2(0, 0);
+  first = lane_value(r.v0, 0);
+  const int2 a64 = nv > kWave ? lane_value(r.v1, 0) : first;
+  const int2 a128 = nv > 2 * kWave ? xy[o + 2 * kWave] : first;
+  int2 s0 = next_lane(r.v0), s1 = next_lane(r.v1);
+  if (lane == kWave - 1) {
+    s0 = a64;
+    s1 = a128;
+  }
+  if (k0 + 1 == nv) s0 = first;
+  if (k1 + 1 == nv) s1 = first;
+  r.w0 = s0;
+  r.w1 = s1;
+}
+
+// Extent and |shoelace|/2 of one ring (Section 3.2's area formula), reduced
+// across the wave.  Fast form: coordinates relative to the first vertex fit in
+// [-2^14, 2^14), so (dx, dy) pack into int16 pairs (one packed min and one
+// packed max reduction) and twice the area, below 2^31, is exact in wrapping
+// 32-bit arithmetic with 24-bit multiplies.  Rings that do not fit are
+// rescanned in 32/64-bit.  Empty rings and rings with |coordinate| > 2^30
+// come back empty.
+__device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t nv, int lane, RingRegs& r, Meta& m,
+                                            int64_t& area) {
+  int2 first;
+  load_ring2(xy, o, nv, lane, r, first);
+  uint32_t pmin = 0x7fff7fffu, pmax = 0x80008000u, twice = 0u, wide = 0u;
   for (int64_t base = 0; base < nv; base += kWave) {
     const int64_t k = base + lane;
+    int2 v, w;
+    if (base == 0) {
+      v = r.v0;
+      w = r.w0;
+    } else if (base == kWave) {
+      v = r.v1;
+      w = r.w1;
+    } else {
+      load_edge(xy, o, nv, k, v, w);
+    }
     if (k < nv) {
-      const int2 v = xy[o + k];
-      const int2 w = xy[o + (k + 1 == nv ? 0 : k + 1)];
-      x0 = min(x0, v.x);
-      y0 = min(y0, v.y);
-      x1 = max(x1, v.x);
-      y1 = max(y1, v.y);
-      twice += (uint64_t)((int64_t)v.x * w.y) - (uint64_t)((int64_t)w.x * v.y);
+      const int dx = v.x - first.x, dy = v.y - first.y;
+      const int ex = w.x - first.x, ey = w.y - first.y;
+      wide |= (uint32_t)((dx + 16384) | (dy + 16384)) >> 15;
+      const uint32_t pk = ((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16);
+      pmin = op_pkmin_i16(pmin, pk);
+      pmax = op_pkmax_i16(pmax, pk);
+      twice += (uint32_t)__mul24(dx, ey) - (uint32_t)__mul24(ex, dy);
     }
   }
-  m.x0 = wave_min_i32(x0);
-  m.y0 = wave_min_i32(y0);
-  m.x1 = wave_max_i32(x1);
-  m.y1 = wave_max_i32(y1);
-  const int64_t t = (int64_t)wave_sum_u64(twice);
-  area = (t < 0 ? -t : t) / 2;
+  const bool any_wide = ballot(wide != 0u) != 0ull;
+  if (!any_wide) {
+    const uint32_t mn = wave_pkmin_i16(pmin), mx = wave_pkmax_i16(pmax);
+    const int32_t t = (int32_t)wave_sum_u32(twice);
+    m.x0 = first.x + (int32_t)(int16_t)(mn & 0xffffu);
+    m.y0 = first.y + (int32_t)(int16_t)(mn >> 16);
+    m.x1 = first.x + (int32_t)(int16_t)(mx & 0xffffu);
+    m.y1 = first.y + (int32_t)(int16_t)(mx >> 16);
+    area = (int64_t)(t < 0 ? -(int64_t)t : (int64_t)t) / 2;
+  } else {
+    int32_t x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
+    uint64_t tw = 0;
+    for (int64_t base = 0; base < nv; base += kWave) {
+      const int64_t k = base + lane;
+      int2 v, w;
+      load_edge(xy, o, nv, k, v, w);
+      if (k < nv) {
+        x0 = min(x0, v.x);
+        y0 = min(y0, v.y);
+        x1 = max(x1, v.x);
+        y1 = max(y1, v.y);
+        tw += (uint64_t)((int64_t)v.x * w.y) - (uint64_t)((int64_t)w.x * v.y);
+      }
+    }
+    m.x0 = wave_min_i32(x0);
+    m.y0 = wave_min_i32(y0);
+    m.x1 = wave_max_i32(x1);
+    m.y1 = wave_max_i32(y1);
+    const int64_t t = (int64_t)wave_sum_u64(tw);
+    area = (t < 0 ? -t : t) / 2;
+  }
   if (nv <= 0 || m.x0 < -kMaxCoord || m.y0 < -kMaxCoord || m.x1 > kMaxCoord || m.y1 > kMaxCoord) {
-    // empty or rejected ring: covers nothing
-    m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+    m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};  // covers nothing
     area = 0;
   }
+}
+
+__device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv, int lane, Meta& m, int64_t& area) {
+  RingRegs r;
+  ring_extent(xy, o, nv, lane, r, m, area);
 }
 
 __device__ __forceinline__ bool coords_bad(const Meta& m, int64_t nv) {
   return nv > 0 && m.x0 == INT_MAX;
 }
 
-// XOR the staged edges into this lane's column mask: an edge at relative
-// X = xr toggles, in every column x < xr, the rows it spans.
+// ------------------------------------------------------------------ leaves
+// A staged edge toggles, in every column x < xr of its tile, the rows of rr.
+// m ^= rr & (x < xr ? ~0 : 0), one v_bitop3 per 32-bit half.
+__device__ __forceinline__ uint32_t toggle32(uint32_t m, uint32_t rr, uint32_t sel) {
+  return __builtin_amdgcn_bitop3_b32(m, rr, sel, 0x78);  // m ^ (rr & sel)
+}
+
+// XOR the staged edges into this lane's column mask.  The loop keeps four
+// LDS reads in flight (deeper unrolling costs registers, hence occupancy).
 __device__ __forceinline__ void flush_edges(const uint4* e, int cnt, int lane, uint64_t& m) {
   wave_sync_lds();
   uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-  int k = 0;
-  for (; k + 2 <= cnt; k += 2) {
-    const uint4 a = e[k], b = e[k + 1];
-    const uint32_t sa = (uint32_t)lane < a.x ? ~0u : 0u;
-    const uint32_t sb = (uint32_t)lane < b.x ? ~0u : 0u;
-    lo ^= a.y & sa;
-    hi ^= a.z & sa;
-    lo ^= b.y & sb;
-    hi ^= b.z & sb;
-  }
-  if (k < cnt) {
+#pragma unroll 4
+  for (int k = 0; k < cnt; ++k) {
     const uint4 a = e[k];
     const uint32_t sa = (uint32_t)lane < a.x ? ~0u : 0u;
-    lo ^= a.y & sa;
-    hi ^= a.z & sa;
+    lo = toggle32(lo, a.y, sa);
+    hi = toggle32(hi, a.z, sa);
   }
   m = ((uint64_t)hi << 32) | lo;
   wave_sync_lds();
 }
 
+// The leaf edge of (v, w) for the tile at (tx0, ty0) of height th: kept iff
+// vertical, right of the tile's left side, with a span meeting the rows.
+__device__ __forceinline__ bool leaf_edge(int2 v, int2 w, int tx0, int ty0, int th, uint32_t& xr, uint64_t& rr) {
+  if (v.x != w.x) return false;
+  const int lo = max(min(v.y, w.y) - ty0, 0);
+  const int hi = min(max(v.y, w.y) - ty0, th);
+  const int dx = v.x - tx0;
+  if (!(lo < hi && dx > 0)) return false;
+  xr = (uint32_t)min(dx, kTile);
+  rr = row_range(lo, hi);
+  return true;
+}
+
 // Column masks of polygon ring xy[o .. o+nv) over the leaf tile
 // [tx0, tx0+64) x [ty0, ty0+th): bit r of lane x is the crossing parity of
 // pixel (tx0 + x, ty0 + r).
-__device__ __forceinline__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o, int64_t nv, int tx0, int ty0, int th) {
+__device__ __forceinline__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o, int64_t nv, int tx0, int ty0,
+                                               int th) {
   const int lane = c.lane;
   uint64_t m = 0;
   int cnt = 0;
   for (int64_t base = 0; base < nv; base += kWave) {
-    const int64_t k = base + lane;
-    bool keep = false;
+    int2 v, w;
+    load_edge(xy, o, nv, base + lane, v, w);
     uint32_t xr = 0;
     uint64_t rr = 0;
-    if (k < nv) {
-      const int2 v = xy[o + k];
-      const int2 w = xy[o + (k + 1 == nv ? 0 : k + 1)];
-      if (v.x == w.x) {
-        const int lo = max(min(v.y, w.y) - ty0, 0);
-        const int hi = min(max(v.y, w.y) - ty0, th);
-        const int dx = v.x - tx0;
-        keep = (lo < hi) && (dx > 0);
-        if (keep) {
-          xr = (uint32_t)min(dx, kTile);
-          rr = row_range(lo, hi);
-        }
-      }
-    }
+    const bool keep = (base + lane < nv) && leaf_edge(v, w, tx0, ty0, th, xr, rr);
     const uint64_t b = ballot(keep);
     const int nk = __popcll(b);
     if (cnt + nk > kLeafCap) {
@@ -218,6 +325,106 @@ __device__ __forceinline__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o
   if (cnt > 0) flush_edges(c.edges, cnt, lane, m);
   if (c.a->stats_on) c.st_stage_edges += (unsigned long long)nv;
   return m;
+}
+
+// Stage the leaf edges of one ring for a small pair's tile into e[0 ..),
+// reading the first two chunks from registers.  Returns the count, or -1 if
+// more than `cap` edges (the caller then takes the general path).
+__device__ __forceinline__ int stage_small(Ctx& c, const int2* xy, int64_t o, int64_t nv, const RingRegs& r,
+                                           int tx0, int ty0, int th, uint4* e, int cap) {
+  const int lane = c.lane;
+  int cnt = 0;
+  for (int64_t base = 0; base < nv; base += kWave) {
+    int2 v, w;
+    if (base == 0) {
+      v = r.v0;
+      w = r.w0;
+    } else if (base == kWave) {
+      v = r.v1;
+      w = r.w1;
+    } else {
+      load_edge(xy, o, nv, base + lane, v, w);
+    }
+    uint32_t xr = 0;
+    uint64_t rr = 0;
+    const bool keep = (base + lane < nv) && leaf_edge(v, w, tx0, ty0, th, xr, rr);
+    const uint64_t b = ballot(keep);
+    const int nk = __popcll(b);
+    if (cnt + nk > cap) return -1;
+    if (keep) e[cnt + lanes_below(b)] = make_uint4(xr, (uint32_t)rr, (uint32_t)(rr >> 32), 0u);
+    cnt += nk;
+  }
+  if (c.a->stats_on) {
+    c.st_edge_updates += cnt;
+    c.st_stage_edges += (unsigned long long)nv;
+  }
+  return cnt;
+}
+
+constexpr int kHalfCap = kLeafCap / 2;
+
+// Intersection count of a small pair (box <= 64 x 64 = the whole leaf tile),
+// from edges staged once.  Narrow boxes (w <= 32) run p in lanes 0-31 and q
+// in lanes 32-63 at the same time; short boxes (h <= 32) use 32-bit row
+// masks.  Returns -1 when an edge list does not fit (general path instead).
+template <bool kRows64>
+__device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const RingRegs& rp, const RingRegs& rq,
+                                              int tw, int th) {
+  const BatchArgs& a = *c.a;
+  const int lane = c.lane;
+  const int tx0 = pi.box.x0, ty0 = pi.box.y0;
+  uint4* ep = c.edges;
+  uint4* eq = c.edges + kHalfCap;
+  const int np = stage_small(c, a.A.xy, pi.op, pi.np, rp, tx0, ty0, th, ep, kHalfCap);
+  const int nq = np < 0 ? -1 : stage_small(c, a.B.xy, pi.oq, pi.nq, rq, tx0, ty0, th, eq, kHalfCap);
+  if (np < 0 || nq < 0) return -1;
+  uint32_t n = 0;
+  if (tw <= 32) {
+    // pad the shorter list with null edges, then one pass for both rings
+    const int nm = max(np, nq);
+    for (int k = np + lane; k < nm; k += kWave) ep[k] = make_uint4(0u, 0u, 0u, 0u);
+    for (int k = nq + lane; k < nm; k += kWave) eq[k] = make_uint4(0u, 0u, 0u, 0u);
+    wave_sync_lds();
+    const uint4* e = lane < 32 ? ep : eq;
+    const uint32_t col = (uint32_t)(lane & 31);
+    uint32_t lo = 0, hi = 0;
+#pragma unroll 4
+    for (int k = 0; k < nm; ++k) {
+      const uint4 x = e[k];
+      const uint32_t s = col < x.x ? ~0u : 0u;
+      lo = toggle32(lo, x.y, s);
+      if (kRows64) hi = toggle32(hi, x.z, s);
+    }
+    wave_sync_lds();
+    // lanes 0-31 hold p's columns, lanes 32-63 q's: bring q's beside p's
+    const uint32_t qlo = (uint32_t)__shfl_xor((int)lo, 32, kWave);
+    const uint32_t qhi = kRows64 ? (uint32_t)__shfl_xor((int)hi, 32, kWave) : 0u;
+    if (lane < tw) n = (uint32_t)__popc(lo & qlo) + (kRows64 ? (uint32_t)__popc(hi & qhi) : 0u);
+  } else {
+    wave_sync_lds();
+    uint32_t plo = 0, phi = 0, qlo = 0, qhi = 0;
+#pragma unroll 4
+    for (int k = 0; k < np; ++k) {
+      const uint4 x = ep[k];
+      const uint32_t s = (uint32_t)lane < x.x ? ~0u : 0u;
+      plo = toggle32(plo, x.y, s);
+      if (kRows64) phi = toggle32(phi, x.z, s);
+    }
+#pragma unroll 4
+    for (int k = 0; k < nq; ++k) {
+      const uint4 x = eq[k];
+      const uint32_t s = (uint32_t)lane < x.x ? ~0u : 0u;
+      qlo = toggle32(qlo, x.y, s);
+      if (kRows64) qhi = toggle32(qhi, x.z, s);
+    }
+    wave_sync_lds();
+    if (lane < tw) n = (uint32_t)__popc(plo & qlo) + (kRows64 ? (uint32_t)__popc(phi & qhi) : 0u);
+  }
+  if (a.stats_on) {
+    c.st_leaf += 1;
+    c.st_leaf_tests += 2ull * (unsigned long long)tw * th;
+  }
+  return (int64_t)wave_sum_u32(n);
 }
 
 // Pixels of the tile [tx0, tx0+tw) x [ty0, ty0+th) inside both polygons.
@@ -468,26 +675,26 @@ __device__ __forceinline__ PairInfo heavy_info(const BatchArgs& a, int64_t hidx)
 
 // A pair from the sweep: MBRs and areas from its own rings, then one leaf
 // tile, or the large path kept entirely by this wave.
-__device__ __forceinline__ void run_pair(Ctx& c, int64_t i) {
+__device__ __forceinline__ void run_pair(Ctx& c, int64_t i, int64_t op, int64_t np, int64_t oq, int64_t nq) {
   const BatchArgs& a = *c.a;
   PairInfo pi;
   pi.pair = i;
   pi.hidx = -1;
-  const int64_t ia = a.pa[i], ib = a.pb[i];
-  pi.op = a.A.off[ia];
-  pi.np = a.A.off[ia + 1] - pi.op;
-  pi.oq = a.B.off[ib];
-  pi.nq = a.B.off[ib + 1] - pi.oq;
+  pi.op = op;
+  pi.np = np;
+  pi.oq = oq;
+  pi.nq = nq;
   Meta mp, mq;
   int64_t ap, aq;
-  ring_scan(a.A.xy, pi.op, pi.np, c.lane, mp, ap);
-  ring_scan(a.B.xy, pi.oq, pi.nq, c.lane, mq, aq);
+  RingRegs rp, rq;
+  ring_extent(a.A.xy, pi.op, pi.np, c.lane, rp, mp, ap);
+  ring_extent(a.B.xy, pi.oq, pi.nq, c.lane, rq, mq, aq);
   if (c.lane == 0 && (coords_bad(mp, pi.np) || coords_bad(mq, pi.nq))) latch_error(a.err, kErrCoord);
   if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[12], (unsigned long long)(pi.np + pi.nq));
   pi.area_sum = ap + aq;
   pi.box = pair_box(mp, mq);
   const int w = pi.box.x1 - pi.box.x0, h = pi.box.y1 - pi.box.y0;
-  uint64_t I = 0;
+  int64_t I = 0;
   int64_t U = pi.area_sum;
   if (pi.box.x0 >= pi.box.x1 || pi.box.y0 >= pi.box.y1) {
     // empty pair box: nothing in common
@@ -497,25 +704,37 @@ __device__ __forceinline__ void run_pair(Ctx& c, int64_t i) {
     if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
     U = 0;
   } else if (w <= kTile && h <= kTile) {
-    I = leaf_count(c, pi, pi.box.x0, pi.box.y0, w, h, false, false);
+    I = h > 32 ? leaf_small<true>(c, pi, rp, rq, w, h) : leaf_small<false>(c, pi, rp, rq, w, h);
+    if (I < 0) I = leaf_count(c, pi, pi.box.x0, pi.box.y0, w, h, false, false);
     if (a.stats_on && c.lane == 0) {
       atomicAdd(&a.st->stats[5], 1ull);
       atomicAdd(&a.st->stats[11], (unsigned long long)w * h);
     }
   } else {
-    I = run_large(c, pi);
+    I = (int64_t)run_large(c, pi);
     if (a.stats_on && c.lane == 0) {
       atomicAdd(&a.st->stats[6], 1ull);
       atomicAdd(&a.st->stats[11], (unsigned long long)w * h);
     }
   }
   if (c.lane == 0) {
-    a.inter[i] = (int64_t)I;
-    a.uni[i] = U - (int64_t)I;
+    a.inter[i] = I;
+    a.uni[i] = U - I;
   }
 }
 
-__global__ void __launch_bounds__(512) k_batch_run(BatchArgs args) {
+// Occupancy target of the persistent kernel (waves per SIMD); 0 leaves the
+// register budget to the compiler.  A build-time tuning knob.
+#ifndef SCCG_RUN_WAVES_PER_EU
+#define SCCG_RUN_WAVES_PER_EU 4
+#endif
+#if SCCG_RUN_WAVES_PER_EU > 0
+#define SCCG_RUN_ATTR __attribute__((amdgpu_waves_per_eu(SCCG_RUN_WAVES_PER_EU)))
+#else
+#define SCCG_RUN_ATTR
+#endif
+
+__global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wave = threadIdx.x / kWave;
   Ctx c;
@@ -523,6 +742,7 @@ __global__ void __launch_bounds__(512) k_batch_run(BatchArgs args) {
   c.lane = lane_id();
   c.edges = reinterpret_cast<uint4*>(smem + (size_t)wave * kLdsPerWave);
   c.local = reinterpret_cast<uint64_t*>(smem + (size_t)wave * kLdsPerWave + kLeafCap * 16);
+  c.meta = reinterpret_cast<ChunkMeta*>(smem + (size_t)wave * kLdsPerWave + kLeafCap * 16 + kLocalCap * 8);
   c.lsp = 0;
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
@@ -586,10 +806,28 @@ __global__ void __launch_bounds__(512) k_batch_run(BatchArgs args) {
       k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
       const unsigned long long g = k * kStreams + st;
       if (g < n_chunks) {
+        // one lane per pair of the chunk fetches its class, indices and ring offsets
         const int64_t i0 = (int64_t)g * a.chunk;
-        const int64_t i1 = min(i0 + a.chunk, a.n_pairs);
-        for (int64_t i = i0; i < i1; ++i)
-          if (a.cls[i] == kClsSweep) run_pair(c, i);
+        const int cnt = (int)min((int64_t)a.chunk, a.n_pairs - i0);
+        if (c.lane < cnt) {
+          const int64_t i = i0 + c.lane;
+          ChunkMeta m{0, 0, 0, 0, a.cls[i], 0};
+          if (m.cls == kClsSweep) {
+            const int64_t ia = a.pa[i], ib = a.pb[i];
+            m.op = a.A.off[ia];
+            m.np = (int32_t)(a.A.off[ia + 1] - m.op);
+            m.oq = a.B.off[ib];
+            m.nq = (int32_t)(a.B.off[ib + 1] - m.oq);
+          }
+          c.meta[c.lane] = m;
+        }
+        wave_sync_lds();
+        for (int j = 0; j < cnt; ++j) {
+          const ChunkMeta m = c.meta[j];
+          if (uniform(m.cls) != kClsSweep) continue;
+          run_pair(c, i0 + j, uniform64(m.op), uniform(m.np), uniform64(m.oq), uniform(m.nq));
+        }
+        wave_sync_lds();
         worked = true;
       } else {
         s_empty |= 1u << st;

@@ -91,8 +91,8 @@ int resolve_params(sccg_ctx* c, const sccg_params* in, sccg_params* out) {
   if (p.box_threshold == 0) p.box_threshold = p.wg_size * p.wg_size / 2;
   if (p.box_threshold < 2 || p.box_threshold > (1 << 30))
     return fail(c, SCCG_E_ARG, "box_threshold %d outside [2, 2^30]", p.box_threshold);
-  if (p.queue_chunk == 0) p.queue_chunk = 32;
-  if (p.queue_chunk < 1 || p.queue_chunk > 4096) return fail(c, SCCG_E_ARG, "queue_chunk outside [1, 4096]");
+  if (p.queue_chunk == 0) p.queue_chunk = 16;
+  if (p.queue_chunk < 1 || p.queue_chunk > 64) return fail(c, SCCG_E_ARG, "queue_chunk outside [1, 64]");
   if (p.lds_vertex_cap == 0) p.lds_vertex_cap = 1024;
   if (p.lds_vertex_cap < 1 || p.lds_vertex_cap > 4096)
     return fail(c, SCCG_E_ARG, "lds_vertex_cap outside [1, 4096]");

@@ -148,7 +148,7 @@ def test_plain_tuning_invariance(wl3s, params):
 BATCH_TUNINGS = [
     dict(queue_cap=1), dict(queue_cap=3, min_queue_cells=1), dict(min_queue_cells=1), dict(min_queue_cells=65),
     dict(flags=sccg.SCCG_F_NO_SPLIT_QUEUE), dict(flags=sccg.SCCG_F_NO_KNOWN_INSIDE),
-    dict(flags=sccg.SCCG_F_NO_LPT), dict(flags=sccg.SCCG_F_NO_GRAPH), dict(queue_chunk=1), dict(queue_chunk=333),
+    dict(flags=sccg.SCCG_F_NO_LPT), dict(flags=sccg.SCCG_F_NO_GRAPH), dict(queue_chunk=1), dict(queue_chunk=64), dict(queue_chunk=37),
     dict(waves_per_wg=1), dict(waves_per_wg=8), dict(n_queues=1), dict(grid=3), dict(heavy_verts=1),
     dict(heavy_verts=1, min_queue_cells=1, queue_cap=50), dict(heavy_verts=100000),
 ]
