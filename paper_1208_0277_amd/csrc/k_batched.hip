@@ -108,9 +108,12 @@ struct Ctx {
   int lsp;          // inline stack depth (wave-uniform)
   int home;         // preferred queue
   int xcd;          // first claim stream (the workgroup's XCD under round-robin dispatch)
-  unsigned long long st_leaf_tests, st_leaf, st_split, st_queued, st_kept;
-  unsigned long long st_edge_updates, st_class_edges, st_stage_edges;
 };
+
+// Work counters (only with sccg_set_stats): one atomic per event from lane 0.
+__device__ __forceinline__ void stat_add(const Ctx& c, int k, unsigned long long v) {
+  if (c.a->stats_on && c.lane == 0 && v) atomicAdd(&c.a->st->stats[k], v);
+}
 
 // What a wave needs to work on one pair.
 struct PairInfo {
@@ -120,6 +123,21 @@ struct PairInfo {
   Meta box;
   int64_t area_sum;  // |p| + |q|
 };
+
+// PairInfo fields are wave-uniform: keep them in scalar registers.
+__device__ __forceinline__ void make_uniform(PairInfo& pi) {
+  pi.pair = uniform64(pi.pair);
+  pi.hidx = uniform64(pi.hidx);
+  pi.op = uniform64(pi.op);
+  pi.np = uniform64(pi.np);
+  pi.oq = uniform64(pi.oq);
+  pi.nq = uniform64(pi.nq);
+  pi.box.x0 = uniform(pi.box.x0);
+  pi.box.y0 = uniform(pi.box.y0);
+  pi.box.x1 = uniform(pi.box.x1);
+  pi.box.y1 = uniform(pi.box.y1);
+  pi.area_sum = uniform64(pi.area_sum);
+}
 
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -164,9 +182,9 @@ __device__ __forceinline__ int2 lane_value(int2 v, int l) {
 // each vertex's successor comes from the neighbouring lane, lane 63's from
 // the next chunk, and the last vertex's is vertex 0.
 __device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int64_t nv, int lane, RingRegs& r,
-                                           int2& first) {
+                                           int2& first, const int2* pre) {
   const int64_t k0 = lane, k1 = lane + kWave;
-  r.v0 = k0 < nv ? xy[o + k0] : make_int2(0, 0);
+  r.v0 = pre ? *pre : (k0 < nv ? xy[o + k0] : make_int2(0, 0));
   r.v1 = k1 < nv ? xy[o + k1] : make_int2(0, 0);
   first = lane_value(r.v0, 0);
   const int2 a64 = nv > kWave ? lane_value(r.v1, 0) : first;
@@ -190,12 +208,12 @@ __device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int64_t nv
 // rescanned in 32/64-bit.  Empty rings and rings with |coordinate| > 2^30
 // come back empty.
 __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t nv, int lane, RingRegs& r, Meta& m,
-                                            int64_t& area) {
+                                            int64_t& area, const int2* pre = nullptr) {
   int2 first;
-  load_ring2(xy, o, nv, lane, r, first);
+  load_ring2(xy, o, nv, lane, r, first, pre);
   uint32_t pmin = 0x7fff7fffu, pmax = 0x80008000u, twice = 0u, wide = 0u;
-  for (int64_t base = 0; base < nv; base += kWave) {
-    const int64_t k = base + lane;
+  for (int base = 0; base < (int)nv; base += kWave) {
+    const int k = base + lane;
     int2 v, w;
     if (base == 0) {
       v = r.v0;
@@ -228,8 +246,8 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
   } else {
     int32_t x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
     uint64_t tw = 0;
-    for (int64_t base = 0; base < nv; base += kWave) {
-      const int64_t k = base + lane;
+    for (int base = 0; base < (int)nv; base += kWave) {
+      const int k = base + lane;
       int2 v, w;
       load_edge(xy, o, nv, k, v, w);
       if (k < nv) {
@@ -305,8 +323,8 @@ __device__ __forceinline__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o
                                                int th) {
   const int lane = c.lane;
   uint64_t m = 0;
-  int cnt = 0;
-  for (int64_t base = 0; base < nv; base += kWave) {
+  int cnt = 0, nk_total = 0;
+  for (int base = 0; base < (int)nv; base += kWave) {
     int2 v, w;
     load_edge(xy, o, nv, base + lane, v, w);
     uint32_t xr = 0;
@@ -320,10 +338,13 @@ __device__ __forceinline__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o
     }
     if (keep) c.edges[cnt + lanes_below(b)] = make_uint4(xr, (uint32_t)rr, (uint32_t)(rr >> 32), 0u);
     cnt += nk;
-    if (c.a->stats_on) c.st_edge_updates += nk;
+    nk_total += nk;
   }
   if (cnt > 0) flush_edges(c.edges, cnt, lane, m);
-  if (c.a->stats_on) c.st_stage_edges += (unsigned long long)nv;
+  if (c.a->stats_on) {
+    stat_add(c, 8, (unsigned long long)nk_total);
+    stat_add(c, 10, (unsigned long long)nv);
+  }
   return m;
 }
 
@@ -334,7 +355,7 @@ __device__ __forceinline__ int stage_small(Ctx& c, const int2* xy, int64_t o, in
                                            int tx0, int ty0, int th, uint4* e, int cap) {
   const int lane = c.lane;
   int cnt = 0;
-  for (int64_t base = 0; base < nv; base += kWave) {
+  for (int base = 0; base < (int)nv; base += kWave) {
     int2 v, w;
     if (base == 0) {
       v = r.v0;
@@ -355,8 +376,8 @@ __device__ __forceinline__ int stage_small(Ctx& c, const int2* xy, int64_t o, in
     cnt += nk;
   }
   if (c.a->stats_on) {
-    c.st_edge_updates += cnt;
-    c.st_stage_edges += (unsigned long long)nv;
+    stat_add(c, 8, (unsigned long long)cnt);
+    stat_add(c, 10, (unsigned long long)nv);
   }
   return cnt;
 }
@@ -421,8 +442,8 @@ __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const 
     if (lane < tw) n = (uint32_t)__popc(plo & qlo) + (kRows64 ? (uint32_t)__popc(phi & qhi) : 0u);
   }
   if (a.stats_on) {
-    c.st_leaf += 1;
-    c.st_leaf_tests += 2ull * (unsigned long long)tw * th;
+    stat_add(c, 1, 1ull);
+    stat_add(c, 0, 2ull * (unsigned long long)tw * th);
   }
   return (int64_t)wave_sum_u32(n);
 }
@@ -435,8 +456,8 @@ __device__ __forceinline__ uint32_t leaf_count(Ctx& c, const PairInfo& pi, int t
   const uint64_t mq = kq ? full : leaf_masks(c, a.B.xy, pi.oq, pi.nq, tx0, ty0, th);
   const uint32_t n = (c.lane < tw) ? (uint32_t)__popcll(mp & mq) : 0u;
   if (a.stats_on) {
-    c.st_leaf += 1;
-    c.st_leaf_tests += (unsigned long long)tw * th * ((kp ? 0 : 1) + (kq ? 0 : 1));
+    stat_add(c, 1, 1ull);
+    stat_add(c, 0, (unsigned long long)tw * th * ((kp ? 0 : 1) + (kq ? 0 : 1)));
   }
   return wave_sum_u32(n);
 }
@@ -447,8 +468,8 @@ __device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int6
                          int gx, int gy, uint64_t& H, uint64_t& P) {
   const int S = 1 << ls;
   uint64_t h = 0, p = 0;
-  for (int64_t base = 0; base < nv; base += kWave) {
-    const int64_t k = base + c.lane;
+  for (int base = 0; base < (int)nv; base += kWave) {
+    const int k = base + c.lane;
     if (k >= nv) break;
     const int2 v = xy[o + k];
     const int2 w = xy[o + (k + 1 == nv ? 0 : k + 1)];
@@ -482,7 +503,7 @@ __device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int6
   }
   H = wave_or64(h);
   P = wave_xor64(p);
-  if (c.a->stats_on) c.st_class_edges += (unsigned long long)nv;
+  stat_add(c, 9, (unsigned long long)nv);
 }
 
 __device__ __forceinline__ void add_counts(const BatchArgs& a, int64_t pair, uint64_t n) {
@@ -563,8 +584,8 @@ __device__ __forceinline__ void emit_children(Ctx& c, const PairInfo& pi, uint64
     }
     if (a.stats_on) {
       const int kept = __popcll(ballot(keep));
-      c.st_queued += n - kept;
-      c.st_kept += kept;
+      stat_add(c, 3, (unsigned long long)(n - kept));
+      stat_add(c, 4, (unsigned long long)kept);
     }
   }
   const uint64_t bk = ballot(keep);
@@ -606,7 +627,7 @@ __device__ __forceinline__ void split_box(Ctx& c, const PairInfo& pi, int bx0, i
     }
     acc += add;
   }
-  if (a.stats_on) c.st_split += 1;
+  stat_add(c, 2, 1ull);
   // one lane per continuing cell
   const int n = __popcll(cont);
   bool has = false;
@@ -646,17 +667,26 @@ __device__ __forceinline__ void drain_local(Ctx& c, const PairInfo& pi, uint64_t
   }
 }
 
-// The whole of a pair whose box is larger than one tile: the root split and
-// every box this wave keeps.  Returns the intersection it counted.
-__device__ __forceinline__ uint64_t run_large(Ctx& c, const PairInfo& pi) {
-  const int w = pi.box.x1 - pi.box.x0, h = pi.box.y1 - pi.box.y0;
-  const int side = max(w, h);
-  int cl = 0;
-  while ((kTile << (3 * cl)) * kMaxGrid < side) ++cl;
+// The large path for one pair: `task` (a root box, a queued box or a leaf
+// tile) goes on the wave's box stack and the stack is drained.  Every large
+// box of the kernel goes through this one site.  Returns the intersection
+// counted.
+__device__ __forceinline__ uint64_t run_large(Ctx& c, const PairInfo& pi, uint64_t task) {
+  c.local[c.lsp] = task;
+  c.lsp += 1;
+  wave_sync_lds();
   uint64_t acc = 0;
-  split_box(c, pi, pi.box.x0, pi.box.y0, pi.box.x1, pi.box.y1, cl, false, false, acc);
   drain_local(c, pi, acc);
   return acc;
+}
+
+// The task word of a whole pair box: a cell of the first level whose side
+// covers the box, at the pair-box origin.
+__device__ __forceinline__ uint64_t root_task(const PairInfo& pi) {
+  const int side = max(pi.box.x1 - pi.box.x0, pi.box.y1 - pi.box.y0);
+  int cl = 0;
+  while ((kTile << (3 * cl)) < side) ++cl;
+  return task_word(pi.hidx < 0 ? 0 : pi.hidx, cl, 0, 0, false, false);
 }
 
 __device__ __forceinline__ PairInfo heavy_info(const BatchArgs& a, int64_t hidx) {
@@ -670,57 +700,8 @@ __device__ __forceinline__ PairInfo heavy_info(const BatchArgs& a, int64_t hidx)
   pi.nq = a.B.off[ib + 1] - pi.oq;
   pi.box = load_meta(a.hbox, hidx);
   pi.area_sum = 0;
+  make_uniform(pi);
   return pi;
-}
-
-// A pair from the sweep: MBRs and areas from its own rings, then one leaf
-// tile, or the large path kept entirely by this wave.
-__device__ __forceinline__ void run_pair(Ctx& c, int64_t i, int64_t op, int64_t np, int64_t oq, int64_t nq) {
-  const BatchArgs& a = *c.a;
-  PairInfo pi;
-  pi.pair = i;
-  pi.hidx = -1;
-  pi.op = op;
-  pi.np = np;
-  pi.oq = oq;
-  pi.nq = nq;
-  Meta mp, mq;
-  int64_t ap, aq;
-  RingRegs rp, rq;
-  ring_extent(a.A.xy, pi.op, pi.np, c.lane, rp, mp, ap);
-  ring_extent(a.B.xy, pi.oq, pi.nq, c.lane, rq, mq, aq);
-  if (c.lane == 0 && (coords_bad(mp, pi.np) || coords_bad(mq, pi.nq))) latch_error(a.err, kErrCoord);
-  if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[12], (unsigned long long)(pi.np + pi.nq));
-  pi.area_sum = ap + aq;
-  pi.box = pair_box(mp, mq);
-  const int w = pi.box.x1 - pi.box.x0, h = pi.box.y1 - pi.box.y0;
-  int64_t I = 0;
-  int64_t U = pi.area_sum;
-  if (pi.box.x0 >= pi.box.x1 || pi.box.y0 >= pi.box.y1) {
-    // empty pair box: nothing in common
-    if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
-  } else if (w > kMaxSide || h > kMaxSide) {
-    if (c.lane == 0) latch_error(a.err, kErrSide);
-    if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
-    U = 0;
-  } else if (w <= kTile && h <= kTile) {
-    I = h > 32 ? leaf_small<true>(c, pi, rp, rq, w, h) : leaf_small<false>(c, pi, rp, rq, w, h);
-    if (I < 0) I = leaf_count(c, pi, pi.box.x0, pi.box.y0, w, h, false, false);
-    if (a.stats_on && c.lane == 0) {
-      atomicAdd(&a.st->stats[5], 1ull);
-      atomicAdd(&a.st->stats[11], (unsigned long long)w * h);
-    }
-  } else {
-    I = (int64_t)run_large(c, pi);
-    if (a.stats_on && c.lane == 0) {
-      atomicAdd(&a.st->stats[6], 1ull);
-      atomicAdd(&a.st->stats[11], (unsigned long long)w * h);
-    }
-  }
-  if (c.lane == 0) {
-    a.inter[i] = I;
-    a.uni[i] = U - I;
-  }
 }
 
 // Occupancy target of the persistent kernel (waves per SIMD); 0 leaves the
@@ -746,115 +727,172 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   c.lsp = 0;
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
-  c.st_leaf_tests = c.st_leaf = c.st_split = c.st_queued = c.st_kept = 0;
-  c.st_edge_updates = c.st_class_edges = c.st_stage_edges = 0;
   const BatchArgs& a = args;
   const unsigned long long n_heavy = a.st->l_count.v;
   const unsigned long long n_chunks = ((unsigned long long)a.n_pairs + a.chunk - 1) / a.chunk;
   uint32_t l_empty = 0, s_empty = 0;  // streams this wave found exhausted (wave-uniform)
+  int64_t ch_i0 = 0;                  // the sweep chunk in hand: pairs ch_i0 + [ch_j, ch_cnt)
+  int ch_cnt = 0, ch_j = 0;
+  int pf_j = -1;                       // chunk index whose first vertices are in pf_vp, pf_vq
+  int2 pf_vp = make_int2(0, 0), pf_vq = make_int2(0, 0), cur_vp = pf_vp, cur_vq = pf_vq;
   for (;;) {
+    // ------------------------------------------------ pick one piece of work
+    PairInfo pi;
+    bool use_pf = false;  // cur_vp / cur_vq hold the pair's first vertices
+    uint64_t task = 0;    // large-path task word, 0 = go through the small-pair path first
+    bool shared = false;  // outputs are shared with other waves: add atomically
     uint64_t w;
+    bool have = false;
     if (queue_claim(c, false, &w)) {
-      const Task t = task_decode(w);
-      const PairInfo pi = heavy_info(a, t.hidx);
-      uint64_t acc = 0;
-      run_box(c, pi, w, acc);
-      drain_local(c, pi, acc);
-      if (c.lane == 0) add_counts(a, pi.pair, acc);
-      continue;
+      pi = heavy_info(a, task_decode(w).hidx);
+      task = w;
+      shared = have = true;
     }
-    bool worked = false;
     // heavy pairs first: a largest-first order over the pairs with most vertices
-    while (l_empty != 0xffu && !worked) {
+    while (!have && l_empty != 0xffu) {
       int st = c.xcd;
       while ((l_empty >> st) & 1u) st = (st + 1) % kStreams;
       unsigned long long k = 0;
       if (c.lane == 0) k = atomicAdd(&a.st->l_next[st].v, 1ull);
       k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
       const unsigned long long e = k * kStreams + st;
-      if (e < n_heavy) {
-        const PairInfo pi = heavy_info(a, (int64_t)e);
-        const unsigned long long area = (unsigned long long)(pi.box.x1 - pi.box.x0) * (pi.box.y1 - pi.box.y0);
-        if (a.cls[pi.pair] == kClsLarge) {
-          const uint64_t acc = run_large(c, pi);
-          if (c.lane == 0) add_counts(a, pi.pair, acc);
-          if (a.stats_on && c.lane == 0) {
-            atomicAdd(&a.st->stats[6], 1ull);
-            atomicAdd(&a.st->stats[11], area);
-          }
-        } else if (a.cls[pi.pair] == kClsSmall) {
-          const int bw = pi.box.x1 - pi.box.x0, bh = pi.box.y1 - pi.box.y0;
-          const uint32_t n = leaf_count(c, pi, pi.box.x0, pi.box.y0, bw, bh, false, false);
-          if (c.lane == 0) add_counts(a, pi.pair, n);
-          if (a.stats_on && c.lane == 0) {
-            atomicAdd(&a.st->stats[5], 1ull);
-            atomicAdd(&a.st->stats[11], area);
-          }
-        }
-        worked = true;
-      } else {
+      if (e >= n_heavy) {
         l_empty |= 1u << st;
+        continue;
+      }
+      pi = heavy_info(a, (int64_t)e);
+      const uint8_t cls = a.cls[pi.pair];
+      if (cls == kClsDone) continue;  // settled by the prepass
+      shared = have = true;
+      if (cls == kClsLarge) {
+        task = root_task(pi);
+        if (a.stats_on && c.lane == 0) {
+          atomicAdd(&a.st->stats[6], 1ull);
+          atomicAdd(&a.st->stats[11], (unsigned long long)(pi.box.x1 - pi.box.x0) * (pi.box.y1 - pi.box.y0));
+        }
       }
     }
-    if (worked) continue;
-    // chunks of the other pairs, in index order
-    while (s_empty != 0xffu && !worked) {
-      int st = c.xcd;
-      while ((s_empty >> st) & 1u) st = (st + 1) % kStreams;
-      unsigned long long k = 0;
-      if (c.lane == 0) k = atomicAdd(&a.st->s_next[st].v, 1ull);
-      k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
-      const unsigned long long g = k * kStreams + st;
-      if (g < n_chunks) {
-        // one lane per pair of the chunk fetches its class, indices and ring offsets
-        const int64_t i0 = (int64_t)g * a.chunk;
-        const int cnt = (int)min((int64_t)a.chunk, a.n_pairs - i0);
-        if (c.lane < cnt) {
-          const int64_t i = i0 + c.lane;
-          ChunkMeta m{0, 0, 0, 0, a.cls[i], 0};
-          if (m.cls == kClsSweep) {
-            const int64_t ia = a.pa[i], ib = a.pb[i];
-            m.op = a.A.off[ia];
-            m.np = (int32_t)(a.A.off[ia + 1] - m.op);
-            m.oq = a.B.off[ib];
-            m.nq = (int32_t)(a.B.off[ib + 1] - m.oq);
+    // then the sweep over the other pairs, a chunk at a time
+    while (!have) {
+      if (ch_j >= ch_cnt) {
+        bool got = false;
+        while (!got && s_empty != 0xffu) {
+          int st = c.xcd;
+          while ((s_empty >> st) & 1u) st = (st + 1) % kStreams;
+          unsigned long long k = 0;
+          if (c.lane == 0) k = atomicAdd(&a.st->s_next[st].v, 1ull);
+          k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
+          const unsigned long long g = k * kStreams + st;
+          if (g >= n_chunks) {
+            s_empty |= 1u << st;
+            continue;
           }
-          c.meta[c.lane] = m;
+          got = true;
+          pf_j = -1;
+          ch_i0 = (int64_t)g * a.chunk;
+          ch_cnt = (int)min((int64_t)a.chunk, a.n_pairs - ch_i0);
+          ch_j = 0;
+          // one lane per pair of the chunk fetches its class, indices and ring offsets
+          wave_sync_lds();
+          if (c.lane < ch_cnt) {
+            const int64_t i = ch_i0 + c.lane;
+            ChunkMeta m{0, 0, 0, 0, a.cls[i], 0};
+            if (m.cls == kClsSweep) {
+              const int64_t ia = a.pa[i], ib = a.pb[i];
+              m.op = a.A.off[ia];
+              m.np = (int32_t)(a.A.off[ia + 1] - m.op);
+              m.oq = a.B.off[ib];
+              m.nq = (int32_t)(a.B.off[ib + 1] - m.oq);
+            }
+            c.meta[c.lane] = m;
+          }
+          wave_sync_lds();
         }
-        wave_sync_lds();
-        for (int j = 0; j < cnt; ++j) {
-          const ChunkMeta m = c.meta[j];
-          if (uniform(m.cls) != kClsSweep) continue;
-          run_pair(c, i0 + j, uniform64(m.op), uniform(m.np), uniform64(m.oq), uniform(m.nq));
+        if (!got) break;
+      }
+      const ChunkMeta m = c.meta[ch_j];
+      const int j = ch_j++;
+      if (uniform(m.cls) != kClsSweep) continue;
+      pi.pair = ch_i0 + j;
+      pi.hidx = -1;
+      pi.op = uniform64(m.op);
+      pi.np = uniform(m.np);
+      pi.oq = uniform64(m.oq);
+      pi.nq = uniform(m.nq);
+      have = true;
+      // the first 64 vertices of both rings of this pair may already be in
+      // registers; start those of the next pair of the chunk
+      use_pf = pf_j == j;
+      if (use_pf) {
+        cur_vp = pf_vp;
+        cur_vq = pf_vq;
+      }
+      pf_j = -1;
+      if (ch_j < ch_cnt) {
+        const ChunkMeta m2 = c.meta[ch_j];
+        if (uniform(m2.cls) == kClsSweep) {
+          const int64_t op2 = uniform64(m2.op), oq2 = uniform64(m2.oq);
+          const int np2 = uniform(m2.np), nq2 = uniform(m2.nq);
+          pf_vp = c.lane < np2 ? a.A.xy[op2 + c.lane] : make_int2(0, 0);
+          pf_vq = c.lane < nq2 ? a.B.xy[oq2 + c.lane] : make_int2(0, 0);
+          pf_j = ch_j;
         }
-        wave_sync_lds();
-        worked = true;
-      } else {
-        s_empty |= 1u << st;
       }
     }
-    if (worked) continue;
     // nothing of its own left: help with every queue, then stop
-    if (queue_claim(c, true, &w)) {
-      const Task t = task_decode(w);
-      const PairInfo pi = heavy_info(a, t.hidx);
-      uint64_t acc = 0;
-      run_box(c, pi, w, acc);
-      drain_local(c, pi, acc);
-      if (c.lane == 0) add_counts(a, pi.pair, acc);
-      continue;
+    if (!have) {
+      if (!queue_claim(c, true, &w)) break;
+      pi = heavy_info(a, task_decode(w).hidx);
+      task = w;
+      shared = have = true;
     }
-    break;
-  }
-  if (a.stats_on && c.lane == 0) {
-    atomicAdd(&a.st->stats[0], c.st_leaf_tests);
-    atomicAdd(&a.st->stats[1], c.st_leaf);
-    atomicAdd(&a.st->stats[2], c.st_split);
-    atomicAdd(&a.st->stats[3], c.st_queued);
-    atomicAdd(&a.st->stats[4], c.st_kept);
-    atomicAdd(&a.st->stats[8], c.st_edge_updates);
-    atomicAdd(&a.st->stats[9], c.st_class_edges);
-    atomicAdd(&a.st->stats[10], c.st_stage_edges);
+
+    // ------------------------------------------------------ small-pair path
+    int64_t I = 0;
+    if (task == 0) {
+      // MBRs and areas from the pair's own rings, then the pair box
+      Meta mp, mq;
+      int64_t ap, aq;
+      RingRegs rp, rq;
+      ring_extent(a.A.xy, pi.op, pi.np, c.lane, rp, mp, ap, use_pf ? &cur_vp : nullptr);
+      ring_extent(a.B.xy, pi.oq, pi.nq, c.lane, rq, mq, aq, use_pf ? &cur_vq : nullptr);
+      if (c.lane == 0 && (coords_bad(mp, pi.np) || coords_bad(mq, pi.nq))) latch_error(a.err, kErrCoord);
+      if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[12], (unsigned long long)(pi.np + pi.nq));
+      pi.area_sum = ap + aq;
+      pi.box = pair_box(mp, mq);
+      const int bw = pi.box.x1 - pi.box.x0, bh = pi.box.y1 - pi.box.y0;
+      if (pi.box.x0 >= pi.box.x1 || pi.box.y0 >= pi.box.y1) {
+        // empty pair box: nothing in common
+        if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
+      } else if (bw > kMaxSide || bh > kMaxSide) {
+        if (c.lane == 0) latch_error(a.err, kErrSide);
+        if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
+        pi.area_sum = 0;
+      } else if (bw <= kTile && bh <= kTile) {
+        I = bh > 32 ? leaf_small<true>(c, pi, rp, rq, bw, bh) : leaf_small<false>(c, pi, rp, rq, bw, bh);
+        if (I < 0) task = task_word(0, 0, 0, 0, false, false);  // too many edges: the general leaf
+        if (a.stats_on && c.lane == 0) {
+          atomicAdd(&a.st->stats[5], 1ull);
+          atomicAdd(&a.st->stats[11], (unsigned long long)bw * bh);
+        }
+      } else {
+        task = root_task(pi);
+        if (a.stats_on && c.lane == 0) {
+          atomicAdd(&a.st->stats[6], 1ull);
+          atomicAdd(&a.st->stats[11], (unsigned long long)bw * bh);
+        }
+      }
+    }
+    // --------------------------------------------------------- large path
+    if (task != 0) I = (int64_t)run_large(c, pi, task);
+    if (c.lane == 0) {
+      if (shared) {
+        add_counts(a, pi.pair, (uint64_t)I);
+      } else {
+        a.inter[pi.pair] = I;
+        a.uni[pi.pair] = pi.area_sum - I;
+      }
+    }
   }
 }
 
