@@ -32,6 +32,9 @@ import numpy as np  # noqa: E402
 METRIC = "polygon pairs/sec and pixel-tests/sec, bit-exact; batched vs plain kernel"
 
 WORKLOADS = {
+    4: "set-level: 64 tiles of 8192^2 px, per tile set A packed with 10-60 px shapes and set B = 85% shifted "
+       "and dilated/eroded copies + 15% fresh shapes, candidate pairs from a 64-px grid MBR join; "
+       "step = pair counts + per-tile Jaccard",
     3: "heavy-tailed mix: 2,000,000 pairs, MBR side lognormal (median 24 px, clipped 8-400 px), "
        "1% merged blobs of 10-40 ellipses, one persistent launch",
     2: "uniform mix: 200,000 pairs of 10-60 px shapes (16-120 vertices) on 16384^2 tiles",
@@ -118,7 +121,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3])
+    ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3, 4])
+    ap.add_argument("--tiles", type=int, default=64, help="workload 4: number of tiles")
     ap.add_argument("--pairs", type=int, default=None, help="override the pair count (not the headline)")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -138,10 +142,16 @@ def main(argv=None):
     from paper_1208_0277_amd import autotune
 
     t0 = time.perf_counter()
-    n_pairs = args.pairs or sccg_gen.DEFAULT_PAIRS[args.workload]
-    wl = sccg_gen.pairs(args.workload, n_pairs)
-    log(f"generated workload {args.workload}: {wl.n_pairs} pairs, {len(wl.A.xy) + len(wl.B.xy)} vertices, "
-        f"{int(wl.blob.sum())} blobs in {time.perf_counter() - t0:.1f} s")
+    if args.workload == 4:
+        wl = sccg_gen.sets(n_tiles=args.tiles, tile_side=8192, cell=64)
+        log(f"generated workload 4: {args.tiles} tiles, {wl.A.n} + {wl.B.n} polygons, {wl.n_pairs} candidate "
+            f"pairs in {time.perf_counter() - t0:.1f} s")
+    else:
+        n_pairs = args.pairs or sccg_gen.DEFAULT_PAIRS[args.workload]
+        wl = sccg_gen.pairs(args.workload, n_pairs)
+        log(f"generated workload {args.workload}: {wl.n_pairs} pairs, {len(wl.A.xy) + len(wl.B.xy)} vertices, "
+            f"{int(wl.blob.sum())} blobs in {time.perf_counter() - t0:.1f} s")
+    with_sets = args.workload == 4
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
@@ -151,6 +161,7 @@ def main(argv=None):
     pb = torch.from_numpy(wl.pb).to(dev)
     I = torch.empty(wl.n_pairs, dtype=torch.int64, device=dev)
     U = torch.empty(wl.n_pairs, dtype=torch.int64, device=dev)
+    so = torch.from_numpy(wl.set_off).to(dev)
     torch.cuda.synchronize()
     ctx = sccg.Context(0, stream=stream)
     ctx.reserve(dA.n, dB.n, wl.n_pairs)
@@ -164,8 +175,12 @@ def main(argv=None):
                                   use_cache=False, log=log)
             log(f"autotuned batched parameters {tuned} in {time.perf_counter() - t:.1f} s")
 
+        sets_out = [None]
+
         def step():
             ctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=sccg.SCCG_BATCHED)
+            if with_sets:
+                sets_out[0] = ctx.jaccard_sets(so, I, U)
 
         for _ in range(args.warmup):
             step()
@@ -182,6 +197,7 @@ def main(argv=None):
         ms_per_step = (t_end - t_start) * 1e3 / args.steps
         value = wl.n_pairs / (ms_per_step / 1e3)
         gI, gU = I.cpu().numpy(), U.cpu().numpy()
+        gsets = [t.cpu().numpy() if t is not None else None for t in sets_out[0]] if with_sets else None
         log(f"batched: {ms_per_step:.3f} ms/step, {value / 1e6:.1f} Mpairs/s")
 
         # kernel duration of the persistent kernel: HIP events on its stream
@@ -236,9 +252,20 @@ def main(argv=None):
                 "hbm_frac_algorithmic": (algo_bytes / (k_avg_ms / 1e3)) / HBM_PEAK}
 
     cpu, exact_sample, n_sample = (None, None, 0)
+    sets_info = {}
     if not args.no_cpu:
         cpu, exact_sample, n_sample = cpu_baseline(wl, gI, gU, args.cpu_seconds, seed=1234)
         log(f"cpu oracle: {cpu['value']:.0f} pairs/s on {n_sample} pairs, bit-exact sample: {exact_sample}")
+        if with_sets and n_sample == wl.n_pairs:
+            import oracle
+            eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS)
+            osi, osu, onn, oj, ojp = oracle.jaccard_sets(wl.set_off, eI, eU)
+            sets_info["sets_bit_exact"] = bool(np.array_equal(gsets[0], osi) and np.array_equal(gsets[1], osu) and
+                                               np.array_equal(gsets[3], oj) and np.array_equal(gsets[4], ojp))
+    if with_sets:
+        sets_info.update({"n_sets": int(len(wl.set_off) - 1), "J_mean": float(np.mean(gsets[3])),
+                          "J_min": float(np.min(gsets[3])), "J_max": float(np.max(gsets[3])),
+                          "Jprime_mean": float(np.mean(gsets[4]))})
 
     out = {
         "metric": METRIC,
@@ -254,6 +281,7 @@ def main(argv=None):
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "n_pairs": wl.n_pairs, "seed": wl.seed,
+                   "n_tiles": args.tiles if with_sets else None,
                    "mode": "batched", "params": tuned, "parallelism": "none (1 GPU)"},
         "pixel_tests_per_s": st["leaf_pixel_tests"] / (ms_per_step / 1e3),
         "covered_pixels_per_s": st["covered_pixels"] / (ms_per_step / 1e3),
@@ -261,6 +289,7 @@ def main(argv=None):
         "bit_exact_oracle_sample": exact_sample,
         "oracle_sample_pairs": n_sample,
         "repeat_identical": bool(same),
+        **sets_info,
         "stats": st,
         "roofline": roofline,
         "cpu_baseline": cpu,

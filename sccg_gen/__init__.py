@@ -49,6 +49,11 @@ def _load():
     lib.sccg_gen_mask.restype = ctypes.c_int
     lib.sccg_gen_mask.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64]
+    lib.sccg_gen_sets_create.restype = ctypes.c_void_p
+    lib.sccg_gen_sets_create.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+    lib.sccg_gen_sets_free.argtypes = [ctypes.c_void_p]
+    lib.sccg_gen_sets_counts.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.sccg_gen_sets_copy.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 7
     lib.sccg_gen_trace_mask.restype = ctypes.c_int64
     lib.sccg_gen_trace_mask.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_int64]
@@ -144,6 +149,56 @@ def pairs(config: int, n_pairs: int | None = None, seed: int | None = None,
     stats = dict(tiles_used=int(c[6]), shapes_outside_vertex_range=int(c[7]), attempts=int(c[8]),
                  n_blobs=int(c[9]))
     return PairWorkload(config, seed, Polys(offA, xyA), Polys(offB, xyB), pa, pb, so, blob, stats, h)
+
+
+@dataclass
+class SetWorkload:
+    """Set-level workload: per tile, a result set A and a result set B of
+    polygons; candidate pairs from a uniform-grid MBR join, grouped by tile
+    (pairs set_off[t]:set_off[t+1] belong to tile t)."""
+    seed: int
+    A: Polys
+    B: Polys
+    pa: np.ndarray
+    pb: np.ndarray
+    set_off: np.ndarray
+    stats: dict
+
+    @property
+    def n_pairs(self) -> int:
+        return len(self.pa)
+
+
+def sets(n_tiles: int = 64, tile_side: int = 8192, cell: int = 64, seed: int | None = None,
+         threads: int | None = None) -> SetWorkload:
+    """Workload 4: n_tiles tiles of tile_side^2 px.  In each tile set A is
+    filled with workload-2 shapes (10-60 px, 16-120 vertices) by shelf packing
+    until the tile is full; set B holds a shifted, dilated or eroded copy of
+    85% of A's shapes plus 15% * |A| fresh shapes at uniform positions."""
+    lib = _load()
+    if seed is None:
+        seed = BASE_SEED + 4
+    if threads is None:
+        threads = min(16, os.cpu_count() or 1)
+    h = lib.sccg_gen_sets_create(seed, n_tiles, tile_side, cell, threads)
+    if not h:
+        raise ValueError("generator rejected the arguments")
+    try:
+        c = np.zeros(6, np.int64)
+        lib.sccg_gen_sets_counts(h, _ptr(c))
+        nA, vA, nB, vB, npairs, nt = (int(v) for v in c)
+        offA = np.zeros(nA + 1, np.int64)
+        xyA = np.zeros((vA, 2), np.int32)
+        offB = np.zeros(nB + 1, np.int64)
+        xyB = np.zeros((vB, 2), np.int32)
+        pa = np.zeros(npairs, np.int32)
+        pb = np.zeros(npairs, np.int32)
+        so = np.zeros(nt + 1, np.int64)
+        lib.sccg_gen_sets_copy(h, _ptr(offA), _ptr(xyA), _ptr(offB), _ptr(xyB), _ptr(pa), _ptr(pb), _ptr(so))
+    finally:
+        lib.sccg_gen_sets_free(h)
+    stats = dict(tiles=nt, polys_a=nA, polys_b=nB, pairs=npairs, tile_side=tile_side, cell=cell)
+    return SetWorkload(seed, Polys(offA, xyA), Polys(offB, xyB), pa, pb, so, stats)
 
 
 def trace_mask(bits: np.ndarray) -> np.ndarray | None:

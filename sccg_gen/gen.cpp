@@ -415,6 +415,138 @@ void gen_pairs(Dataset& D, int config, uint64_t seed, int64_t n, int n_threads, 
   D.set_off = {0, n};
 }
 
+
+// ------------------------------------------------------- set-level tiles ----
+// Workload 4: n_tiles square tiles; in each, set A is filled with
+// workload-2 shapes by shelf packing until the tile is full; set B holds, for
+// 85% of A's shapes (one draw per shape), a shifted and dilated or eroded
+// copy, plus 15% * |A| fresh shapes at uniform positions in the tile.
+// Candidate pairs come from a uniform-grid join of the MBRs (cell side
+// `cell`): a pair is emitted when the MBRs share at least one pixel, once, in
+// the cell that holds the lower-left pixel of their intersection.
+struct TileSets {
+  std::vector<Shape> A, B;
+  std::vector<int64_t> ax, ay, bx, by;
+  std::vector<int32_t> pa, pb;  // tile-local indices
+};
+
+void gen_tile(TileSets& T, uint64_t seed, int64_t tile, int64_t tile_side, int64_t ox, int64_t oy, int cell) {
+  const uint64_t base = (uint64_t)tile << 32;
+  // A: shelf packing, pad 1
+  int64_t cx = 0, cy = 0, shelf = 0;
+  for (int64_t k = 0;; ++k) {
+    Rng g(seed, base | (uint64_t)k);
+    bool blob = false;
+    ShapeSpec sp = spec_for(2, g, blob);
+    Shape A;
+    int used = 0;
+    make_shape(g, sp, A, &used);
+    if (A.ring.size() < 8) continue;
+    const int64_t w = A.mask.w + 2, h = A.mask.h + 2;
+    if (cx + w > tile_side) { cx = 0; cy += shelf; shelf = 0; }
+    if (cy + h > tile_side) break;
+    T.ax.push_back(ox + cx + 1);
+    T.ay.push_back(oy + cy + 1);
+    cx += w;
+    shelf = std::max(shelf, h);
+    // B derived from A with probability 0.85
+    Rng gb(seed ^ 0x5bd1e995ull, base | (uint64_t)k);
+    if (gb.unit() < 0.85) {
+      Shape B;
+      int bx = 0, by = 0;
+      if (derive_b(gb, A, B, bx, by)) {
+        T.bx.push_back(T.ax.back() + bx);
+        T.by.push_back(T.ay.back() + by);
+        B.mask = Mask();
+        T.B.push_back(std::move(B));
+      }
+    }
+    T.A.push_back(std::move(A));
+    T.A.back().mask.m.shrink_to_fit();
+  }
+  // unmatched B shapes at uniform positions
+  const int64_t n_fresh = (int64_t)std::llround(0.15 * (double)T.A.size());
+  for (int64_t k = 0; k < n_fresh; ++k) {
+    Rng g(seed ^ 0x9e3779b9ull, base | (uint64_t)k);
+    bool blob = false;
+    ShapeSpec sp = spec_for(2, g, blob);
+    Shape B;
+    int used = 0;
+    make_shape(g, sp, B, &used);
+    if (B.ring.size() < 8) continue;
+    const int64_t px = g.uni(0, tile_side - B.mask.w), py = g.uni(0, tile_side - B.mask.h);
+    T.bx.push_back(ox + px);
+    T.by.push_back(oy + py);
+    B.mask = Mask();
+    T.B.push_back(std::move(B));
+  }
+  for (auto& a : T.A) a.mask = Mask();
+  // MBRs (pixel extents) of both sets, tile-local cell grid
+  auto mbr = [](const Shape& S, int64_t gx, int64_t gy, int64_t* m) {
+    int64_t x0 = INT64_MAX, y0 = INT64_MAX, x1 = INT64_MIN, y1 = INT64_MIN;
+    for (size_t k = 0; k < S.ring.size(); k += 2) {
+      x0 = std::min<int64_t>(x0, S.ring[k] + gx);
+      x1 = std::max<int64_t>(x1, S.ring[k] + gx);
+      y0 = std::min<int64_t>(y0, S.ring[k + 1] + gy);
+      y1 = std::max<int64_t>(y1, S.ring[k + 1] + gy);
+    }
+    m[0] = x0; m[1] = y0; m[2] = x1; m[3] = y1;
+  };
+  const int64_t ncell = (tile_side + cell - 1) / cell + 2;  // B shapes may reach a little past the tile
+  std::vector<std::vector<int32_t>> grid((size_t)(ncell * ncell));
+  std::vector<int64_t> ma(4 * T.A.size());
+  auto cell_of = [&](int64_t v, int64_t o) { return std::min<int64_t>(ncell - 1, std::max<int64_t>(0, (v - o) / cell + 1)); };
+  for (size_t k = 0; k < T.A.size(); ++k) {
+    int64_t* m = &ma[4 * k];
+    mbr(T.A[k], T.ax[k], T.ay[k], m);
+    for (int64_t gy = cell_of(m[1], oy); gy <= cell_of(m[3] - 1, oy); ++gy)
+      for (int64_t gx = cell_of(m[0], ox); gx <= cell_of(m[2] - 1, ox); ++gx)
+        grid[(size_t)(gy * ncell + gx)].push_back((int32_t)k);
+  }
+  for (size_t k = 0; k < T.B.size(); ++k) {
+    int64_t mb[4];
+    mbr(T.B[k], T.bx[k], T.by[k], mb);
+    std::vector<int32_t> found;
+    for (int64_t gy = cell_of(mb[1], oy); gy <= cell_of(mb[3] - 1, oy); ++gy)
+      for (int64_t gx = cell_of(mb[0], ox); gx <= cell_of(mb[2] - 1, ox); ++gx)
+        for (int32_t a : grid[(size_t)(gy * ncell + gx)]) {
+          const int64_t* m = &ma[4 * (size_t)a];
+          const int64_t ix0 = std::max(m[0], mb[0]), iy0 = std::max(m[1], mb[1]);
+          const int64_t ix1 = std::min(m[2], mb[2]), iy1 = std::min(m[3], mb[3]);
+          if (ix0 >= ix1 || iy0 >= iy1) continue;
+          // reference point: emit only in the cell of the intersection's lower-left pixel
+          if (cell_of(ix0, ox) != gx || cell_of(iy0, oy) != gy) continue;
+          found.push_back(a);
+        }
+    std::sort(found.begin(), found.end());
+    for (int32_t a : found) {
+      T.pa.push_back(a);
+      T.pb.push_back((int32_t)k);
+    }
+  }
+}
+
+struct SetsDataset {
+  int64_t n_tiles = 0;
+  std::vector<TileSets> tiles;
+};
+
+void gen_sets(SetsDataset& D, uint64_t seed, int64_t n_tiles, int64_t tile_side, int cell, int n_threads) {
+  D.n_tiles = n_tiles;
+  D.tiles.resize((size_t)n_tiles);
+  std::atomic<int64_t> next{0};
+  auto worker = [&]() {
+    for (;;) {
+      const int64_t t = next.fetch_add(1);
+      if (t >= n_tiles) break;
+      gen_tile(D.tiles[(size_t)t], seed, t, tile_side, (t % 8) * tile_side, (t / 8) * tile_side, cell);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int k = 0; k < std::max(1, n_threads); ++k) th.emplace_back(worker);
+  for (auto& x : th) x.join();
+}
+
 }  // namespace
 
 // ============================================================== C ABI ====
@@ -514,6 +646,71 @@ int64_t sccg_gen_trace_mask(const uint8_t* bits, int w, int h, int32_t* xy, int6
   int64_t nv = (int64_t)ring.size() / 2;
   for (int64_t k = 0; k < std::min(nv, cap); ++k) { xy[2 * k] = ring[2 * k]; xy[2 * k + 1] = ring[2 * k + 1]; }
   return nv;
+}
+
+typedef struct sccg_gen_sets sccg_gen_sets;
+struct sccg_gen_sets { SetsDataset d; };
+
+// Set-level workload 4: n_tiles tiles of tile_side^2 pixels (8 tiles to a
+// row of tiles), candidate pairs from a uniform grid of `cell`-pixel cells.
+sccg_gen_sets* sccg_gen_sets_create(uint64_t seed, int64_t n_tiles, int64_t tile_side, int cell, int n_threads) {
+  if (n_tiles < 0 || tile_side < 64 || cell < 1) return nullptr;
+  sccg_gen_sets* h = new sccg_gen_sets();
+  gen_sets(h->d, seed, n_tiles, tile_side, cell, n_threads);
+  return h;
+}
+
+void sccg_gen_sets_free(sccg_gen_sets* h) { delete h; }
+
+// c[0..3] = polygons in A, vertices in A, polygons in B, vertices in B; c[4] = pairs; c[5] = tiles
+void sccg_gen_sets_counts(const sccg_gen_sets* h, int64_t* c) {
+  int64_t na = 0, va = 0, nb = 0, vb = 0, np = 0;
+  for (const auto& T : h->d.tiles) {
+    na += (int64_t)T.A.size();
+    nb += (int64_t)T.B.size();
+    for (auto& s : T.A) va += (int64_t)s.ring.size() / 2;
+    for (auto& s : T.B) vb += (int64_t)s.ring.size() / 2;
+    np += (int64_t)T.pa.size();
+  }
+  c[0] = na; c[1] = va; c[2] = nb; c[3] = vb; c[4] = np; c[5] = h->d.n_tiles;
+}
+
+// CSR rings of both sets (tiles concatenated in order), global pair indices
+// and the pair offsets of each tile (set_off[n_tiles+1]).
+void sccg_gen_sets_copy(const sccg_gen_sets* h, int64_t* offA, int32_t* xyA, int64_t* offB, int32_t* xyB, int32_t* pa,
+                        int32_t* pb, int64_t* set_off) {
+  int64_t ia = 0, ib = 0, va = 0, vb = 0, np = 0;
+  offA[0] = 0;
+  offB[0] = 0;
+  set_off[0] = 0;
+  for (size_t t = 0; t < h->d.tiles.size(); ++t) {
+    const TileSets& T = h->d.tiles[t];
+    const int64_t a0 = ia, b0 = ib;
+    for (size_t k = 0; k < T.A.size(); ++k) {
+      const auto& r = T.A[k].ring;
+      for (size_t j = 0; j < r.size(); j += 2) {
+        xyA[2 * va] = (int32_t)(r[j] + T.ax[k]);
+        xyA[2 * va + 1] = (int32_t)(r[j + 1] + T.ay[k]);
+        ++va;
+      }
+      offA[++ia] = va;
+    }
+    for (size_t k = 0; k < T.B.size(); ++k) {
+      const auto& r = T.B[k].ring;
+      for (size_t j = 0; j < r.size(); j += 2) {
+        xyB[2 * vb] = (int32_t)(r[j] + T.bx[k]);
+        xyB[2 * vb + 1] = (int32_t)(r[j + 1] + T.by[k]);
+        ++vb;
+      }
+      offB[++ib] = vb;
+    }
+    for (size_t k = 0; k < T.pa.size(); ++k) {
+      pa[np] = (int32_t)(a0 + T.pa[k]);
+      pb[np] = (int32_t)(b0 + T.pb[k]);
+      ++np;
+    }
+    set_off[t + 1] = np;
+  }
 }
 
 }  // extern "C"

@@ -313,3 +313,28 @@ def test_kernel_timing(wl3s):
         ms, n = c.get_timing()
         assert n == 2 and ms > 0
     c.close()
+
+
+@pytest.fixture(scope="module")
+def sets4():
+    wl = sccg_gen.sets(n_tiles=4, tile_side=2048, cell=64)
+    I, U = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS)
+    return wl, I, U
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_set_workload_tiles(ctx, sets4, mode):
+    """Workload 4 on four tiles: pair counts of the grid-join candidates and the
+    per-tile J and J' bit-identical to the oracle."""
+    import torch
+    wl, eI, eU = sets4
+    dwl = device_workload(wl.A, wl.B, wl.pa, wl.pb)
+    I, U = ctx.area_pairs(*dwl, mode=mode)
+    so = torch.from_numpy(wl.set_off).cuda()
+    si, su, nn, j, jp = ctx.jaccard_sets(so, I, U)
+    ctx.sync()
+    assert_exact(I.cpu().numpy(), U.cpu().numpy(), eI, eU, f"set workload mode {mode}")
+    osi, osu, onn, oj, ojp = oracle.jaccard_sets(wl.set_off, eI, eU)
+    assert np.array_equal(si.cpu().numpy(), osi) and np.array_equal(su.cpu().numpy(), osu)
+    assert np.array_equal(nn.cpu().numpy(), onn)
+    assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(jp.cpu().numpy(), ojp)

@@ -282,3 +282,32 @@ def test_jprime_exact_sum():
         exact = sum(Fraction(float(I[k]) / float(U[k])) for k in range(n))
         assert nn[0] == n
         assert jp[0] == float(exact) / n
+
+
+def test_set_workload_join_is_exact():
+    """Workload 4's candidate pairs are exactly the (A, B) pairs whose MBRs
+    share a pixel, each once (brute force over small tiles)."""
+    wl = sccg_gen.sets(n_tiles=2, tile_side=768, cell=64)
+
+    def mbrs(P):
+        m = np.zeros((P.n, 4), np.int64)
+        for k in range(P.n):
+            r = P.ring(k)
+            m[k] = (r[:, 0].min(), r[:, 1].min(), r[:, 0].max(), r[:, 1].max())
+        return m
+    ma, mb = mbrs(wl.A), mbrs(wl.B)
+    got = set(zip(wl.pa.tolist(), wl.pb.tolist()))
+    assert len(got) == wl.n_pairs  # no duplicates
+    a_ids = np.arange(len(ma))
+    by_b = {}
+    for (a, b) in got:
+        by_b.setdefault(b, set()).add(a)
+    for t in range(1):
+        for b in range(len(mb)):
+            x0 = np.maximum(ma[:, 0], mb[b, 0])
+            y0 = np.maximum(ma[:, 1], mb[b, 1])
+            x1 = np.minimum(ma[:, 2], mb[b, 2])
+            y1 = np.minimum(ma[:, 3], mb[b, 3])
+            hit = set(a_ids[(x0 < x1) & (y0 < y1)].tolist())
+            assert hit == by_b.get(b, set()), b
+    assert wl.stats["polys_a"] > 0 and wl.n_pairs > 0
