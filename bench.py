@@ -32,6 +32,8 @@ import numpy as np  # noqa: E402
 METRIC = "polygon pairs/sec and pixel-tests/sec, bit-exact; batched vs plain kernel"
 
 WORKLOADS = {
+    5: "serving: Poisson job arrivals at 5, 20 and 80 jobs/s, 600 jobs per rate (first 20 not measured), "
+       "each job a window of 1e3-5e5 pairs (log-uniform) of a pinned 500,000-pair uniform-mix corpus",
     4: "set-level: 64 tiles of 8192^2 px, per tile set A packed with 10-60 px shapes and set B = 85% shifted "
        "and dilated/eroded copies + 15% fresh shapes, candidate pairs from a 64-px grid MBR join; "
        "step = pair counts + per-tile Jaccard",
@@ -116,17 +118,132 @@ def cpu_baseline(wl, I_gpu, U_gpu, seconds: float, seed: int):
                       f"oracle form, {t_total:.1f} s of CPU time"}, exact, done
 
 
+def serve_bench(args):
+    """Continuous-batching server under Poisson arrivals; latency is submit
+    to results on the host (the server's clock).  Every job is checked
+    against the oracle's counts of the corpus."""
+    import math
+    import threading
+
+    import torch
+
+    import oracle
+    import paper_1208_0277_amd as sccg
+    import sccg_gen
+
+    rates = [float(r) for r in args.rates.split(",")]
+    corpus_n = 500_000
+    t0 = time.perf_counter()
+    wl = sccg_gen.pairs(2, corpus_n, seed=sccg_gen.BASE_SEED + 5)
+    a_xy = torch.empty(wl.A.xy.size, dtype=torch.int32, pin_memory=True).numpy()
+    b_xy = torch.empty(wl.B.xy.size, dtype=torch.int32, pin_memory=True).numpy()
+    a_xy[:] = wl.A.xy.reshape(-1)
+    b_xy[:] = wl.B.xy.reshape(-1)
+    eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS, threads=min(os.cpu_count() or 1, 16))
+    log(f"corpus: {corpus_n} pairs, {len(wl.A.xy) + len(wl.B.xy)} vertices (pinned), oracle counts in "
+        f"{time.perf_counter() - t0:.1f} s")
+    local = np.arange(5 * 10 ** 5, dtype=np.int32)
+    srv = sccg.Server(0)
+    rng = np.random.default_rng(sccg_gen.BASE_SEED + 5)
+    out_rates, all_exact = [], True
+    try:
+        # warm-up: one job through every stage
+        srv.submit(wl.A.off[:1001], a_xy, wl.B.off[:1001], b_xy, local[:1000], local[:1000])
+        if not srv.poll(1, timeout=60.0):
+            raise RuntimeError("warm-up job did not finish")
+        for lam in rates:
+            n_jobs = args.jobs
+            sizes = np.exp(rng.uniform(math.log(1e3), math.log(5e5), n_jobs)).astype(np.int64)
+            starts = rng.integers(0, corpus_n - sizes + 1)
+            arrive = np.cumsum(rng.exponential(1.0 / lam, n_jobs))
+            outs, errors = {}, []
+            lock = threading.Lock()
+
+            def submitter():
+                t_start = time.perf_counter()
+                for k in range(n_jobs):
+                    delay = t_start + arrive[k] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                    s, n = int(starts[k]), int(sizes[k])
+                    oi, ou = np.empty(n, np.int64), np.empty(n, np.int64)
+                    with lock:  # the job may finish before submit returns
+                        try:
+                            j = srv.submit(wl.A.off[s:s + n + 1], a_xy, wl.B.off[s:s + n + 1], b_xy, local[:n],
+                                           local[:n], out_inter=oi, out_union=ou)
+                        except Exception as e:  # reported after the run
+                            errors.append(repr(e))
+                            return
+                        outs[j] = (k, oi, ou)
+
+            th = threading.Thread(target=submitter)
+            st0 = srv.stats()
+            th.start()
+            results, exact = {}, True
+            deadline = time.perf_counter() + arrive[-1] + 120.0
+            while len(results) < n_jobs and time.perf_counter() < deadline and not errors:
+                for r in srv.poll(256, timeout=1.0):
+                    with lock:
+                        k, oi, ou = outs.pop(r["job_id"])
+                    s, n = int(starts[k]), int(sizes[k])
+                    if r["status"] != 0 or not (np.array_equal(oi, eI[s:s + n]) and np.array_equal(ou, eU[s:s + n])):
+                        exact = False
+                    results[k] = r
+            th.join()
+            if errors or len(results) < n_jobs:
+                raise RuntimeError(f"rate {lam}: {len(results)} of {n_jobs} jobs finished; errors {errors[:3]}")
+            # set sums against the oracle (after the run: not on the serving path)
+            for k, r in results.items():
+                s, n = int(starts[k]), int(sizes[k])
+                si, su, nn, jj, jp = oracle.jaccard_sets(np.array([0, n], np.int64), eI[s:s + n], eU[s:s + n])
+                if (r["sum_i"], r["sum_u"], r["n_contrib"], r["j"], r["jprime"]) != \
+                        (int(si[0]), int(su[0]), int(nn[0]), float(jj[0]), float(jp[0])):
+                    exact = False
+            all_exact &= exact
+            st1 = srv.stats()
+            meas = [results[k] for k in range(20, n_jobs)] if n_jobs > 40 else list(results.values())
+            lat = np.array([r["t_done"] - r["t_submit"] for r in meas]) * 1e3
+            span = max(r["t_done"] for r in meas) - min(r["t_submit"] for r in meas)
+            pairs = sum(r["n_pairs"] for r in meas)
+            rec = {"rate_jobs_per_s": lam, "jobs": n_jobs, "measured_jobs": len(meas),
+                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                   "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+                   "pairs_per_s": pairs / span, "offered_pairs_per_s": float(sizes.mean() * lam),
+                   "launches": st1["launches"] - st0["launches"], "max_jobs_per_launch": st1["max_jobs_per_launch"],
+                   "admission_waits": st1["admission_waits"] - st0["admission_waits"], "bit_exact": bool(exact)}
+            log(f"rate {lam:g}/s: p50 {rec['p50_ms']:.2f} ms, p99 {rec['p99_ms']:.2f} ms, "
+                f"{rec['pairs_per_s'] / 1e6:.2f} Mpairs/s served, {rec['launches']} launches, exact {exact}")
+            out_rates.append(rec)
+    finally:
+        srv.close()
+    top = out_rates[-1]
+    out = {
+        "metric": METRIC, "value": top["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.jobs, "warmup": 20, "ms_per_step": top["mean_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": WORKLOADS[5], "corpus_pairs": corpus_n, "rates": rates,
+                   "parallelism": "none (1 GPU)"},
+        "serving": out_rates, "bit_exact_oracle_sample": bool(all_exact), "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3, 4])
+    ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--rates", type=str, default="5,20,80", help="workload 5: arrival rates (jobs/s)")
+    ap.add_argument("--jobs", type=int, default=600, help="workload 5: jobs per rate")
     ap.add_argument("--tiles", type=int, default=64, help="workload 4: number of tiles")
     ap.add_argument("--pairs", type=int, default=None, help="override the pair count (not the headline)")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--params", type=str, default=None,
+                    help='fixed batched parameters as JSON (e.g. \'{"min_queue_cells": 24}\'); skips the autotuner')
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args(argv)
@@ -134,6 +251,9 @@ def main(argv=None):
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the pair path has no cross-GPU "
               f"exchange in this build; see DESIGN.md for how it would shard.", file=sys.stderr)
         return 2
+
+    if args.workload == 5:
+        return serve_bench(args)
 
     import torch
 
@@ -169,7 +289,11 @@ def main(argv=None):
 
     with torch.cuda.stream(stream):
         tuned = {}
-        if not args.no_autotune:
+        if args.params:
+            tuned = json.loads(args.params)
+            ctx.set_params(**tuned)
+            log(f"fixed batched parameters {tuned}")
+        elif not args.no_autotune:
             t = time.perf_counter()
             tuned = autotune.tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key=wkey,
                                   use_cache=False, log=log)

@@ -189,6 +189,89 @@ int sccg_get_timing(sccg_ctx* ctx, double* out_ms, int64_t* out_launches);
 /* Message of the last error on this context ("" if none). */
 const char* sccg_last_error(const sccg_ctx* ctx);
 
+/* ------------------------------------------------------------ serving ---- */
+/* A server answers a stream of jobs, each one cross-comparison of two
+ * polygon sets over a list of candidate pairs (the unit of work of Section
+ * 4.1's pipeline: a tile's two result sets after the MBR filter).  Jobs
+ * are copied into resident device arenas when they are admitted, run
+ * together in bounded persistent launches (every admitted job that has not
+ * run yet joins the next launch: the aggregator stage of Section 4.1, which
+ * groups small tile tasks and is the only one to launch kernels), and
+ * retired in submission order.  A job is admitted once its
+ * footprint fits in all three arenas; until then it waits, and later jobs
+ * wait behind it.  Results are identical to sccg_area_pairs (BATCHED) plus
+ * sccg_jaccard_sets over the job's pairs, whatever else runs beside it.
+ *
+ * Unlike the calls above, sccg_server_submit takes HOST pointers.  They are
+ * borrowed until the job's result has been returned by sccg_server_poll;
+ * memory from hipHostMalloc (pinned) is copied by DMA without staging.  A
+ * server runs its own scheduler thread and two streams on its device;
+ * submit, poll, stats and clock may be called from any thread. */
+typedef struct sccg_server sccg_server;
+
+typedef struct {
+  int64_t vertex_cap;     /* resident vertex arena, in vertices (8 B each); 0 = 2^28                  */
+  int64_t slot_cap;       /* resident offset arena, in entries (8 B each): a job takes
+                             n_polys(A) + n_polys(B) + 2; 0 = 2^24, at most 2^31 - 1                 */
+  int64_t pair_cap;       /* resident pair arena, in pairs (24 B of device and 16 B of pinned host
+                             memory each); 0 = 2^23                                                   */
+  int64_t max_step_pairs; /* pairs per launch; a larger job runs alone in its launch; 0 = 2^21        */
+  int32_t max_inflight;   /* launches queued on the device at once, 1..4; 0 = 2                      */
+  uint32_t jaccard_flags; /* SCCG_J_* for the per-job sums                                            */
+} sccg_server_config;
+
+typedef struct {
+  uint64_t job_id;       /* as returned by sccg_server_submit                                        */
+  int32_t status;        /* SCCG_OK, or SCCG_E_RANGE / SCCG_E_DEVICE latched by the job's launch, or
+                            SCCG_E_HIP if the server failed                                           */
+  int32_t jobs_in_launch;/* jobs that shared the job's launch                                        */
+  int64_t n_pairs;
+  int64_t sum_i, sum_u, n_contrib; /* as sccg_jaccard_sets over the job's pairs                      */
+  double j, jprime;
+  double t_submit, t_admit, t_launch, t_done; /* seconds on the server's clock: submitted, copied
+                             into the arenas, launched, results on the host                          */
+} sccg_job_result;
+
+/* Create a server on HIP device `hip_device`.  `config` and `params` may be
+ * NULL (defaults); `params` tunes the batched launches (SCCG_F_NO_GRAPH is
+ * implied).  All device and pinned memory is allocated here. */
+int sccg_server_create(sccg_server** out, int hip_device, const sccg_server_config* config,
+                       const sccg_params* params);
+
+/* Queue one job: pairs (A[pair_a[k]], B[pair_b[k]]), k < n_pairs, with A and
+ * B given as host CSR (here offsets[0] need not be 0: polygon k's vertices
+ * are xy[2*offsets[k]] ... xy[2*offsets[k+1]-1]).  out_inter / out_union
+ * (host, [n_pairs], nullable) receive the per-pair counts before the job is
+ * reported done.  Offsets and pair indices are checked here (SCCG_E_ARG); a
+ * job larger than an arena gives SCCG_E_NOMEM; a failed server gives
+ * SCCG_E_STATE.  A job with no pairs completes at once.  *out_job_id gets
+ * the job's id (ids count up from 1). */
+int sccg_server_submit(sccg_server* srv, const sccg_polys* A, const sccg_polys* B, int64_t n_pairs,
+                       const int32_t* pair_a, const int32_t* pair_b, int64_t* out_inter, int64_t* out_union,
+                       uint64_t* out_job_id);
+
+/* Move up to max_results finished jobs into out (in completion order),
+ * waiting up to timeout_us microseconds for the first one (0 = do not wait,
+ * < 0 = wait without limit).  Returns the number written. */
+int sccg_server_poll(sccg_server* srv, sccg_job_result* out, int max_results, int64_t timeout_us);
+
+/* Server counters: [0] jobs submitted [1] jobs done [2] launches [3] pairs
+ * done [4] peak resident vertices [5] peak resident offset entries [6] peak
+ * resident pairs [7] admission waits (the oldest queued job did not fit)
+ * [8] most jobs in one launch [9] jobs rejected at submit.  Writes
+ * min(n, 10) values; returns that count. */
+int sccg_server_get_stats(sccg_server* srv, int64_t* out, int n);
+
+/* Seconds since the server was created, on the clock of sccg_job_result. */
+double sccg_server_clock(const sccg_server* srv);
+
+/* Message of the last error of this server ("" if none). */
+const char* sccg_server_last_error(sccg_server* srv);
+
+/* Finish every submitted job, stop the scheduler and free everything.
+ * Results not yet polled are dropped. */
+int sccg_server_destroy(sccg_server* srv);
+
 /* Library version string. */
 const char* sccg_version(void);
 

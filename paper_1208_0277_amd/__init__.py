@@ -40,7 +40,13 @@ SCCG_J_INCLUDE_ZERO = 1
 #: C-ABI entry points the library must export (checked by the CPU tests).
 EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
            "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
-           "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version")
+           "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version",
+           "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
+           "sccg_server_clock", "sccg_server_last_error", "sccg_server_destroy")
+
+SERVER_STAT_KEYS = ("jobs_submitted", "jobs_done", "launches", "pairs_done", "peak_resident_vertices",
+                    "peak_resident_slots", "peak_resident_pairs", "admission_waits", "max_jobs_per_launch",
+                    "jobs_rejected")
 
 STAT_KEYS = ("leaf_pixel_tests", "leaf_boxes", "split_boxes", "queued_boxes", "kept_boxes", "small_pairs",
              "large_pairs", "empty_pairs", "leaf_edge_updates", "classify_edge_visits", "leaf_staging_edges",
@@ -63,6 +69,23 @@ class sccg_params(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("grid", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("waves_per_wg", ctypes.c_int32), ("min_queue_cells", ctypes.c_int32),
                 ("n_queues", ctypes.c_int32), ("heavy_verts", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class sccg_server_config(ctypes.Structure):
+    _fields_ = [("vertex_cap", ctypes.c_int64), ("slot_cap", ctypes.c_int64), ("pair_cap", ctypes.c_int64),
+                ("max_step_pairs", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("jaccard_flags", ctypes.c_uint32)]
+
+
+class sccg_job_result(ctypes.Structure):
+    _fields_ = [("job_id", ctypes.c_uint64), ("status", ctypes.c_int32), ("jobs_in_launch", ctypes.c_int32),
+                ("n_pairs", ctypes.c_int64), ("sum_i", ctypes.c_int64), ("sum_u", ctypes.c_int64),
+                ("n_contrib", ctypes.c_int64), ("j", ctypes.c_double), ("jprime", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -99,6 +122,15 @@ def load_library(path: str = LIB_PATH):
         "sccg_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "sccg_last_error": ([P], ctypes.c_char_p),
         "sccg_version": ([], ctypes.c_char_p),
+        "sccg_server_create": ([ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(sccg_server_config),
+                                ctypes.POINTER(sccg_params)], ctypes.c_int),
+        "sccg_server_submit": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P,
+                                ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "sccg_server_poll": ([P, ctypes.POINTER(sccg_job_result), ctypes.c_int, i64], ctypes.c_int),
+        "sccg_server_get_stats": ([P, P, ctypes.c_int], ctypes.c_int),
+        "sccg_server_clock": ([P], ctypes.c_double),
+        "sccg_server_last_error": ([P], ctypes.c_char_p),
+        "sccg_server_destroy": ([P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -269,6 +301,97 @@ class Context:
     def sync_code(self) -> int:
         """Wait for the stream and return the status code without raising."""
         return int(self.lib.sccg_sync(self.h))
+
+
+def _host(a: np.ndarray, dtype, name: str) -> np.ndarray:
+    if not isinstance(a, np.ndarray) or a.dtype != dtype or not a.flags.c_contiguous:
+        raise ValueError(f"{name} must be a C-contiguous numpy array of {np.dtype(dtype).name}")
+    return a
+
+
+class Server:
+    """Continuous-batching server (sccg_server_*): jobs are host CSR pairs of
+    polygon sets plus candidate pairs; results come back through poll().
+
+    Arrays passed to submit() are borrowed until that job's result has been
+    polled (the object keeps them alive until then).  Arrays that live in
+    pinned memory (e.g. numpy views of ``torch.empty(..., pin_memory=True)``)
+    are copied by DMA without staging."""
+
+    def __init__(self, device: int = 0, params: dict | None = None, **config):
+        self.lib = load_library()
+        self.h = ctypes.c_void_p()
+        cfg = sccg_server_config(**config)
+        prm = sccg_params(**(params or {}))
+        rc = self.lib.sccg_server_create(ctypes.byref(self.h), device, ctypes.byref(cfg), ctypes.byref(prm))
+        if rc != SCCG_OK:
+            self.h = ctypes.c_void_p()
+            raise SccgError(rc, "sccg_server_create failed")
+        self._live = {}
+        import threading
+        self._lock = threading.Lock()  # submit stores a job's arrays before poll may drop them
+
+    def _rc(self, rc: int) -> int:
+        if rc < 0:
+            raise SccgError(rc, self.lib.sccg_server_last_error(self.h).decode())
+        return rc
+
+    def submit(self, a_off, a_xy, b_off, b_xy, pa, pb, out_inter=None, out_union=None) -> int:
+        a_off = _host(a_off, np.int64, "a_off")
+        b_off = _host(b_off, np.int64, "b_off")
+        a_xy = _host(a_xy, np.int32, "a_xy")
+        b_xy = _host(b_xy, np.int32, "b_xy")
+        pa = _host(pa, np.int32, "pa")
+        pb = _host(pb, np.int32, "pb")
+        if len(pa) != len(pb):
+            raise ValueError("pa and pb differ in length")
+        for o, name in ((out_inter, "out_inter"), (out_union, "out_union")):
+            if o is not None and (_host(o, np.int64, name).shape[0] < len(pa)):
+                raise ValueError(f"{name} is shorter than the pair list")
+        A = sccg_polys(len(a_off) - 1, a_off.ctypes.data, a_xy.ctypes.data if a_xy.size else None)
+        B = sccg_polys(len(b_off) - 1, b_off.ctypes.data, b_xy.ctypes.data if b_xy.size else None)
+        jid = ctypes.c_uint64()
+        with self._lock:
+            self._rc(self.lib.sccg_server_submit(
+                self.h, ctypes.byref(A), ctypes.byref(B), len(pa), pa.ctypes.data if len(pa) else None,
+                pb.ctypes.data if len(pb) else None, out_inter.ctypes.data if out_inter is not None else None,
+                out_union.ctypes.data if out_union is not None else None, ctypes.byref(jid)))
+            self._live[jid.value] = (a_off, a_xy, b_off, b_xy, pa, pb, out_inter, out_union)
+        return jid.value
+
+    def poll(self, max_results: int = 256, timeout: float | None = 0.0) -> list[dict]:
+        """Finished jobs (dicts of sccg_job_result fields); waits up to
+        `timeout` seconds for the first (None = without limit)."""
+        buf = (sccg_job_result * max_results)()
+        us = -1 if timeout is None else int(timeout * 1e6)
+        n = self._rc(self.lib.sccg_server_poll(self.h, buf, max_results, us))
+        out = []
+        with self._lock:
+            for k in range(n):
+                d = buf[k].as_dict()
+                self._live.pop(d["job_id"], None)
+                out.append(d)
+        return out
+
+    def stats(self) -> dict:
+        v = np.zeros(len(SERVER_STAT_KEYS), np.int64)
+        n = self._rc(self.lib.sccg_server_get_stats(self.h, v.ctypes.data, len(v)))
+        return {k: int(v[i]) for i, k in enumerate(SERVER_STAT_KEYS[:n])}
+
+    def clock(self) -> float:
+        return float(self.lib.sccg_server_clock(self.h))
+
+    def close(self):
+        if self.h:
+            self.lib.sccg_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -209,6 +209,8 @@ Polys to_polys(const sccg_polys* P) {
 
 }  // namespace
 
+uint32_t* sccg::ctx_error_word(sccg_ctx* c) { return c->err; }
+
 extern "C" {
 
 const char* sccg_version(void) { return kVersion; }

@@ -127,4 +127,8 @@ hipError_t launch_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t*
 // Ring validation.
 hipError_t launch_validate(const Polys& P, int64_t* first_bad, hipStream_t s);
 
+// The device error word of a context (read and cleared by the server, which
+// owns its context and runs on the context's stream).
+uint32_t* ctx_error_word(sccg_ctx* c);
+
 }  // namespace sccg
