@@ -28,11 +28,17 @@ class _Polys(ctypes.Structure):
 
 def _load():
     global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"oracle library not built: {LIB_PATH} (run __graft_entry__.build())")
-    lib = ctypes.CDLL(LIB_PATH)
+    if _lib is None:
+        _lib = load_library(LIB_PATH)
+    return _lib
+
+
+def load_library(path: str):
+    """Load an oracle library build with its signatures set (the pin-strength
+    tests load deliberately broken builds this way)."""
+    if not os.path.exists(path):
+        raise RuntimeError(f"oracle library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
     lib.sccg_oracle_pixel_inside.restype = ctypes.c_int
     lib.sccg_oracle_pixel_inside.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
     lib.sccg_oracle_poly_area.restype = ctypes.c_int64
@@ -45,7 +51,6 @@ def _load():
     lib.sccg_oracle_jaccard_sets.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
-    _lib = lib
     return lib
 
 

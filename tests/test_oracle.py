@@ -247,6 +247,18 @@ def test_containment_and_degenerate():
     assert U.tolist() == [100, 100, 12, 100]
 
 
+def test_empty_rings():
+    """A ring without vertices has no edges, so no pixel centre sees a
+    crossing: it covers nothing, and the other ring is counted alone."""
+    R = band_ring([0, 3], [0], [5])  # [0,5)x[0,3): 15 pixels
+    empty = np.zeros((0, 2), np.int32)
+    A, B, pa, pb = _pairs_from([empty, R, empty], [R, empty, empty])
+    for form in (oracle.PURE, oracle.ROWS):
+        I, U = oracle.area_pairs(A, B, pa, pb, form=form)
+        assert I.tolist() == [0, 0, 0] and U.tolist() == [15, 15, 0]
+    assert oracle.poly_areas(A).tolist() == [0, 15, 0]
+
+
 def test_jaccard_exact_rational():
     rng = np.random.default_rng(3)
     n = 5000
