@@ -18,12 +18,12 @@
 //     cells whose first pixel it crosses, in two 64-bit masks, which are then
 //     OR- and XOR-reduced across the wave.  Cost O(edges) per split instead of
 //     O(cells x edges).
-//   - Leaf tiles use bit-sliced crossing tests: lane x holds column x of the
-//     tile as a 64-bit row mask; each vertical edge of the tile's band at X
-//     toggles, in every column left of X, the rows its span holds.  Only the
-//     edges whose span meets the tile's rows and that lie right of its left
-//     side are staged (band culling); a polygon known to contain a tile is
-//     not tested again (its mask is all ones).
+//   - Leaf tiles use bit-sliced crossing tests: a lane holds one column of
+//     the tile as a row mask.  Each vertical edge of the tile's band XORs its
+//     row mask into the LDS slot of the rightmost column it toggles (one
+//     atomic per edge), and a prefix XOR over the lanes turns the slots into
+//     every column's crossing parities.  A polygon known to contain a tile
+//     is not tested again (its mask is all ones).
 //   - The pair's MBRs and shoelace areas are reduced by the wave that takes
 //     the pair, from the same coalesced ring loads it needs anyway; only the
 //     pairs with many vertices ("heavy", claimed first: a largest-first
@@ -43,20 +43,22 @@
 //     bounded anyway and latches SCCG_E_DEVICE if the bound is hit.
 #include <limits.h>
 
+#include <type_traits>
+
 #include "sccg_device.h"
 
 namespace sccg {
 
-constexpr int kLeafCap = 256;   // staged band edges per flush (per wave)
-constexpr int kLocalCap = 256;  // per-wave stack of boxes to process inline
+constexpr int kLeafSlots = 2 * kWave;  // per-wave leaf slots: one per column of p and of q
+constexpr int kLocalCap = 256;          // per-wave stack of boxes to process inline
 constexpr uint32_t kSpinLimit = 1u << 22;
-// per-wave LDS: staged edges, the inline box stack, the metadata of one chunk
+// per-wave LDS: leaf slots, the inline box stack, the metadata of one chunk
 struct ChunkMeta {
   int64_t op, oq;
   int32_t np, nq;
   int32_t cls, pad;
 };
-constexpr int kLdsPerWave = kLeafCap * 16 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta);
+constexpr int kLdsPerWave = kLeafSlots * 8 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta);
 constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
 
 int batch_lds_bytes_per_wave() { return kLdsPerWave; }
@@ -102,7 +104,7 @@ __device__ __forceinline__ uint64_t row_range(int lo, int hi) {
 struct Ctx {
   const BatchArgs* a;
   int lane;
-  uint4* edges;     // per-wave staging, kLeafCap entries
+  uint64_t* slots;  // per-wave leaf slots, kLeafSlots entries
   uint64_t* local;  // per-wave inline stack, kLocalCap entries
   ChunkMeta* meta;  // per-wave metadata of the pairs of one chunk
   int lsp;          // inline stack depth (wave-uniform)
@@ -281,166 +283,136 @@ __device__ __forceinline__ bool coords_bad(const Meta& m, int64_t nv) {
 }
 
 // ------------------------------------------------------------------ leaves
-// A staged edge toggles, in every column x < xr of its tile, the rows of rr.
-// m ^= rr & (x < xr ? ~0 : 0), one v_bitop3 per 32-bit half.
-__device__ __forceinline__ uint32_t toggle32(uint32_t m, uint32_t rr, uint32_t sel) {
-  return __builtin_amdgcn_bitop3_b32(m, rr, sel, 0x78);  // m ^ (rr & sel)
+// Scatter-and-scan leaves.  The columns of a leaf tile live in lanes in
+// reverse order: in a W-column group (W = 64, or 32 when p and q share the
+// wave as two halves), lane L holds column W - 1 - L.  A vertical edge at X
+// whose span meets the tile's rows toggles those rows in every column left of
+// X.  It XORs its row mask into one LDS slot: the slot of the rightmost column
+// it toggles, W - min(X - x0, W).  Any number of edges may share a slot.  An
+// inclusive prefix XOR over the lanes then leaves in every column the XOR of
+// the edges right of it: bit r of lane L is the crossing parity of the centre
+// of pixel (x0 + W - 1 - L, y0 + r) (Section 3.1).  Cost per tile: one atomic
+// per edge of the band, no per-edge work in the other lanes.
+
+// Inclusive prefix XOR over lanes (rows of 16 by shifts, then the row
+// broadcasts); with kHalves the scan restarts at lane 32.
+template <bool kHalves>
+__device__ __forceinline__ uint32_t wave_prefix_xor(uint32_t x) {
+  x ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+  if (!kHalves) x ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+template <bool kHalves>
+__device__ __forceinline__ uint64_t wave_prefix_xor(uint64_t x) {
+  return ((uint64_t)wave_prefix_xor<kHalves>((uint32_t)(x >> 32)) << 32) | wave_prefix_xor<kHalves>((uint32_t)x);
 }
 
-// XOR the staged edges into this lane's column mask.  The loop keeps four
-// LDS reads in flight (deeper unrolling costs registers, hence occupancy).
-__device__ __forceinline__ void flush_edges(const uint4* e, int cnt, int lane, uint64_t& m) {
-  wave_sync_lds();
-  uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-#pragma unroll 4
-  for (int k = 0; k < cnt; ++k) {
-    const uint4 a = e[k];
-    const uint32_t sa = (uint32_t)lane < a.x ? ~0u : 0u;
-    lo = toggle32(lo, a.y, sa);
-    hi = toggle32(hi, a.z, sa);
-  }
-  m = ((uint64_t)hi << 32) | lo;
-  wave_sync_lds();
-}
-
-// The leaf edge of (v, w) for the tile at (tx0, ty0) of height th: kept iff
-// vertical, right of the tile's left side, with a span meeting the rows.
-__device__ __forceinline__ bool leaf_edge(int2 v, int2 w, int tx0, int ty0, int th, uint32_t& xr, uint64_t& rr) {
+// The slot and row mask of edge (v, w) for the tile at (tx0, ty0) of height
+// th in a W-column group: kept iff vertical, right of the tile's left side,
+// with a span meeting the rows.
+__device__ __forceinline__ bool leaf_edge(int2 v, int2 w, int tx0, int ty0, int th, int W, int& slot,
+                                          uint64_t& rr) {
   if (v.x != w.x) return false;
   const int lo = max(min(v.y, w.y) - ty0, 0);
   const int hi = min(max(v.y, w.y) - ty0, th);
   const int dx = v.x - tx0;
   if (!(lo < hi && dx > 0)) return false;
-  xr = (uint32_t)min(dx, kTile);
+  slot = W - min(dx, W);
   rr = row_range(lo, hi);
   return true;
 }
 
-// Column masks of polygon ring xy[o .. o+nv) over the leaf tile
-// [tx0, tx0+64) x [ty0, ty0+th): bit r of lane x is the crossing parity of
-// pixel (tx0 + x, ty0 + r).
-__device__ __forceinline__ uint64_t leaf_masks(Ctx& c, const int2* xy, int64_t o, int64_t nv, int tx0, int ty0,
-                                               int th) {
-  const int lane = c.lane;
-  uint64_t m = 0;
-  int cnt = 0, nk_total = 0;
-  for (int base = 0; base < (int)nv; base += kWave) {
-    int2 v, w;
-    load_edge(xy, o, nv, base + lane, v, w);
-    uint32_t xr = 0;
-    uint64_t rr = 0;
-    const bool keep = (base + lane < nv) && leaf_edge(v, w, tx0, ty0, th, xr, rr);
-    const uint64_t b = ballot(keep);
-    const int nk = __popcll(b);
-    if (cnt + nk > kLeafCap) {
-      flush_edges(c.edges, cnt, lane, m);
-      cnt = 0;
-    }
-    if (keep) c.edges[cnt + lanes_below(b)] = make_uint4(xr, (uint32_t)rr, (uint32_t)(rr >> 32), 0u);
-    cnt += nk;
-    nk_total += nk;
-  }
-  if (cnt > 0) flush_edges(c.edges, cnt, lane, m);
-  if (c.a->stats_on) {
-    stat_add(c, 8, (unsigned long long)nk_total);
-    stat_add(c, 10, (unsigned long long)nv);
-  }
-  return m;
+template <typename M>
+__device__ __forceinline__ void slot_xor(M* slots, int k, uint64_t rr) {
+  __hip_atomic_fetch_xor(slots + k, (M)rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-// Stage the leaf edges of one ring for a small pair's tile into e[0 ..),
-// reading the first two chunks from registers.  Returns the count, or -1 if
-// more than `cap` edges (the caller then takes the general path).
-__device__ __forceinline__ int stage_small(Ctx& c, const int2* xy, int64_t o, int64_t nv, const RingRegs& r,
-                                           int tx0, int ty0, int th, uint4* e, int cap) {
+// Scatter the leaf edges of one ring into slots[base ..).  The first two
+// 64-vertex chunks come from registers when `r` is given, the rest (or all)
+// from global memory.  Returns the number of edges scattered.
+template <typename M>
+__device__ __forceinline__ uint32_t scatter_ring(Ctx& c, const int2* xy, int64_t o, int64_t nv, const RingRegs* r,
+                                                 int tx0, int ty0, int th, int W, M* slots, int base) {
   const int lane = c.lane;
-  int cnt = 0;
-  for (int base = 0; base < (int)nv; base += kWave) {
+  uint32_t kept = 0;
+#pragma unroll 1
+  for (int b0 = 0; b0 < (int)nv; b0 += kWave) {
     int2 v, w;
-    if (base == 0) {
-      v = r.v0;
-      w = r.w0;
-    } else if (base == kWave) {
-      v = r.v1;
-      w = r.w1;
+    if (r && b0 == 0) {
+      v = r->v0;
+      w = r->w0;
+    } else if (r && b0 == kWave) {
+      v = r->v1;
+      w = r->w1;
     } else {
-      load_edge(xy, o, nv, base + lane, v, w);
+      // one coalesced load per chunk; successors from the next lane, lane
+      // 63's from the next chunk, the last vertex's is the first (single-lane
+      // loads)
+      const int k = b0 + lane;
+      v = k < (int)nv ? xy[o + k] : make_int2(0, 0);
+      w = next_lane(v);
+      if (lane == kWave - 1 && k + 1 < (int)nv) w = xy[o + k + 1];
+      if (k + 1 == (int)nv) w = xy[o];
     }
-    uint32_t xr = 0;
+    int slot = 0;
     uint64_t rr = 0;
-    const bool keep = (base + lane < nv) && leaf_edge(v, w, tx0, ty0, th, xr, rr);
-    const uint64_t b = ballot(keep);
-    const int nk = __popcll(b);
-    if (cnt + nk > cap) return -1;
-    if (keep) e[cnt + lanes_below(b)] = make_uint4(xr, (uint32_t)rr, (uint32_t)(rr >> 32), 0u);
-    cnt += nk;
+    const bool keep = (b0 + lane < (int)nv) && leaf_edge(v, w, tx0, ty0, th, W, slot, rr);
+    if (keep) slot_xor(slots, base + slot, rr);
+    if (c.a->stats_on) kept += (uint32_t)__popcll(ballot(keep));
   }
   if (c.a->stats_on) {
-    stat_add(c, 8, (unsigned long long)cnt);
+    stat_add(c, 8, (unsigned long long)kept);
     stat_add(c, 10, (unsigned long long)nv);
   }
-  return cnt;
+  return kept;
 }
 
-constexpr int kHalfCap = kLeafCap / 2;
-
-// Intersection count of a small pair (box <= 64 x 64 = the whole leaf tile),
-// from edges staged once.  Narrow boxes (w <= 32) run p in lanes 0-31 and q
-// in lanes 32-63 at the same time; short boxes (h <= 32) use 32-bit row
-// masks.  Returns -1 when an edge list does not fit (general path instead).
+// Intersection count of a small pair (box <= 64 x 64 = one leaf tile).
+// Narrow boxes (w <= 32) run p in lanes 0-31 and q in lanes 32-63 with one
+// scan; short boxes (h <= 32) use 32-bit row masks.
 template <bool kRows64>
 __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const RingRegs& rp, const RingRegs& rq,
                                               int tw, int th) {
+  using M = typename std::conditional<kRows64, uint64_t, uint32_t>::type;
   const BatchArgs& a = *c.a;
   const int lane = c.lane;
   const int tx0 = pi.box.x0, ty0 = pi.box.y0;
-  uint4* ep = c.edges;
-  uint4* eq = c.edges + kHalfCap;
-  const int np = stage_small(c, a.A.xy, pi.op, pi.np, rp, tx0, ty0, th, ep, kHalfCap);
-  const int nq = np < 0 ? -1 : stage_small(c, a.B.xy, pi.oq, pi.nq, rq, tx0, ty0, th, eq, kHalfCap);
-  if (np < 0 || nq < 0) return -1;
+  M* slots = reinterpret_cast<M*>(c.slots);
   uint32_t n = 0;
   if (tw <= 32) {
-    // pad the shorter list with null edges, then one pass for both rings
-    const int nm = max(np, nq);
-    for (int k = np + lane; k < nm; k += kWave) ep[k] = make_uint4(0u, 0u, 0u, 0u);
-    for (int k = nq + lane; k < nm; k += kWave) eq[k] = make_uint4(0u, 0u, 0u, 0u);
+    slots[lane] = 0;
     wave_sync_lds();
-    const uint4* e = lane < 32 ? ep : eq;
-    const uint32_t col = (uint32_t)(lane & 31);
-    uint32_t lo = 0, hi = 0;
-#pragma unroll 4
-    for (int k = 0; k < nm; ++k) {
-      const uint4 x = e[k];
-      const uint32_t s = col < x.x ? ~0u : 0u;
-      lo = toggle32(lo, x.y, s);
-      if (kRows64) hi = toggle32(hi, x.z, s);
-    }
+    scatter_ring(c, a.A.xy, pi.op, pi.np, &rp, tx0, ty0, th, 32, slots, 0);
+    scatter_ring(c, a.B.xy, pi.oq, pi.nq, &rq, tx0, ty0, th, 32, slots, 32);
     wave_sync_lds();
+    const M m = wave_prefix_xor<true>(slots[lane]);
     // lanes 0-31 hold p's columns, lanes 32-63 q's: bring q's beside p's
-    const uint32_t qlo = (uint32_t)__shfl_xor((int)lo, 32, kWave);
-    const uint32_t qhi = kRows64 ? (uint32_t)__shfl_xor((int)hi, 32, kWave) : 0u;
-    if (lane < tw) n = (uint32_t)__popc(lo & qlo) + (kRows64 ? (uint32_t)__popc(hi & qhi) : 0u);
+    M mq;
+    if (kRows64) {
+      const uint64_t m64 = (uint64_t)m;
+      const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)m64, 32, kWave);
+      const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(m64 >> 32), 32, kWave);
+      mq = (M)(((uint64_t)hi << 32) | lo);
+    } else {
+      mq = (M)(uint32_t)__shfl_xor((int)(uint32_t)m, 32, kWave);
+    }
+    if (lane < 32 && 31 - lane < tw) n = (uint32_t)__popcll((uint64_t)(m & mq));
   } else {
+    slots[lane] = 0;
+    slots[kWave + lane] = 0;
     wave_sync_lds();
-    uint32_t plo = 0, phi = 0, qlo = 0, qhi = 0;
-#pragma unroll 4
-    for (int k = 0; k < np; ++k) {
-      const uint4 x = ep[k];
-      const uint32_t s = (uint32_t)lane < x.x ? ~0u : 0u;
-      plo = toggle32(plo, x.y, s);
-      if (kRows64) phi = toggle32(phi, x.z, s);
-    }
-#pragma unroll 4
-    for (int k = 0; k < nq; ++k) {
-      const uint4 x = eq[k];
-      const uint32_t s = (uint32_t)lane < x.x ? ~0u : 0u;
-      qlo = toggle32(qlo, x.y, s);
-      if (kRows64) qhi = toggle32(qhi, x.z, s);
-    }
+    scatter_ring(c, a.A.xy, pi.op, pi.np, &rp, tx0, ty0, th, kWave, slots, 0);
+    scatter_ring(c, a.B.xy, pi.oq, pi.nq, &rq, tx0, ty0, th, kWave, slots, kWave);
     wave_sync_lds();
-    if (lane < tw) n = (uint32_t)__popc(plo & qlo) + (kRows64 ? (uint32_t)__popc(phi & qhi) : 0u);
+    const M mp = wave_prefix_xor<false>(slots[lane]);
+    const M mq = wave_prefix_xor<false>(slots[kWave + lane]);
+    if (kWave - 1 - lane < tw) n = (uint32_t)__popcll((uint64_t)(mp & mq));
   }
+  wave_sync_lds();
   if (a.stats_on) {
     stat_add(c, 1, 1ull);
     stat_add(c, 0, 2ull * (unsigned long long)tw * th);
@@ -448,13 +420,24 @@ __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const 
   return (int64_t)wave_sum_u32(n);
 }
 
-// Pixels of the tile [tx0, tx0+tw) x [ty0, ty0+th) inside both polygons.
-__device__ __forceinline__ uint32_t leaf_count(Ctx& c, const PairInfo& pi, int tx0, int ty0, int tw, int th, bool kp, bool kq) {
+// Pixels of the tile [tx0, tx0+tw) x [ty0, ty0+th) inside both polygons; a
+// polygon known to contain the tile is not scattered (all rows set).
+__device__ __forceinline__ uint32_t leaf_count(Ctx& c, const PairInfo& pi, int tx0, int ty0, int tw, int th, bool kp,
+                                               bool kq) {
   const BatchArgs& a = *c.a;
+  const int lane = c.lane;
+  uint64_t* slots = c.slots;
+  slots[lane] = 0;
+  slots[kWave + lane] = 0;
+  wave_sync_lds();
+  if (!kp) scatter_ring(c, a.A.xy, pi.op, pi.np, (const RingRegs*)nullptr, tx0, ty0, th, kWave, slots, 0);
+  if (!kq) scatter_ring(c, a.B.xy, pi.oq, pi.nq, (const RingRegs*)nullptr, tx0, ty0, th, kWave, slots, kWave);
+  wave_sync_lds();
   const uint64_t full = row_range(0, th);
-  const uint64_t mp = kp ? full : leaf_masks(c, a.A.xy, pi.op, pi.np, tx0, ty0, th);
-  const uint64_t mq = kq ? full : leaf_masks(c, a.B.xy, pi.oq, pi.nq, tx0, ty0, th);
-  const uint32_t n = (c.lane < tw) ? (uint32_t)__popcll(mp & mq) : 0u;
+  const uint64_t mp = kp ? full : wave_prefix_xor<false>(slots[lane]);
+  const uint64_t mq = kq ? full : wave_prefix_xor<false>(slots[kWave + lane]);
+  wave_sync_lds();
+  const uint32_t n = (kWave - 1 - lane < tw) ? (uint32_t)__popcll(mp & mq) : 0u;
   if (a.stats_on) {
     stat_add(c, 1, 1ull);
     stat_add(c, 0, (unsigned long long)tw * th * ((kp ? 0 : 1) + (kq ? 0 : 1)));
@@ -721,9 +704,9 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   Ctx c;
   c.a = &args;
   c.lane = lane_id();
-  c.edges = reinterpret_cast<uint4*>(smem + (size_t)wave * kLdsPerWave);
-  c.local = reinterpret_cast<uint64_t*>(smem + (size_t)wave * kLdsPerWave + kLeafCap * 16);
-  c.meta = reinterpret_cast<ChunkMeta*>(smem + (size_t)wave * kLdsPerWave + kLeafCap * 16 + kLocalCap * 8);
+  c.slots = reinterpret_cast<uint64_t*>(smem + (size_t)wave * kLdsPerWave);
+  c.local = reinterpret_cast<uint64_t*>(smem + (size_t)wave * kLdsPerWave + kLeafSlots * 8);
+  c.meta = reinterpret_cast<ChunkMeta*>(smem + (size_t)wave * kLdsPerWave + kLeafSlots * 8 + kLocalCap * 8);
   c.lsp = 0;
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
@@ -870,7 +853,6 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
         pi.area_sum = 0;
       } else if (bw <= kTile && bh <= kTile) {
         I = bh > 32 ? leaf_small<true>(c, pi, rp, rq, bw, bh) : leaf_small<false>(c, pi, rp, rq, bw, bh);
-        if (I < 0) task = task_word(0, 0, 0, 0, false, false);  // too many edges: the general leaf
         if (a.stats_on && c.lane == 0) {
           atomicAdd(&a.st->stats[5], 1ull);
           atomicAdd(&a.st->stats[11], (unsigned long long)bw * bh);
