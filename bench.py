@@ -32,6 +32,8 @@ import numpy as np  # noqa: E402
 METRIC = "polygon pairs/sec and pixel-tests/sec, bit-exact; batched vs plain kernel"
 
 WORKLOADS = {
+    6: "Figure 8 stand-in: 15,724 uniform-mix pairs with coordinates scaled by k = 1..5; PixelOnly, "
+       "PixelBox-NoSep and PixelBox (batched) and the plain Algorithm 1 kernel, each autotuned",
     5: "serving: Poisson job arrivals at 5, 20 and 80 jobs/s, 600 jobs per rate (first 20 not measured), "
        "each job a window of 1e3-5e5 pairs (log-uniform) of a pinned 500,000-pair uniform-mix corpus",
     4: "set-level: 64 tiles of 8192^2 px, per tile set A packed with 10-60 px shapes and set B = 85% shifted "
@@ -45,22 +47,24 @@ WORKLOADS = {
 
 # Algorithmic integer work of the persistent kernel, in int32 lane-ops per
 # counted unit (the counters come from an instrumented call):
-#   leaf_edge_updates:    one staged vertical edge applied to one 64x64 leaf
-#                         tile: per column lane a compare, a select and an
-#                         and-xor on each half of the 64-bit row mask -> 4 x 64
+#   leaf_edge_updates:    one band edge of a leaf tile XORed into its column
+#                         slot: a 64-bit XOR -> 2
 #   leaf_staging_edges:   one ring edge tested for a tile's band: vertical
-#                         test, span clip (4), X test (2), keep (2), row mask (3)
+#                         test, span clip (4), X test (2), keep (2), slot (1),
+#                         row mask (2) -> 12
 #   classify_edge_visits: one ring edge against a split grid: hover test and
 #                         cell masks (12), first-pixel parity range and masks (12)
 #   ring_scan_vertices:   one vertex of a pair's rings: extent (4 min/max),
 #                         shoelace term (2 multiplies and a subtract in 64 bits: 6)
-#   leaf_boxes:           one leaf tile: and + popcount of both halves per lane (3 x 64)
+#   leaf_boxes:           one leaf tile: per ring a 64-bit prefix XOR over the
+#                         64 column lanes (6 steps x 2 words), then the AND and
+#                         popcount of both masks -> (2 x 12 + 2) x 64
 ALGO_OPS = {
-    "leaf_edge_updates": 4 * 64,
+    "leaf_edge_updates": 2,
     "leaf_staging_edges": 12,
     "classify_edge_visits": 24,
     "ring_scan_vertices": 10,
-    "leaf_boxes": 3 * 64,
+    "leaf_boxes": 26 * 64,
 }
 # int32 VALU peak of MI355X: 256 CUs x 4 SIMD16 = 64 lanes per CU per clock at 2.4 GHz
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
@@ -79,10 +83,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload: int):
-    """HBM bytes per launch of the persistent kernel from the committed
-    counter summary, or None when it is missing or older than the kernel."""
-    path = os.path.join(ROOT, "profiles", f"traffic_k_batch_run_workload{workload}.json")
+PROFILE_STEMS = {3: "k_batch_run_heavy_tailed_2M", 4: "k_batch_run_set_level_64_tiles"}
+
+
+def profile_summary(workload: int):
+    """The committed counter summary of the persistent kernel on this
+    workload (profiles/<stem>.json), or None when it is missing or was taken
+    on another version of the kernel source."""
+    stem = PROFILE_STEMS.get(workload)
+    if stem is None:
+        return None
+    path = os.path.join(ROOT, "profiles", stem + ".json")
     if not os.path.exists(path):
         return None
     try:
@@ -92,7 +103,7 @@ def traffic_from_profile(workload: int):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    return d
 
 
 def cpu_baseline(wl, I_gpu, U_gpu, seconds: float, seed: int):
@@ -229,12 +240,81 @@ def serve_bench(args):
     return 0
 
 
+def fig8_bench(args):
+    """Section 5.2's comparison (Figure 8) on a synthetic stand-in for its
+    15,724-pair set: the same pairs with every coordinate multiplied by k.
+    Every variant must give identical counts, and counts at k must be k^2
+    times those at 1."""
+    import torch
+
+    import paper_1208_0277_amd as sccg
+    import sccg_gen
+    from paper_1208_0277_amd import autotune
+
+    base = sccg_gen.pairs(2, 15724, seed=sccg_gen.BASE_SEED + 6)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    variants = [("PixelOnly", sccg.SCCG_BATCHED, {"flags": sccg.SCCG_F_PIXEL_ONLY}),
+                ("PixelBox-NoSep", sccg.SCCG_BATCHED, {"flags": sccg.SCCG_F_NO_SEP}),
+                ("PixelBox", sccg.SCCG_BATCHED, {}),
+                ("Algorithm 1 (plain)", sccg.SCCG_PLAIN, {})]
+    rows, exact, ref1 = [], True, None
+    for k in range(1, 6):
+        dA = sccg.DevicePolys.from_host(base.A.off, base.A.xy * k, dev)
+        dB = sccg.DevicePolys.from_host(base.B.off, base.B.xy * k, dev)
+        pa = torch.from_numpy(base.pa).to(dev)
+        pb = torch.from_numpy(base.pb).to(dev)
+        I = torch.empty(base.n_pairs, dtype=torch.int64, device=dev)
+        U = torch.empty_like(I)
+        rec, ref = {"k": k}, None
+        for name, mode, fixed in variants:
+            ctx = sccg.Context(0, stream=stream, **fixed)
+            with torch.cuda.stream(stream):
+                tuned = {}
+                if not args.no_autotune:
+                    tuned = autotune.tune(ctx, dA, dB, pa, pb, I, U, mode=mode, workload_key=f"fig8/{name}/{k}",
+                                          steps=2, use_cache=False, log=lambda m: None)
+                    ctx.set_params(**{**tuned, **fixed})
+                for _ in range(args.warmup):
+                    ctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=mode)
+                ctx.sync()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(args.steps):
+                    ctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=mode)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t) * 1e3 / args.steps
+                ctx.sync()
+            got = (I.cpu().numpy(), U.cpu().numpy())
+            ctx.close()
+            if ref is None:
+                ref = got
+            exact &= bool(np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]))
+            rec[name + "_ms"] = ms
+            log(f"k={k} {name}: {ms:.3f} ms ({base.n_pairs / (ms / 1e3) / 1e6:.1f} Mpairs/s)")
+        if ref1 is None:
+            ref1 = ref
+        exact &= bool(np.array_equal(ref[0], k * k * ref1[0]) and np.array_equal(ref[1], k * k * ref1[1]))
+        rows.append(rec)
+    top = rows[-1]["PixelBox_ms"]
+    out = {
+        "metric": METRIC, "value": base.n_pairs / (top / 1e3), "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": top, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": WORKLOADS[6], "n_pairs": base.n_pairs, "value_at": "PixelBox, k = 5",
+                   "parallelism": "none (1 GPU)"},
+        "figure8": rows, "bit_exact_across_variants_and_k2": bool(exact), "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--rates", type=str, default="5,20,80", help="workload 5: arrival rates (jobs/s)")
     ap.add_argument("--jobs", type=int, default=600, help="workload 5: jobs per rate")
     ap.add_argument("--tiles", type=int, default=64, help="workload 4: number of tiles")
@@ -254,6 +334,8 @@ def main(argv=None):
 
     if args.workload == 5:
         return serve_bench(args)
+    if args.workload == 6:
+        return fig8_bench(args)
 
     import torch
 
@@ -368,12 +450,17 @@ def main(argv=None):
     algo_ops = sum(ALGO_OPS[k] * st.get(k, 0) for k in ALGO_OPS)
     achieved = algo_ops / (k_avg_ms / 1e3)
     algo_bytes = 8 * wl.n_pairs + 32 * wl.n_pairs + 8 * (len(wl.A.xy) + len(wl.B.xy)) + 16 * wl.n_pairs
-    traffic = traffic_from_profile(args.workload)
+    prof = profile_summary(args.workload)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
-                "frac": achieved / VALU_PEAK_OPS, "traffic": traffic, "kernel": "k_batch_run",
-                "kernel_ms": k_avg_ms, "algorithmic_ops_per_launch": algo_ops,
+                "frac": achieved / VALU_PEAK_OPS, "traffic": prof["bytes_per_launch"] if prof else None,
+                "kernel": "k_batch_run", "kernel_ms": k_avg_ms, "algorithmic_ops_per_launch": algo_ops,
                 "algorithmic_bytes_per_launch": algo_bytes,
                 "hbm_frac_algorithmic": (algo_bytes / (k_avg_ms / 1e3)) / HBM_PEAK}
+    if prof and prof.get("sq_insts_valu"):
+        # counter view: every issued VALU instruction at 64 lanes, over the
+        # profiled kernel time, against the same peak
+        roofline["valu_issue_frac_counters"] = prof["sq_insts_valu"] * 64 / (prof["kernel_ms"] / 1e3) / VALU_PEAK_OPS
+        roofline["profile"] = f"profiles/{PROFILE_STEMS[args.workload]}.md"
 
     cpu, exact_sample, n_sample = (None, None, 0)
     sets_info = {}

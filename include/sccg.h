@@ -62,8 +62,9 @@ extern "C" {
 #define SCCG_PLAIN 0u
 /* BATCHED: one persistent launch over all pairs with a device task queue
  * that spreads the hovering sampling boxes of large pairs over workgroups;
- * edge-parallel box classification, band-culled edges and bit-sliced
- * 64x64-pixel leaves. */
+ * edge-parallel box classification and bit-sliced 64x64-pixel leaves, in
+ * which every band edge XORs its row mask into one column slot and a prefix
+ * XOR over the columns gives the crossing parities. */
 #define SCCG_BATCHED 1u
 
 /* sccg_params.flags (ablation switches; none changes any count) */
@@ -71,6 +72,15 @@ extern "C" {
 #define SCCG_F_NO_KNOWN_INSIDE 0x2u /* batched: re-test a polygon already known to contain a box */
 #define SCCG_F_NO_SPLIT_QUEUE 0x4u  /* batched: a large pair's boxes stay with the wave that split it */
 #define SCCG_F_NO_GRAPH 0x8u        /* batched: launch the kernels directly, no HIP graph      */
+/* The two baselines of Section 5.2 (Figure 8), as ablations of BATCHED mode.
+ * Both count the union directly, pixel by pixel, over the bounding box of
+ * MBR(p) ∪ MBR(q), instead of deriving it from the polygon areas:
+ *   PIXEL_ONLY: no sampling boxes, every pixel of that box is tested;
+ *   NO_SEP:     sampling boxes, but a box stops only when it is decided for
+ *               both the intersection and the union.
+ * Counts are identical to the default; only the work differs. */
+#define SCCG_F_PIXEL_ONLY 0x10u
+#define SCCG_F_NO_SEP 0x20u
 
 /* sccg_jaccard_sets flags */
 #define SCCG_J_NONZERO_ONLY 0u /* default: only pairs with I > 0 contribute (Equation 1's filter) */

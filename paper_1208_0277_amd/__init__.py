@@ -33,6 +33,8 @@ SCCG_F_NO_LPT = 0x1
 SCCG_F_NO_KNOWN_INSIDE = 0x2
 SCCG_F_NO_SPLIT_QUEUE = 0x4
 SCCG_F_NO_GRAPH = 0x8
+SCCG_F_PIXEL_ONLY = 0x10
+SCCG_F_NO_SEP = 0x20
 
 SCCG_J_NONZERO_ONLY = 0
 SCCG_J_INCLUDE_ZERO = 1

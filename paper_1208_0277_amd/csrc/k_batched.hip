@@ -50,15 +50,17 @@
 namespace sccg {
 
 constexpr int kLeafSlots = 2 * kWave;  // per-wave leaf slots: one per column of p and of q
+constexpr int kBandCap = 256;           // per-wave band-edge list of one ring (p and q each)
 constexpr int kLocalCap = 256;          // per-wave stack of boxes to process inline
 constexpr uint32_t kSpinLimit = 1u << 22;
-// per-wave LDS: leaf slots, the inline box stack, the metadata of one chunk
+// per-wave LDS: leaf slots, band-edge lists, the inline box stack, the
+// metadata of one chunk
 struct ChunkMeta {
   int64_t op, oq;
   int32_t np, nq;
   int32_t cls, pad;
 };
-constexpr int kLdsPerWave = kLeafSlots * 8 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta);
+constexpr int kLdsPerWave = kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta);
 constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
 
 int batch_lds_bytes_per_wave() { return kLdsPerWave; }
@@ -105,6 +107,7 @@ struct Ctx {
   const BatchArgs* a;
   int lane;
   uint64_t* slots;  // per-wave leaf slots, kLeafSlots entries
+  uint32_t* band;   // per-wave band-edge lists: p at [0, kBandCap), q at [kBandCap, 2 kBandCap)
   uint64_t* local;  // per-wave inline stack, kLocalCap entries
   ChunkMeta* meta;  // per-wave metadata of the pairs of one chunk
   int lsp;          // inline stack depth (wave-uniform)
@@ -185,9 +188,10 @@ __device__ __forceinline__ int2 lane_value(int2 v, int l) {
 // the next chunk, and the last vertex's is vertex 0.
 __device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int64_t nv, int lane, RingRegs& r,
                                            int2& first, const int2* pre) {
+  // pre: the prefetched first two chunks (pre[0] = vertex lane, pre[1] = vertex lane + 64)
   const int64_t k0 = lane, k1 = lane + kWave;
-  r.v0 = pre ? *pre : (k0 < nv ? xy[o + k0] : make_int2(0, 0));
-  r.v1 = k1 < nv ? xy[o + k1] : make_int2(0, 0);
+  r.v0 = pre ? pre[0] : (k0 < nv ? xy[o + k0] : make_int2(0, 0));
+  r.v1 = pre ? pre[1] : (k1 < nv ? xy[o + k1] : make_int2(0, 0));
   first = lane_value(r.v0, 0);
   const int2 a64 = nv > kWave ? lane_value(r.v1, 0) : first;
   const int2 a128 = nv > 2 * kWave ? xy[o + 2 * kWave] : first;
@@ -282,6 +286,22 @@ __device__ __forceinline__ bool coords_bad(const Meta& m, int64_t nv) {
   return nv > 0 && m.x0 == INT_MAX;
 }
 
+// The ablations of Section 5.2 (SCCG_F_PIXEL_ONLY, SCCG_F_NO_SEP) count the
+// union directly, over the bounding box of both MBRs, instead of deriving it
+// from the areas.  Counts of one box then travel packed: intersection in
+// the low 32 bits, direct union in the high 32 (a processed box has at most
+// 32767^2 < 2^32 pixels).
+__device__ __forceinline__ bool direct_union(const BatchArgs& a) {
+  return (a.flags & (SCCG_F_PIXEL_ONLY | SCCG_F_NO_SEP)) != 0u;
+}
+
+// Wave total of a lane's intersection count n and, when `direct`, of its
+// union count nu, packed.
+__device__ __forceinline__ uint64_t pack_counts(uint32_t n, uint32_t nu, bool direct) {
+  const uint64_t i = wave_sum_u32(n);
+  return direct ? i | ((uint64_t)wave_sum_u32(nu) << 32) : i;
+}
+
 // ------------------------------------------------------------------ leaves
 // Scatter-and-scan leaves.  The columns of a leaf tile live in lanes in
 // reverse order: in a W-column group (W = 64, or 32 when p and q share the
@@ -333,10 +353,13 @@ __device__ __forceinline__ void slot_xor(M* slots, int k, uint64_t rr) {
 
 // Scatter the leaf edges of one ring into slots[base ..).  The first two
 // 64-vertex chunks come from registers when `r` is given, the rest (or all)
-// from global memory.  Returns the number of edges scattered.
+// from global memory.  With `full` given, edges right of the whole group
+// (they toggle every column) are XORed into *full (per lane) instead of
+// slot 0, so that they do not all hit one LDS address.
 template <typename M>
-__device__ __forceinline__ uint32_t scatter_ring(Ctx& c, const int2* xy, int64_t o, int64_t nv, const RingRegs* r,
-                                                 int tx0, int ty0, int th, int W, M* slots, int base) {
+__device__ __forceinline__ void scatter_ring(Ctx& c, const int2* xy, int64_t o, int64_t nv, const RingRegs* r,
+                                             int tx0, int ty0, int th, int W, M* slots, int base,
+                                             uint64_t* full = nullptr) {
   const int lane = c.lane;
   uint32_t kept = 0;
 #pragma unroll 1
@@ -361,14 +384,18 @@ __device__ __forceinline__ uint32_t scatter_ring(Ctx& c, const int2* xy, int64_t
     int slot = 0;
     uint64_t rr = 0;
     const bool keep = (b0 + lane < (int)nv) && leaf_edge(v, w, tx0, ty0, th, W, slot, rr);
-    if (keep) slot_xor(slots, base + slot, rr);
+    if (keep) {
+      if (full && slot == 0)
+        *full ^= rr;
+      else
+        slot_xor(slots, base + slot, rr);
+    }
     if (c.a->stats_on) kept += (uint32_t)__popcll(ballot(keep));
   }
   if (c.a->stats_on) {
     stat_add(c, 8, (unsigned long long)kept);
     stat_add(c, 10, (unsigned long long)nv);
   }
-  return kept;
 }
 
 // Intersection count of a small pair (box <= 64 x 64 = one leaf tile).
@@ -382,7 +409,8 @@ __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const 
   const int lane = c.lane;
   const int tx0 = pi.box.x0, ty0 = pi.box.y0;
   M* slots = reinterpret_cast<M*>(c.slots);
-  uint32_t n = 0;
+  const bool direct = direct_union(a);
+  uint32_t n = 0, nu = 0;
   if (tw <= 32) {
     slots[lane] = 0;
     wave_sync_lds();
@@ -400,7 +428,10 @@ __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const 
     } else {
       mq = (M)(uint32_t)__shfl_xor((int)(uint32_t)m, 32, kWave);
     }
-    if (lane < 32 && 31 - lane < tw) n = (uint32_t)__popcll((uint64_t)(m & mq));
+    if (lane < 32 && 31 - lane < tw) {
+      n = (uint32_t)__popcll((uint64_t)(m & mq));
+      nu = (uint32_t)__popcll((uint64_t)(m | mq));
+    }
   } else {
     slots[lane] = 0;
     slots[kWave + lane] = 0;
@@ -410,19 +441,22 @@ __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const 
     wave_sync_lds();
     const M mp = wave_prefix_xor<false>(slots[lane]);
     const M mq = wave_prefix_xor<false>(slots[kWave + lane]);
-    if (kWave - 1 - lane < tw) n = (uint32_t)__popcll((uint64_t)(mp & mq));
+    if (kWave - 1 - lane < tw) {
+      n = (uint32_t)__popcll((uint64_t)(mp & mq));
+      nu = (uint32_t)__popcll((uint64_t)(mp | mq));
+    }
   }
   wave_sync_lds();
   if (a.stats_on) {
     stat_add(c, 1, 1ull);
     stat_add(c, 0, 2ull * (unsigned long long)tw * th);
   }
-  return (int64_t)wave_sum_u32(n);
+  return (int64_t)pack_counts(n, nu, direct);
 }
 
 // Pixels of the tile [tx0, tx0+tw) x [ty0, ty0+th) inside both polygons; a
 // polygon known to contain the tile is not scattered (all rows set).
-__device__ __forceinline__ uint32_t leaf_count(Ctx& c, const PairInfo& pi, int tx0, int ty0, int tw, int th, bool kp,
+__device__ __forceinline__ uint64_t leaf_count(Ctx& c, const PairInfo& pi, int tx0, int ty0, int tw, int th, bool kp,
                                                bool kq) {
   const BatchArgs& a = *c.a;
   const int lane = c.lane;
@@ -430,19 +464,150 @@ __device__ __forceinline__ uint32_t leaf_count(Ctx& c, const PairInfo& pi, int t
   slots[lane] = 0;
   slots[kWave + lane] = 0;
   wave_sync_lds();
-  if (!kp) scatter_ring(c, a.A.xy, pi.op, pi.np, (const RingRegs*)nullptr, tx0, ty0, th, kWave, slots, 0);
-  if (!kq) scatter_ring(c, a.B.xy, pi.oq, pi.nq, (const RingRegs*)nullptr, tx0, ty0, th, kWave, slots, kWave);
+  uint64_t fp = 0, fq = 0;
+  if (!kp) scatter_ring(c, a.A.xy, pi.op, pi.np, (const RingRegs*)nullptr, tx0, ty0, th, kWave, slots, 0, &fp);
+  if (!kq) scatter_ring(c, a.B.xy, pi.oq, pi.nq, (const RingRegs*)nullptr, tx0, ty0, th, kWave, slots, kWave, &fq);
   wave_sync_lds();
   const uint64_t full = row_range(0, th);
-  const uint64_t mp = kp ? full : wave_prefix_xor<false>(slots[lane]);
-  const uint64_t mq = kq ? full : wave_prefix_xor<false>(slots[kWave + lane]);
+  const uint64_t mp = kp ? full : wave_prefix_xor<false>(slots[lane]) ^ wave_xor64(fp);
+  const uint64_t mq = kq ? full : wave_prefix_xor<false>(slots[kWave + lane]) ^ wave_xor64(fq);
   wave_sync_lds();
-  const uint32_t n = (kWave - 1 - lane < tw) ? (uint32_t)__popcll(mp & mq) : 0u;
+  const bool in_tile = kWave - 1 - lane < tw;
+  const uint32_t n = in_tile ? (uint32_t)__popcll(mp & mq) : 0u;
+  const uint32_t nu = in_tile ? (uint32_t)__popcll(mp | mq) : 0u;
   if (a.stats_on) {
     stat_add(c, 1, 1ull);
     stat_add(c, 0, (unsigned long long)tw * th * ((kp ? 0 : 1) + (kq ? 0 : 1)));
   }
-  return wave_sum_u32(n);
+  return pack_counts(n, nu, direct_union(a));
+}
+
+// Band rows.  When a split leaves several leaf tiles in one 64-row band,
+// each ring is read once into a compact list of its band edges (4 bytes per
+// edge: X relative to the row's leftmost tile, and the row span), and every
+// tile of the row scatters from that list instead of reading the ring again.
+// Record: dx (11 bits, capped at 2047), lo (7 bits), hi (7 bits).
+
+// Stage the band edges of one ring that lie right of xs; returns the count,
+// or -1 if they do not fit in kBandCap.
+__device__ __forceinline__ int stage_band(Ctx& c, const int2* xy, int64_t o, int64_t nv, int xs, int ty0, int th,
+                                          uint32_t* list) {
+  const int lane = c.lane;
+  int cnt = 0;
+#pragma unroll 1
+  for (int b0 = 0; b0 < (int)nv; b0 += kWave) {
+    const int k = b0 + lane;
+    int2 v = k < (int)nv ? xy[o + k] : make_int2(0, 0);
+    int2 w = next_lane(v);
+    if (lane == kWave - 1 && k + 1 < (int)nv) w = xy[o + k + 1];
+    if (k + 1 == (int)nv) w = xy[o];
+    bool keep = false;
+    uint32_t rec = 0;
+    if (k < (int)nv && v.x == w.x) {
+      const int lo = max(min(v.y, w.y) - ty0, 0);
+      const int hi = min(max(v.y, w.y) - ty0, th);
+      const int dx = v.x - xs;
+      if (lo < hi && dx > 0) {
+        keep = true;
+        rec = (uint32_t)min(dx, 2047) | ((uint32_t)lo << 11) | ((uint32_t)hi << 18);
+      }
+    }
+    const uint64_t b = ballot(keep);
+    const int nk = __popcll(b);
+    if (cnt + nk > kBandCap) return -1;
+    if (keep) list[cnt + lanes_below(b)] = rec;
+    cnt += nk;
+  }
+  stat_add(c, 10, (unsigned long long)nv);
+  return cnt;
+}
+
+// Scatter a staged band list into slots[base ..) for the tile whose left
+// side is `off` pixels right of the list's origin; edges right of the tile
+// go to *full.
+__device__ __forceinline__ void scatter_band(Ctx& c, const uint32_t* list, int n, int off, uint64_t* slots, int base,
+                                             uint64_t& full) {
+  const int lane = c.lane;
+  uint32_t kept = 0;
+#pragma unroll 1
+  for (int k0 = 0; k0 < n; k0 += kWave) {
+    const int k = k0 + lane;
+    const uint32_t rec = k < n ? list[k] : 0u;
+    const int rel = (int)(rec & 0x7ffu) - off;
+    const bool keep = k < n && rel > 0;
+    if (keep) {
+      const uint64_t rr = row_range((int)((rec >> 11) & 0x7fu), (int)((rec >> 18) & 0x7fu));
+      if (rel >= kWave)
+        full ^= rr;
+      else
+        slot_xor(slots, base + kWave - rel, rr);
+    }
+    if (c.a->stats_on) kept += (uint32_t)__popcll(ballot(keep));
+  }
+  stat_add(c, 8, (unsigned long long)kept);
+}
+
+// Count of one tile of a band row from the staged lists (n < 0: the polygon
+// is known to contain the tile).
+__device__ __forceinline__ uint64_t leaf_from_band(Ctx& c, int np, int nq, int off, int tw, int th) {
+  const int lane = c.lane;
+  uint64_t* slots = c.slots;
+  slots[lane] = 0;
+  slots[kWave + lane] = 0;
+  wave_sync_lds();
+  uint64_t fp = 0, fq = 0;
+  if (np >= 0) scatter_band(c, c.band, np, off, slots, 0, fp);
+  if (nq >= 0) scatter_band(c, c.band + kBandCap, nq, off, slots, kWave, fq);
+  wave_sync_lds();
+  const uint64_t all = row_range(0, th);
+  const uint64_t mp = np < 0 ? all : wave_prefix_xor<false>(slots[lane]) ^ wave_xor64(fp);
+  const uint64_t mq = nq < 0 ? all : wave_prefix_xor<false>(slots[kWave + lane]) ^ wave_xor64(fq);
+  wave_sync_lds();
+  const bool in_tile = kWave - 1 - lane < tw;
+  const uint32_t n = in_tile ? (uint32_t)__popcll(mp & mq) : 0u;
+  const uint32_t nu = in_tile ? (uint32_t)__popcll(mp | mq) : 0u;
+  if (c.a->stats_on) {
+    stat_add(c, 1, 1ull);
+    stat_add(c, 0, (unsigned long long)tw * th * ((np < 0 ? 0 : 1) + (nq < 0 ? 0 : 1)));
+  }
+  return pack_counts(n, nu, direct_union(*c.a));
+}
+
+// The leaf tiles `cont` (bit 8j + i = tile (i, j) of side 64 from (bx0, by0))
+// of a split, processed by this wave a band row at a time.  kin_p / kin_q:
+// tiles known to lie inside p / q.
+__device__ __forceinline__ void leaf_rows(Ctx& c, const PairInfo& pi, int bx0, int by0, int bx1, int by1, int gy,
+                                          uint64_t cont, uint64_t kin_p, uint64_t kin_q, uint64_t& acc) {
+  const BatchArgs& a = *c.a;
+  for (int j = 0; j < gy; ++j) {
+    const uint32_t row = (uint32_t)(cont >> (8 * j)) & 0xffu;
+    if (!row) continue;
+    const int ty0 = by0 + kTile * j, th = min(kTile, by1 - ty0);
+    const uint32_t kp_row = (uint32_t)(kin_p >> (8 * j)) & row, kq_row = (uint32_t)(kin_q >> (8 * j)) & row;
+    const int ilo = __ffs((int)row) - 1;
+    const int xs = bx0 + kTile * ilo;
+    int np = -1, nq = -1;
+    bool staged = __popc(row) > 1;
+    if (staged && kp_row != row) {
+      np = stage_band(c, a.A.xy, pi.op, pi.np, xs, ty0, th, c.band);
+      staged = np >= 0;
+    }
+    if (staged && kq_row != row) {
+      nq = stage_band(c, a.B.xy, pi.oq, pi.nq, xs, ty0, th, c.band + kBandCap);
+      staged = nq >= 0;
+    }
+    wave_sync_lds();
+    for (uint32_t r = row; r; r &= r - 1) {
+      const int i = __ffs((int)r) - 1;
+      const int tx0 = bx0 + kTile * i, tw = min(kTile, bx1 - tx0);
+      const bool kp = (kp_row >> i) & 1u, kq = (kq_row >> i) & 1u;
+      if (staged)
+        acc += leaf_from_band(c, kp ? -1 : np, kq ? -1 : nq, tx0 - xs, tw, th);
+      else
+        acc += leaf_count(c, pi, tx0, ty0, tw, th, kp, kq);
+    }
+    wave_sync_lds();
+  }
 }
 
 // One pass over the ring: hover mask H and first-pixel parity mask P of the
@@ -489,10 +654,15 @@ __device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int6
   stat_add(c, 9, (unsigned long long)nv);
 }
 
+// Add a shared pair's partial counts: `n` packed as by pack_counts.  The
+// union starts at |p| + |q| and loses every intersection pixel, or (direct
+// union) starts at 0 and gains every union pixel.
 __device__ __forceinline__ void add_counts(const BatchArgs& a, int64_t pair, uint64_t n) {
   if (n == 0) return;
-  atomicAdd(reinterpret_cast<unsigned long long*>(a.inter + pair), (unsigned long long)n);
-  atomicAdd(reinterpret_cast<unsigned long long*>(a.uni + pair), (unsigned long long)(0 - n));
+  const unsigned long long i = n & 0xffffffffull;
+  const unsigned long long u = direct_union(a) ? (n >> 32) : (0 - i);
+  if (i) atomicAdd(reinterpret_cast<unsigned long long*>(a.inter + pair), i);
+  if (u) atomicAdd(reinterpret_cast<unsigned long long*>(a.uni + pair), u);
 }
 
 // ------------------------------------------------------------------- queue
@@ -580,6 +750,20 @@ __device__ __forceinline__ void emit_children(Ctx& c, const PairInfo& pi, uint64
   }
 }
 
+// Pixels of the cells `m` of a gx x gy grid of side S whose last column and
+// row are lw and lh wide.
+__device__ __forceinline__ uint64_t cells_area(uint64_t m, int gx, int gy, int S, int lw, int lh) {
+  uint64_t add = 0;
+  for (int j = 0; j < gy; ++j) {
+    const uint32_t row = (uint32_t)(m >> (8 * j)) & 0xFFu;
+    if (!row) continue;
+    const uint64_t hgt = (j == gy - 1) ? (uint64_t)lh : (uint64_t)S;
+    const uint32_t last = (row >> (gx - 1)) & 1u;
+    add += hgt * ((uint64_t)(__popc(row) - last) * S + (uint64_t)last * lw);
+  }
+  return add;
+}
+
 // Split box [bx0,bx1) x [by0,by1) of a pair (already known to be a
 // continuing box) into cells of level `cl` (side 64*8^cl).  Cells inside
 // both polygons add their size to `acc`; continuing cells become tasks.
@@ -591,28 +775,38 @@ __device__ __forceinline__ void split_box(Ctx& c, const PairInfo& pi, int bx0, i
   const int gx = (bx1 - bx0 + S - 1) >> ls, gy = (by1 - by0 + S - 1) >> ls;
   const uint64_t valid = rows_bits(0, gy - 1) & spread(cols_bits(0, gx - 1));
   uint64_t Hp = 0, Pp = valid, Hq = 0, Pq = valid;
-  if (!kp) classify(c, a.A.xy, pi.op, pi.np, bx0, by0, bx1, by1, ls, gx, gy, Hp, Pp);
-  if (!kq) classify(c, a.B.xy, pi.oq, pi.nq, bx0, by0, bx1, by1, ls, gx, gy, Hq, Pq);
+  if (a.flags & SCCG_F_PIXEL_ONLY) {
+    Hp = Hq = valid;  // PixelOnly: no sampling boxes, every cell is pixelized
+  } else {
+    if (!kp) classify(c, a.A.xy, pi.op, pi.np, bx0, by0, bx1, by1, ls, gx, gy, Hp, Pp);
+    if (!kq) classify(c, a.B.xy, pi.oq, pi.nq, bx0, by0, bx1, by1, ls, gx, gy, Hq, Pq);
+  }
   const uint64_t in_p = ~Hp & Pp & valid, out_p = ~Hp & ~Pp & valid;
   const uint64_t in_q = ~Hq & Pq & valid, out_q = ~Hq & ~Pq & valid;
   const uint64_t both = in_p & in_q;
-  const uint64_t cont = valid & ~out_p & ~out_q & ~both;
-  // cells inside both polygons contribute their size at once
-  if (both) {
-    const int lw = (bx1 - bx0) - (gx - 1) * S, lh = (by1 - by0) - (gy - 1) * S;
-    uint64_t add = 0;
-    for (int j = 0; j < gy; ++j) {
-      const uint32_t row = (uint32_t)(both >> (8 * j)) & 0xFFu;
-      if (!row) continue;
-      const uint64_t hgt = (j == gy - 1) ? (uint64_t)lh : (uint64_t)S;
-      const uint32_t last = (row >> (gx - 1)) & 1u;
-      add += hgt * ((uint64_t)(__popc(row) - last) * S + (uint64_t)last * lw);
-    }
-    acc += add;
+  uint64_t cont = valid & ~out_p & ~out_q & ~both;
+  uint64_t uni_add = 0;  // cells that stop inside p or q (direct union only)
+  if (direct_union(a)) {
+    // a cell stops only when decided for the intersection (inside both, or
+    // outside one) and for the union (inside one, or outside both)
+    const uint64_t dec_i = both | out_p | out_q, dec_u = in_p | in_q | (out_p & out_q);
+    cont = valid & ~(dec_i & dec_u);
+    uni_add = (in_p | in_q) & valid & ~cont;
   }
+  const int lw = (bx1 - bx0) - (gx - 1) * S, lh = (by1 - by0) - (gy - 1) * S;
+  // cells inside both polygons contribute their size at once
+  if (both) acc += cells_area(both, gx, gy, S, lw, lh);
+  if (uni_add) acc += cells_area(uni_add, gx, gy, S, lw, lh) << 32;
   stat_add(c, 2, 1ull);
-  // one lane per continuing cell
   const int n = __popcll(cont);
+  // leaf tiles that this wave keeps: process them now, a band row at a time
+  const bool publish = pi.hidx >= 0 && !(a.flags & SCCG_F_NO_SPLIT_QUEUE) && n >= a.min_cells_to_queue;
+  if (cl == 0 && n && !publish) {
+    const uint64_t kn = (a.flags & SCCG_F_NO_KNOWN_INSIDE) ? 0ull : ~0ull;
+    leaf_rows(c, pi, bx0, by0, bx1, by1, gy, cont, in_p & kn, in_q & kn, acc);
+    return;
+  }
+  // one lane per continuing cell
   bool has = false;
   uint64_t word = 0;
   if ((cont >> c.lane) & 1ull) {
@@ -704,29 +898,37 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   Ctx c;
   c.a = &args;
   c.lane = lane_id();
-  c.slots = reinterpret_cast<uint64_t*>(smem + (size_t)wave * kLdsPerWave);
-  c.local = reinterpret_cast<uint64_t*>(smem + (size_t)wave * kLdsPerWave + kLeafSlots * 8);
-  c.meta = reinterpret_cast<ChunkMeta*>(smem + (size_t)wave * kLdsPerWave + kLeafSlots * 8 + kLocalCap * 8);
+  unsigned char* lds = smem + (size_t)wave * kLdsPerWave;
+  c.slots = reinterpret_cast<uint64_t*>(lds);
+  c.band = reinterpret_cast<uint32_t*>(lds + kLeafSlots * 8);
+  c.local = reinterpret_cast<uint64_t*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4);
+  c.meta = reinterpret_cast<ChunkMeta*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8);
   c.lsp = 0;
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
   const BatchArgs& a = args;
   const unsigned long long n_heavy = a.st->l_count.v;
+  // Boxes reach a queue only from splits of heavy pairs with at least
+  // min_cells_to_queue continuing cells (at most 64): otherwise no wave ever
+  // needs to look at the queues.
+  const bool queues_used = n_heavy > 0 && !(a.flags & SCCG_F_NO_SPLIT_QUEUE) && a.min_cells_to_queue <= kWave;
   const unsigned long long n_chunks = ((unsigned long long)a.n_pairs + a.chunk - 1) / a.chunk;
   uint32_t l_empty = 0, s_empty = 0;  // streams this wave found exhausted (wave-uniform)
   int64_t ch_i0 = 0;                  // the sweep chunk in hand: pairs ch_i0 + [ch_j, ch_cnt)
   int ch_cnt = 0, ch_j = 0;
-  int pf_j = -1;                       // chunk index whose first vertices are in pf_vp, pf_vq
-  int2 pf_vp = make_int2(0, 0), pf_vq = make_int2(0, 0), cur_vp = pf_vp, cur_vq = pf_vq;
+  int pf_j = -1;  // chunk index whose first 128 vertices per ring are in pf_vp, pf_vq
+  int2 pf_vp[2] = {make_int2(0, 0), make_int2(0, 0)}, pf_vq[2] = {make_int2(0, 0), make_int2(0, 0)};
+  int2 cur_vp[2] = {pf_vp[0], pf_vp[1]}, cur_vq[2] = {pf_vq[0], pf_vq[1]};
   for (;;) {
     // ------------------------------------------------ pick one piece of work
     PairInfo pi;
-    bool use_pf = false;  // cur_vp / cur_vq hold the pair's first vertices
+    bool use_pf = false;  // cur_vp / cur_vq hold the pair's first 128 vertices per ring
     uint64_t task = 0;    // large-path task word, 0 = go through the small-pair path first
     bool shared = false;  // outputs are shared with other waves: add atomically
     uint64_t w;
     bool have = false;
-    if (queue_claim(c, false, &w)) {
+    // the home queue first, but not between the pairs of a sweep chunk
+    if (queues_used && (ch_j >= ch_cnt || l_empty != 0xffu) && queue_claim(c, false, &w)) {
       pi = heavy_info(a, task_decode(w).hidx);
       task = w;
       shared = have = true;
@@ -803,12 +1005,14 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
       pi.oq = uniform64(m.oq);
       pi.nq = uniform(m.nq);
       have = true;
-      // the first 64 vertices of both rings of this pair may already be in
+      // the first 128 vertices of both rings of this pair may already be in
       // registers; start those of the next pair of the chunk
       use_pf = pf_j == j;
       if (use_pf) {
-        cur_vp = pf_vp;
-        cur_vq = pf_vq;
+        cur_vp[0] = pf_vp[0];
+        cur_vp[1] = pf_vp[1];
+        cur_vq[0] = pf_vq[0];
+        cur_vq[1] = pf_vq[1];
       }
       pf_j = -1;
       if (ch_j < ch_cnt) {
@@ -816,15 +1020,17 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
         if (uniform(m2.cls) == kClsSweep) {
           const int64_t op2 = uniform64(m2.op), oq2 = uniform64(m2.oq);
           const int np2 = uniform(m2.np), nq2 = uniform(m2.nq);
-          pf_vp = c.lane < np2 ? a.A.xy[op2 + c.lane] : make_int2(0, 0);
-          pf_vq = c.lane < nq2 ? a.B.xy[oq2 + c.lane] : make_int2(0, 0);
+          pf_vp[0] = c.lane < np2 ? a.A.xy[op2 + c.lane] : make_int2(0, 0);
+          pf_vq[0] = c.lane < nq2 ? a.B.xy[oq2 + c.lane] : make_int2(0, 0);
+          pf_vp[1] = c.lane + kWave < np2 ? a.A.xy[op2 + kWave + c.lane] : make_int2(0, 0);
+          pf_vq[1] = c.lane + kWave < nq2 ? a.B.xy[oq2 + kWave + c.lane] : make_int2(0, 0);
           pf_j = ch_j;
         }
       }
     }
     // nothing of its own left: help with every queue, then stop
     if (!have) {
-      if (!queue_claim(c, true, &w)) break;
+      if (!queues_used || !queue_claim(c, true, &w)) break;
       pi = heavy_info(a, task_decode(w).hidx);
       task = w;
       shared = have = true;
@@ -837,12 +1043,12 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
       Meta mp, mq;
       int64_t ap, aq;
       RingRegs rp, rq;
-      ring_extent(a.A.xy, pi.op, pi.np, c.lane, rp, mp, ap, use_pf ? &cur_vp : nullptr);
-      ring_extent(a.B.xy, pi.oq, pi.nq, c.lane, rq, mq, aq, use_pf ? &cur_vq : nullptr);
+      ring_extent(a.A.xy, pi.op, pi.np, c.lane, rp, mp, ap, use_pf ? cur_vp : nullptr);
+      ring_extent(a.B.xy, pi.oq, pi.nq, c.lane, rq, mq, aq, use_pf ? cur_vq : nullptr);
       if (c.lane == 0 && (coords_bad(mp, pi.np) || coords_bad(mq, pi.nq))) latch_error(a.err, kErrCoord);
       if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[12], (unsigned long long)(pi.np + pi.nq));
       pi.area_sum = ap + aq;
-      pi.box = pair_box(mp, mq);
+      pi.box = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
       const int bw = pi.box.x1 - pi.box.x0, bh = pi.box.y1 - pi.box.y0;
       if (pi.box.x0 >= pi.box.x1 || pi.box.y0 >= pi.box.y1) {
         // empty pair box: nothing in common
@@ -866,10 +1072,20 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
       }
     }
     // --------------------------------------------------------- large path
-    if (task != 0) I = (int64_t)run_large(c, pi, task);
+    if (task != 0) {
+      // the next pair's prefetched vertices are dropped: the large path
+      // needs the registers more than the next pair needs the head start
+      pf_j = -1;
+      pf_vp[0] = pf_vp[1] = pf_vq[0] = pf_vq[1] = make_int2(0, 0);
+      cur_vp[0] = cur_vp[1] = cur_vq[0] = cur_vq[1] = make_int2(0, 0);
+      I = (int64_t)run_large(c, pi, task);
+    }
     if (c.lane == 0) {
       if (shared) {
         add_counts(a, pi.pair, (uint64_t)I);
+      } else if (direct_union(a)) {
+        a.inter[pi.pair] = I & 0xffffffffll;
+        a.uni[pi.pair] = (I >> 32) & 0xffffffffll;
       } else {
         a.inter[pi.pair] = I;
         a.uni[pi.pair] = pi.area_sum - I;
@@ -942,12 +1158,12 @@ __global__ void __launch_bounds__(256) k_batch_heavy_meta(BatchArgs a) {
     ring_scan(a.B.xy, oq, a.B.off[ib + 1] - oq, lane, mq, aq);
     if (lane != 0) continue;
     if (coords_bad(mp, a.A.off[ia + 1] - op) || coords_bad(mq, a.B.off[ib + 1] - oq)) latch_error(a.err, kErrCoord);
-    const Meta b = pair_box(mp, mq);
+    const Meta b = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
     *reinterpret_cast<int4*>(a.hbox + k) = make_int4(b.x0, b.y0, b.x1, b.y1);
     const int64_t w = (int64_t)b.x1 - b.x0, h = (int64_t)b.y1 - b.y0;
     uint8_t cls = kClsDone;
     a.inter[i] = 0;
-    a.uni[i] = ap + aq;
+    a.uni[i] = direct_union(a) ? 0 : ap + aq;
     if (b.x0 >= b.x1 || b.y0 >= b.y1) {
       cls = kClsDone;
     } else if (w > kMaxSide || h > kMaxSide) {

@@ -100,6 +100,16 @@ __device__ __forceinline__ Meta pair_box(const Meta& p, const Meta& q) {
   return b;
 }
 
+// Bounding box of MBR(p) ∪ MBR(q) (an empty MBR contributes nothing).
+__device__ __forceinline__ Meta union_box(const Meta& p, const Meta& q) {
+  Meta b;
+  b.x0 = min(p.x0, q.x0);
+  b.y0 = min(p.y0, q.y0);
+  b.x1 = max(p.x1, q.x1);
+  b.y1 = max(p.y1, q.y1);
+  return b;
+}
+
 __device__ __forceinline__ Meta load_meta(const Meta* m, int64_t k) {
   const int4 v = *reinterpret_cast<const int4*>(m + k);
   return Meta{v.x, v.y, v.z, v.w};

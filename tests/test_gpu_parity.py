@@ -151,6 +151,9 @@ BATCH_TUNINGS = [
     dict(flags=sccg.SCCG_F_NO_LPT), dict(flags=sccg.SCCG_F_NO_GRAPH), dict(queue_chunk=1), dict(queue_chunk=64), dict(queue_chunk=37),
     dict(waves_per_wg=1), dict(waves_per_wg=8), dict(n_queues=1), dict(grid=3), dict(heavy_verts=1),
     dict(heavy_verts=1, min_queue_cells=1, queue_cap=50), dict(heavy_verts=100000),
+    dict(flags=sccg.SCCG_F_NO_SEP), dict(flags=sccg.SCCG_F_PIXEL_ONLY),
+    dict(flags=sccg.SCCG_F_NO_SEP, heavy_verts=1, min_queue_cells=1),
+    dict(flags=sccg.SCCG_F_PIXEL_ONLY | sccg.SCCG_F_NO_KNOWN_INSIDE, heavy_verts=1, min_queue_cells=1),
 ]
 
 
@@ -210,6 +213,35 @@ def test_degenerate_rings(ctx, mode):
     gI, gU = run(ctx, device_workload(A, B, idx, idx), mode)
     assert gI.tolist() == [25, 25, 25, 0, 0, 0]
     assert gU.tolist() == [25, 25, 25, 50, 50, 50]
+
+
+def _comb(width, height, base, tooth, gap):
+    """A comb: `base` full rows, then teeth `tooth` px wide every
+    tooth + gap px up to `height`: many vertical edges in every 64-row band."""
+    m = np.zeros((height, width), np.uint8)
+    m[:base, :] = 1
+    for x in range(0, width, tooth + gap):
+        m[base:, x:x + tooth] = 1
+    ring = sccg_gen.trace_mask(m)
+    assert ring is not None
+    return ring
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_dense_band_rows(ctx, mode):
+    """Rings with more vertical edges in one 64-row band than a band list
+    holds (the per-tile path takes over), rows of several leaf tiles, and
+    tiles known to lie inside one polygon; counts equal the oracle's."""
+    comb = _comb(520, 150, 8, 2, 2)          # about 260 vertical edges per band
+    sparse = _comb(520, 150, 8, 2, 30)       # a few dozen per band
+    rect = band_ring([20, 130], [40], [480])
+    big = band_ring([-10, 200], [-10], [600])
+    A = concat([comb, comb, comb, sparse, sparse, comb])
+    B = concat([comb + np.array([1, 3], np.int32), rect, big, sparse + np.array([5, -2], np.int32), rect, sparse])
+    idx = np.arange(6, dtype=np.int32)
+    eI, eU = oracle.area_pairs(A, B, idx, idx, form=oracle.ROWS)
+    gI, gU = run(ctx, device_workload(A, B, idx, idx), mode)
+    assert_exact(gI, gU, eI, eU, f"dense band rows mode {mode}")
 
 
 @pytest.mark.parametrize("mode", MODES)
