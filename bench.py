@@ -124,9 +124,22 @@ def cpu_baseline(wl, I_gpu, U_gpu, seconds: float, seed: int):
         done += len(sel)
         if not (np.array_equal(eI, I_gpu[sel]) and np.array_equal(eU, U_gpu[sel])):
             exact = False
+    # one core on a fixed 1% subset (every 100th pair)
+    sub = np.arange(0, wl.n_pairs, 100)
+    t = time.perf_counter()
+    oracle.area_pairs(wl.A, wl.B, wl.pa[sub], wl.pb[sub], form=oracle.ROWS, threads=1)
+    one = len(sub) / (time.perf_counter() - t)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": done / t_total, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} pairs drawn uniformly (seed {seed}) from the same workload, row-bucketed "
-                      f"oracle form, {t_total:.1f} s of CPU time"}, exact, done
+                      f"oracle form, {t_total:.1f} s of CPU time",
+            "one_core_pairs_per_s": one, "one_core_sample": f"every 100th pair ({len(sub)} pairs)",
+            "nproc": os.cpu_count(), "cpu_model": model}, exact, done
 
 
 def serve_bench(args):
