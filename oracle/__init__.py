@@ -51,6 +51,10 @@ def load_library(path: str):
     lib.sccg_oracle_jaccard_sets.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
+    lib.sccg_oracle_join_sets.restype = ctypes.c_int64
+    lib.sccg_oracle_join_sets.argtypes = [ctypes.POINTER(_Polys), ctypes.POINTER(_Polys), ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]
     return lib
 
 
@@ -125,3 +129,23 @@ def jaccard_sets(set_off, I, U, include_zero: bool = False):
         n = len(i_k)
         jp[s] = math.fsum(ratios.tolist()) / n if n else 0.0
     return si, su, nn, j, jp
+
+
+def join_sets(A, B, a_set_off, b_set_off):
+    """Candidate pairs with intersecting MBRs, per set (Section 4.1's filter
+    stage), by testing every pair of each set: (pa, pb, set_off), ordered by
+    set, then b, then a."""
+    lib = _load()
+    sa, ka = _polys(A)
+    sb, kb = _polys(B)
+    ao = _c(a_set_off, np.int64)
+    bo = _c(b_set_off, np.int64)
+    ns = len(ao) - 1
+    so = np.zeros(ns + 1, np.int64)
+    total = lib.sccg_oracle_join_sets(ctypes.byref(sa), ctypes.byref(sb), ns, ao.ctypes.data, bo.ctypes.data, 0,
+                                      None, None, so.ctypes.data)
+    pa = np.zeros(total, np.int32)
+    pb = np.zeros(total, np.int32)
+    lib.sccg_oracle_join_sets(ctypes.byref(sa), ctypes.byref(sb), ns, ao.ctypes.data, bo.ctypes.data, total,
+                              pa.ctypes.data, pb.ctypes.data, so.ctypes.data)
+    return pa, pb, so

@@ -15,6 +15,10 @@
  *    vertical edge with X > x whose y-span [min, max) holds y.
  *  - Polygon area (Section 3.2): the shoelace sum, cyclic, absolute value
  *    taken per polygon.
+ *  - The filter stage (Section 4.1): the candidate pairs of two polygon sets
+ *    are those whose MBRs intersect; here MBR = pixel extent of the vertices,
+ *    and two MBRs intersect when they share a pixel.  Every pair of a set is
+ *    tested (no index).
  *  - Jaccard (Section 2.1): J = total intersection / total union of a set of
  *    pairs.  J' (Equation 1, the mean of the per-pair ratios over the pairs
  *    with non-zero intersection) is formed in the Python wrapper.
@@ -225,4 +229,42 @@ void sccg_oracle_jaccard_sets(int64_t n_sets, const int64_t* set_off, const int6
     out_n[s] = n;
     out_j[s] = (su > 0) ? (double)si / (double)su : 0.0;
   }
+}
+
+static void poly_mbr(const sccg_oracle_polys* P, int64_t k, int64_t* m) {
+  const int64_t o = P->offsets[k], nv = P->offsets[k + 1] - o;
+  if (nv <= 0) { /* no vertices: an MBR that holds no pixel */
+    m[0] = m[1] = 1;
+    m[2] = m[3] = 0;
+    return;
+  }
+  ring_mbr(P->xy + 2 * o, nv, &m[0], &m[1], &m[2], &m[3]);
+}
+
+int64_t sccg_oracle_join_sets(const sccg_oracle_polys* A, const sccg_oracle_polys* B, int64_t n_sets,
+                              const int64_t* a_off, const int64_t* b_off, int64_t cap, int32_t* out_pa,
+                              int32_t* out_pb, int64_t* out_set_off) {
+  int64_t total = 0;
+  for (int64_t s = 0; s < n_sets; ++s) {
+    if (out_set_off) out_set_off[s] = total;
+    for (int64_t b = b_off[s]; b < b_off[s + 1]; ++b) {
+      int64_t mb[4];
+      poly_mbr(B, b, mb);
+      for (int64_t a = a_off[s]; a < a_off[s + 1]; ++a) {
+        int64_t ma[4];
+        poly_mbr(A, a, ma);
+        const int64_t x0 = ma[0] > mb[0] ? ma[0] : mb[0], x1 = ma[2] < mb[2] ? ma[2] : mb[2];
+        const int64_t y0 = ma[1] > mb[1] ? ma[1] : mb[1], y1 = ma[3] < mb[3] ? ma[3] : mb[3];
+        if (x0 < x1 && y0 < y1) {
+          if (total < cap) {
+            out_pa[total] = (int32_t)a;
+            out_pb[total] = (int32_t)b;
+          }
+          ++total;
+        }
+      }
+    }
+  }
+  if (out_set_off) out_set_off[n_sets] = total;
+  return total;
 }

@@ -50,6 +50,16 @@ void sccg_oracle_jaccard_sets(int64_t n_sets, const int64_t* set_off, const int6
                               const int64_t* uni, int include_zero, int64_t* out_sum_i,
                               int64_t* out_sum_u, int64_t* out_n, double* out_j);
 
+/* The filter stage of Section 4.1: candidate pairs with intersecting MBRs.
+ * For each set s, every (a, b) with a in [a_off[s], a_off[s+1]) and b in
+ * [b_off[s], b_off[s+1]) whose MBRs (the pixel extents [min x, max x) x
+ * [min y, max y) of their vertices) share at least one pixel, ordered by set,
+ * then b, then a.  Writes the first min(total, cap) pairs and the per-set
+ * offsets (out_set_off[n_sets+1], counting every pair); returns the total. */
+int64_t sccg_oracle_join_sets(const sccg_oracle_polys* A, const sccg_oracle_polys* B, int64_t n_sets,
+                              const int64_t* a_off, const int64_t* b_off, int64_t cap, int32_t* out_pa,
+                              int32_t* out_pb, int64_t* out_set_off);
+
 #ifdef __cplusplus
 }
 #endif

@@ -54,6 +54,7 @@ def _load():
     lib.sccg_gen_sets_free.argtypes = [ctypes.c_void_p]
     lib.sccg_gen_sets_counts.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.sccg_gen_sets_copy.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 7
+    lib.sccg_gen_sets_poly_off.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.sccg_gen_trace_mask.restype = ctypes.c_int64
     lib.sccg_gen_trace_mask.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_int64]
@@ -163,6 +164,8 @@ class SetWorkload:
     pb: np.ndarray
     set_off: np.ndarray
     stats: dict
+    a_set_off: np.ndarray = None  # int64 [n_tiles+1]: A polygons of tile t
+    b_set_off: np.ndarray = None  # int64 [n_tiles+1]: B polygons of tile t
 
     @property
     def n_pairs(self) -> int:
@@ -195,10 +198,13 @@ def sets(n_tiles: int = 64, tile_side: int = 8192, cell: int = 64, seed: int | N
         pb = np.zeros(npairs, np.int32)
         so = np.zeros(nt + 1, np.int64)
         lib.sccg_gen_sets_copy(h, _ptr(offA), _ptr(xyA), _ptr(offB), _ptr(xyB), _ptr(pa), _ptr(pb), _ptr(so))
+        aso = np.zeros(nt + 1, np.int64)
+        bso = np.zeros(nt + 1, np.int64)
+        lib.sccg_gen_sets_poly_off(h, _ptr(aso), _ptr(bso))
     finally:
         lib.sccg_gen_sets_free(h)
     stats = dict(tiles=nt, polys_a=nA, polys_b=nB, pairs=npairs, tile_side=tile_side, cell=cell)
-    return SetWorkload(seed, Polys(offA, xyA), Polys(offB, xyB), pa, pb, so, stats)
+    return SetWorkload(seed, Polys(offA, xyA), Polys(offB, xyB), pa, pb, so, stats, aso, bso)
 
 
 def trace_mask(bits: np.ndarray) -> np.ndarray | None:

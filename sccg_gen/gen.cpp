@@ -713,4 +713,15 @@ void sccg_gen_sets_copy(const sccg_gen_sets* h, int64_t* offA, int32_t* xyA, int
   }
 }
 
+// Polygon ranges of each tile: A polygons [a_off[t], a_off[t+1]), B polygons
+// [b_off[t], b_off[t+1]) (both [n_tiles+1]).
+void sccg_gen_sets_poly_off(const sccg_gen_sets* h, int64_t* a_off, int64_t* b_off) {
+  a_off[0] = 0;
+  b_off[0] = 0;
+  for (size_t t = 0; t < h->d.tiles.size(); ++t) {
+    a_off[t + 1] = a_off[t] + (int64_t)h->d.tiles[t].A.size();
+    b_off[t + 1] = b_off[t] + (int64_t)h->d.tiles[t].B.size();
+  }
+}
+
 }  // extern "C"

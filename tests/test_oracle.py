@@ -323,3 +323,55 @@ def test_set_workload_join_is_exact():
             hit = set(a_ids[(x0 < x1) & (y0 < y1)].tolist())
             assert hit == by_b.get(b, set()), b
     assert wl.stats["polys_a"] > 0 and wl.n_pairs > 0
+
+
+def test_join_closed_forms():
+    """MBRs that only touch along a side or at a corner share no pixel; one
+    pixel of overlap is enough; a ring without vertices meets nothing."""
+    sq = band_ring([0, 5], [0], [5])
+    A = concat([sq])
+    cases = [(sq + np.array([5, 0], np.int32), 0), (sq + np.array([5, 5], np.int32), 0),
+             (sq + np.array([4, 4], np.int32), 1), (sq + np.array([-4, 0], np.int32), 1),
+             (np.zeros((0, 2), np.int32), 0), (band_ring([1, 2], [1], [2]), 1)]
+    B = concat([r for r, _ in cases])
+    pa, pb, so = oracle.join_sets(A, B, np.array([0, 1], np.int64), np.array([0, len(cases)], np.int64))
+    assert pb.tolist() == [k for k, (_, hit) in enumerate(cases) if hit] and set(pa.tolist()) <= {0}
+    assert so.tolist() == [0, len(pb)]
+
+
+def test_join_brute_force_and_sets():
+    """Random rectangles in three sets against a brute-force overlap test;
+    pairs never cross sets; order is set, then b, then a."""
+    rng = np.random.default_rng(21)
+    ra, rb, a_off, b_off = [], [], [0], [0]
+    for s in range(3):
+        na, nb = int(rng.integers(0, 40)), int(rng.integers(0, 40))
+        for _ in range(na):
+            x, y, w, h = (int(v) for v in rng.integers([0, 0, 1, 1], [100, 100, 20, 20]))
+            ra.append(band_ring([y, y + h], [x], [x + w]))
+        for _ in range(nb):
+            x, y, w, h = (int(v) for v in rng.integers([0, 0, 1, 1], [100, 100, 20, 20]))
+            rb.append(band_ring([y, y + h], [x], [x + w]))
+        a_off.append(a_off[-1] + na)
+        b_off.append(b_off[-1] + nb)
+    A, B = concat(ra), concat(rb)
+    pa, pb, so = oracle.join_sets(A, B, np.array(a_off), np.array(b_off))
+    expect = []
+    for s in range(3):
+        for b in range(b_off[s], b_off[s + 1]):
+            rbx = rb[b]
+            for a in range(a_off[s], a_off[s + 1]):
+                rax = ra[a]
+                if (max(rax[:, 0].min(), rbx[:, 0].min()) < min(rax[:, 0].max(), rbx[:, 0].max()) and
+                        max(rax[:, 1].min(), rbx[:, 1].min()) < min(rax[:, 1].max(), rbx[:, 1].max())):
+                    expect.append((a, b))
+    assert list(zip(pa.tolist(), pb.tolist())) == expect
+    assert so[-1] == len(expect)
+
+
+def test_join_agrees_with_grid_join():
+    """The oracle's all-pairs test and the generator's uniform-grid join
+    (reference-point dedup) are independent and give the same pair list."""
+    wl = sccg_gen.sets(n_tiles=3, tile_side=1536, cell=64)
+    pa, pb, so = oracle.join_sets(wl.A, wl.B, wl.a_set_off, wl.b_set_off)
+    assert np.array_equal(pa, wl.pa) and np.array_equal(pb, wl.pb) and np.array_equal(so, wl.set_off)
