@@ -487,6 +487,34 @@ def main(argv=None):
             sets_info["sets_bit_exact"] = bool(np.array_equal(gsets[0], osi) and np.array_equal(gsets[1], osu) and
                                                np.array_equal(gsets[3], oj) and np.array_equal(gsets[4], ojp))
     if with_sets:
+        # the filter stage on the device too: join, pair counts and set sums
+        with torch.cuda.stream(stream):
+            dao = torch.from_numpy(wl.a_set_off).to(dev)
+            dbo = torch.from_numpy(wl.b_set_off).to(dev)
+            jctx = sccg.Context(0, stream=stream, **tuned)
+            jpa, jpb, jso = jctx.join_sets(dA, dB, dao, dbo)
+            jctx.sync()
+            same_join = bool(np.array_equal(jpa.cpu().numpy(), wl.pa) and np.array_equal(jpb.cpu().numpy(), wl.pb)
+                             and np.array_equal(jso.cpu().numpy(), wl.set_off))
+            reps = max(1, args.steps // 4)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                jctx.join_sets(dA, dB, dao, dbo, cap=wl.n_pairs)
+            torch.cuda.synchronize()
+            join_ms = (time.perf_counter() - t) * 1e3 / reps
+            t = time.perf_counter()
+            for _ in range(reps):
+                jpa, jpb, jso = jctx.join_sets(dA, dB, dao, dbo, cap=wl.n_pairs)
+                jI, jU = jctx.area_pairs(dA, dB, jpa, jpb, mode=sccg.SCCG_BATCHED)
+                jctx.jaccard_sets(jso, jI, jU)
+            torch.cuda.synchronize()
+            e2e_ms = (time.perf_counter() - t) * 1e3 / reps
+            jctx.sync()
+            jctx.close()
+        log(f"device join: {join_ms:.3f} ms, equals the host join: {same_join}; join + pairs + sets: {e2e_ms:.3f} ms")
+        sets_info["device_join"] = {"join_ms": join_ms, "equals_host_join": same_join,
+                                    "end_to_end_ms": e2e_ms, "end_to_end_pairs_per_s": wl.n_pairs / (e2e_ms / 1e3)}
         sets_info.update({"n_sets": int(len(wl.set_off) - 1), "J_mean": float(np.mean(gsets[3])),
                           "J_min": float(np.min(gsets[3])), "J_max": float(np.max(gsets[3])),
                           "Jprime_mean": float(np.mean(gsets[4]))})

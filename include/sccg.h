@@ -157,6 +157,29 @@ int sccg_jaccard_sets(sccg_ctx* ctx, int64_t n_sets, const int64_t* set_pair_off
                       const int64_t* uni, uint32_t flags, int64_t* out_sum_i, int64_t* out_sum_u,
                       int64_t* out_n_contrib, double* out_j, double* out_jprime);
 
+/* The filter stage of Section 4.1 on the device: candidate pairs of two
+ * polygon sets are the pairs whose MBRs intersect.  For each set s, every
+ * (a, b) with a in [a_set_off[s], a_set_off[s+1]) and b in
+ * [b_set_off[s], b_set_off[s+1]) whose MBRs (the pixel extents
+ * [min x, max x) x [min y, max y) of their vertices) share at least one
+ * pixel, each once, ordered by set, then b, then a: the input that
+ * sccg_area_pairs and sccg_jaccard_sets take.
+ *   a_set_off, b_set_off: device int64 [n_sets+1], non-decreasing, within
+ *     [0, n_polys] of A and B.
+ *   cell: side in pixels of the uniform grid that indexes each set's A
+ *     polygons (0 = 64); a set whose grid would exceed 2^24 cells latches
+ *     SCCG_E_RANGE and yields no pairs.
+ *   out_pa, out_pb: device int32 [cap]; written only if the total fits.
+ *   out_set_off: device int64 [n_sets+1], offsets of each set's pairs
+ *     (always written, counting every pair).
+ *   *out_total (host): the number of pairs; if it exceeds cap, no pair is
+ *     written: call again with cap >= *out_total.
+ * The call waits for the context's stream three times (to size its scratch
+ * and to read the total), so it cannot be captured in a HIP graph. */
+int sccg_join_sets(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, int64_t n_sets,
+                   const int64_t* a_set_off, const int64_t* b_set_off, int32_t cell, int64_t cap,
+                   int32_t* out_pa, int32_t* out_pb, int64_t* out_set_off, int64_t* out_total);
+
 /* Check every ring of P: at least 4 vertices and every edge axis-aligned.
  * Writes the smallest bad polygon index, or -1, to *out_first_bad (device
  * int64).  Asynchronous; read the value after sccg_sync. */

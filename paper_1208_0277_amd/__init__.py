@@ -43,7 +43,7 @@ SCCG_J_INCLUDE_ZERO = 1
 EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
            "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
            "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version",
-           "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
+           "sccg_join_sets", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
            "sccg_server_clock", "sccg_server_last_error", "sccg_server_destroy")
 
 SERVER_STAT_KEYS = ("jobs_submitted", "jobs_done", "launches", "pairs_done", "peak_resident_vertices",
@@ -124,6 +124,8 @@ def load_library(path: str = LIB_PATH):
         "sccg_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "sccg_last_error": ([P], ctypes.c_char_p),
         "sccg_version": ([], ctypes.c_char_p),
+        "sccg_join_sets": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, ctypes.c_int32,
+                            i64, P, P, P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "sccg_server_create": ([ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(sccg_server_config),
                                 ctypes.POINTER(sccg_params)], ctypes.c_int),
         "sccg_server_submit": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P,
@@ -288,6 +290,32 @@ class Context:
         self._rc(self.lib.sccg_jaccard_sets(self.h, ns, _ptr(set_pair_off), _ptr(inter), _ptr(uni), flags, _ptr(si),
                                             _ptr(su), _ptr(nn), _ptr(j), _ptr(jp)))
         return si, su, nn, j, jp
+
+    def join_sets(self, A: DevicePolys, B: DevicePolys, a_set_off, b_set_off, cell: int = 64, cap: int | None = None):
+        """Queue sccg_join_sets: candidate pairs by MBR intersection per set.
+        Returns (pair_a, pair_b, set_off) device tensors; retries once with a
+        larger buffer when `cap` (default 4 x |B|) is too small."""
+        import torch
+        _check_dev(a_set_off, torch.int64, "a_set_off")
+        _check_dev(b_set_off, torch.int64, "b_set_off")
+        ns = int(a_set_off.shape[0]) - 1
+        if int(b_set_off.shape[0]) - 1 != ns:
+            raise ValueError("a_set_off and b_set_off differ in length")
+        dev = a_set_off.device
+        cap = 4 * max(B.n, 1) if cap is None else cap
+        so = torch.empty(ns + 1, dtype=torch.int64, device=dev)
+        cA, cB = A.c(), B.c()
+        for _ in range(2):
+            pa = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            pb = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            total = ctypes.c_int64(0)
+            self._rc(self.lib.sccg_join_sets(self.h, ctypes.byref(cA), ctypes.byref(cB), ns, _ptr(a_set_off),
+                                             _ptr(b_set_off), cell, cap, _ptr(pa), _ptr(pb), _ptr(so),
+                                             ctypes.byref(total)))
+            if total.value <= cap:
+                return pa[:total.value], pb[:total.value], so
+            cap = total.value
+        raise SccgError(SCCG_E_STATE, "join output did not fit after resizing")
 
     def validate_polys(self, P: DevicePolys):
         import torch

@@ -43,6 +43,18 @@ struct sccg_ctx {
   // graph cache for the batched sequence
   hipGraphExec_t gexec = nullptr;
   std::string gkey;
+  // filter-stage scratch
+  int4* j_bbox = nullptr;
+  int4* j_grid = nullptr;
+  int64_t* j_cells = nullptr;
+  int64_t* j_cell_base = nullptr;
+  int64_t* j_sums = nullptr;
+  int32_t* j_count = nullptr;
+  int64_t* j_start = nullptr;
+  int32_t* j_list = nullptr;
+  int32_t* j_bcount = nullptr;
+  int64_t* j_bstart = nullptr;
+  int64_t j_cap[10] = {};
   // kernel timing
   int timing_on = 0;
   std::vector<hipEvent_t> ev;  // start/stop pairs
@@ -158,6 +170,18 @@ int ensure_pairs(sccg_ctx* c, int64_t n) {
   return SCCG_OK;
 }
 
+// Grow a filter-stage buffer to at least n elements (waits for the stream
+// before freeing the old one).
+template <typename T>
+int need(sccg_ctx* c, T** ptr, int64_t& cap, int64_t n, const char* what) {
+  if (n <= cap && *ptr) return SCCG_OK;
+  (void)hipStreamSynchronize(c->stream);
+  const int64_t want = n + n / 4 + 64;
+  int r = grow(c, ptr, want, what);
+  cap = r ? 0 : want;
+  return r;
+}
+
 int ensure_queue(sccg_ctx* c) {
   const int64_t want = (int64_t)c->p.n_queues * c->p.queue_cap;
   if (c->queue && c->queue_slots == want) return SCCG_OK;
@@ -262,8 +286,10 @@ int sccg_destroy(sccg_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   drop_graph(c);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-  void* ptrs[] = {c->metaA, c->areaA, c->bigA, c->metaB, c->areaB, c->bigB, c->big_count, c->err,
-                  c->cls,   c->l_list, c->hbox, c->st, c->queue, c->plain_stats};
+  void* ptrs[] = {c->metaA,  c->areaA,  c->bigA,        c->metaB,  c->areaB,   c->bigB,    c->big_count,
+                  c->err,    c->cls,    c->l_list,      c->hbox,   c->st,      c->queue,   c->plain_stats,
+                  c->j_bbox, c->j_grid, c->j_cells,     c->j_cell_base, c->j_sums, c->j_count, c->j_start,
+                  c->j_list, c->j_bcount, c->j_bstart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -483,6 +509,86 @@ int sccg_jaccard_sets(sccg_ctx* c, int64_t n_sets, const int64_t* set_pair_off, 
   hipError_t e = launch_jaccard(n_sets, set_pair_off, inter, uni, flags, out_sum_i, out_sum_u, out_n_contrib, out_j,
                                 out_jprime, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "jaccard");
+  return SCCG_OK;
+}
+
+int sccg_join_sets(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64_t n_sets, const int64_t* a_set_off,
+                   const int64_t* b_set_off, int32_t cell, int64_t cap, int32_t* out_pa, int32_t* out_pb,
+                   int64_t* out_set_off, int64_t* out_total) {
+  if (!c) return SCCG_E_ARG;
+  int r;
+  if ((r = check_polys(c, A, "A")) || (r = check_polys(c, B, "B"))) return r;
+  if (n_sets < 0) return fail(c, SCCG_E_ARG, "n_sets < 0");
+  if (cap < 0) return fail(c, SCCG_E_ARG, "cap < 0");
+  if (cell == 0) cell = 64;
+  if (cell < 1 || cell > (1 << 20)) return fail(c, SCCG_E_ARG, "cell outside [1, 2^20]");
+  if (!out_total || !out_set_off || (n_sets > 0 && (!a_set_off || !b_set_off)))
+    return fail(c, SCCG_E_ARG, "NULL offsets or output");
+  if (cap > 0 && (!out_pa || !out_pb)) return fail(c, SCCG_E_ARG, "NULL pair output with cap > 0");
+  HIP_TRY(c, hipSetDevice(c->device));
+  *out_total = 0;
+  if (n_sets == 0) {
+    HIP_TRY(c, hipMemsetAsync(out_set_off, 0, sizeof(int64_t), c->stream));
+    return SCCG_OK;
+  }
+  hipError_t e;
+  const Polys pA = to_polys(A), pB = to_polys(B);
+  if ((r = ensure_polys(c, 0, A->n_polys)) || (r = ensure_polys(c, 1, B->n_polys))) return r;
+  if ((e = launch_poly_meta(pA, c->metaA, c->areaA, c->bigA, c->big_count, c->err, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "poly meta A");
+  if ((e = launch_poly_meta(pB, c->metaB, c->areaB, c->bigB, c->big_count + 1, c->err, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "poly meta B");
+  // grids: per-set extents of A, cells per set, their offsets
+  if ((r = need(c, &c->j_bbox, c->j_cap[0], n_sets, "join boxes")) ||
+      (r = need(c, &c->j_grid, c->j_cap[1], n_sets, "join grids")) ||
+      (r = need(c, &c->j_cells, c->j_cap[2], n_sets, "join cells")) ||
+      (r = need(c, &c->j_cell_base, c->j_cap[3], n_sets + 1, "join cell offsets")) ||
+      (r = need(c, &c->j_sums, c->j_cap[4], scan_scratch(n_sets), "scan sums")))
+    return r;
+  if ((e = launch_join_grid(pA, c->metaA, a_set_off, n_sets, cell, c->j_bbox, c->j_grid, c->j_cells, c->j_cell_base,
+                            c->j_sums, c->err, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "join grid");
+  int64_t n_cells = 0;
+  HIP_TRY(c, hipMemcpyAsync(&n_cells, c->j_cell_base + n_sets, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // counting sort of (cell, A polygon) entries
+  if ((r = need(c, &c->j_count, c->j_cap[5], n_cells + 1, "cell counts")) ||
+      (r = need(c, &c->j_start, c->j_cap[6], n_cells + 1, "cell starts")) ||
+      (r = need(c, &c->j_sums, c->j_cap[4], scan_scratch(n_cells), "scan sums")))
+    return r;
+  HIP_TRY(c, hipMemsetAsync(c->j_count, 0, sizeof(int32_t) * (size_t)(n_cells + 1), c->stream));
+  if ((e = launch_join_cells(pA, c->metaA, a_set_off, n_sets, c->j_grid, c->j_cell_base, cell, 0, c->j_count,
+                             nullptr, nullptr, c->stream)) != hipSuccess ||
+      (e = launch_join_scan_counts(c->j_count, n_cells, c->j_start, c->j_sums, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "join cell counts");
+  int64_t n_entries = 0;
+  HIP_TRY(c, hipMemcpyAsync(&n_entries, c->j_start + n_cells, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if ((r = need(c, &c->j_list, c->j_cap[7], n_entries + 1, "cell lists"))) return r;
+  HIP_TRY(c, hipMemsetAsync(c->j_count, 0, sizeof(int32_t) * (size_t)(n_cells + 1), c->stream));
+  if ((e = launch_join_cells(pA, c->metaA, a_set_off, n_sets, c->j_grid, c->j_cell_base, cell, 1, c->j_count,
+                             c->j_start, c->j_list, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "join cell lists");
+  // pairs: count per B polygon, offsets, then (if they fit) write and sort
+  if ((r = need(c, &c->j_bcount, c->j_cap[8], B->n_polys + 1, "pair counts")) ||
+      (r = need(c, &c->j_bstart, c->j_cap[9], B->n_polys + 1, "pair starts")) ||
+      (r = need(c, &c->j_sums, c->j_cap[4], scan_scratch(B->n_polys), "scan sums")))
+    return r;
+  if ((e = launch_join_pairs(pB, c->metaA, c->metaB, b_set_off, n_sets, c->j_grid, c->j_cell_base, c->j_start,
+                             c->j_list, cell, 0, c->j_bcount, nullptr, 0, nullptr, nullptr, c->stream)) != hipSuccess ||
+      (e = launch_join_scan_counts(c->j_bcount, B->n_polys, c->j_bstart, c->j_sums, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "join pair counts");
+  int64_t total = 0;
+  HIP_TRY(c, hipMemcpyAsync(&total, c->j_bstart + B->n_polys, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *out_total = total;
+  if (total <= cap && total > 0) {
+    if ((e = launch_join_pairs(pB, c->metaA, c->metaB, b_set_off, n_sets, c->j_grid, c->j_cell_base, c->j_start,
+                               c->j_list, cell, 1, nullptr, c->j_bstart, cap, out_pa, out_pb, c->stream)) != hipSuccess)
+      return hip_fail(c, e, "join pairs");
+  }
+  if ((e = launch_join_set_off(n_sets, B->n_polys, b_set_off, c->j_bstart, out_set_off, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "join set offsets");
   return SCCG_OK;
 }
 

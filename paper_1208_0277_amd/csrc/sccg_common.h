@@ -127,6 +127,22 @@ hipError_t launch_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t*
 // Ring validation.
 hipError_t launch_validate(const Polys& P, int64_t* first_bad, hipStream_t s);
 
+// Filter stage (candidate pairs by MBR intersection).
+int64_t scan_scratch(int64_t n);
+hipError_t launch_join_grid(const Polys& A, const Meta* metaA, const int64_t* a_off, int64_t n_sets, int cell,
+                            int4* bbox, int4* grid, int64_t* cells, int64_t* cell_base, int64_t* sums,
+                            uint32_t* err, hipStream_t s);
+hipError_t launch_join_cells(const Polys& A, const Meta* metaA, const int64_t* a_off, int64_t n_sets,
+                             const int4* grid, const int64_t* cell_base, int cell, int mode, int32_t* count,
+                             const int64_t* start, int32_t* list, hipStream_t s);
+hipError_t launch_join_scan_counts(const int32_t* count, int64_t n, int64_t* start, int64_t* sums, hipStream_t s);
+hipError_t launch_join_pairs(const Polys& B, const Meta* metaA, const Meta* metaB, const int64_t* b_off,
+                             int64_t n_sets, const int4* grid, const int64_t* cell_base, const int64_t* start,
+                             const int32_t* list, int cell, int mode, int32_t* b_count, const int64_t* b_start,
+                             int64_t cap, int32_t* out_pa, int32_t* out_pb, hipStream_t s);
+hipError_t launch_join_set_off(int64_t n_sets, int64_t n_b, const int64_t* b_off, const int64_t* b_start,
+                               int64_t* out_set_off, hipStream_t s);
+
 // The device error word of a context (read and cleared by the server, which
 // owns its context and runs on the context's stream).
 uint32_t* ctx_error_word(sccg_ctx* c);

@@ -370,3 +370,71 @@ def test_set_workload_tiles(ctx, sets4, mode):
     assert np.array_equal(si.cpu().numpy(), osi) and np.array_equal(su.cpu().numpy(), osu)
     assert np.array_equal(nn.cpu().numpy(), onn)
     assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(jp.cpu().numpy(), ojp)
+
+
+def _dev_i64(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.int64)).to("cuda")
+
+
+@pytest.mark.parametrize("cell", [64, 7, 1000])
+def test_join_sets_equals_oracle(ctx, sets4, cell):
+    """Filter stage on the device: the same pairs, in the same order, as the
+    oracle's all-pairs test (and the generator's host grid join)."""
+    wl, _, _ = sets4
+    dA, dB, _, _ = device_workload(wl.A, wl.B, wl.pa, wl.pb)
+    pa, pb, so = ctx.join_sets(dA, dB, _dev_i64(wl.a_set_off), _dev_i64(wl.b_set_off), cell=cell)
+    ctx.sync()
+    ea, eb, eso = oracle.join_sets(wl.A, wl.B, wl.a_set_off, wl.b_set_off)
+    assert np.array_equal(pa.cpu().numpy(), ea) and np.array_equal(pb.cpu().numpy(), eb)
+    assert np.array_equal(so.cpu().numpy(), eso)
+
+
+def test_join_edge_cases_and_capacity(ctx):
+    sq = band_ring([0, 5], [0], [5])
+    empty = np.zeros((0, 2), np.int32)
+    # set 0: touching, overlapping, empty, far-away B; set 1: no A; set 2: no B; set 3: empty
+    ra = [sq, sq + np.array([20, 0], np.int32), empty, sq + np.array([100, 100], np.int32)]
+    rb = [sq + np.array([5, 0], np.int32), sq + np.array([4, 4], np.int32), empty, sq + np.array([-500, 0], np.int32),
+          band_ring([-3, 30], [-3], [40]), sq + np.array([100, 100], np.int32)]
+    A, B = concat(ra), concat(rb)
+    a_off = np.array([0, 3, 3, 4, 4], np.int64)
+    b_off = np.array([0, 5, 6, 6, 6], np.int64)
+    ea, eb, eso = oracle.join_sets(A, B, a_off, b_off)
+    assert len(ea) > 0
+    dA, dB, _, _ = device_workload(A, B, np.zeros(1, np.int32), np.zeros(1, np.int32))
+    for cell in (1, 3, 64):
+        pa, pb, so = ctx.join_sets(dA, dB, _dev_i64(a_off), _dev_i64(b_off), cell=cell)
+        ctx.sync()
+        assert list(zip(pa.cpu().tolist(), pb.cpu().tolist())) == list(zip(ea.tolist(), eb.tolist()))
+        assert np.array_equal(so.cpu().numpy(), eso)
+    # a buffer that is too small: the total comes back and nothing is written
+    import ctypes
+    import torch
+    out_a = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    out_b = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    so = torch.empty(5, dtype=torch.int64, device="cuda")
+    total = ctypes.c_int64(0)
+    cA, cB = dA.c(), dB.c()
+    rc = ctx.lib.sccg_join_sets(ctx.h, ctypes.byref(cA), ctypes.byref(cB), 4, _dev_i64(a_off).data_ptr(),
+                                _dev_i64(b_off).data_ptr(), 64, 1, out_a.data_ptr(), out_b.data_ptr(),
+                                so.data_ptr(), ctypes.byref(total))
+    ctx.sync()
+    assert rc == sccg.SCCG_OK and total.value == len(ea) > 1
+    assert out_a.item() == -7 and out_b.item() == -7
+    assert np.array_equal(so.cpu().numpy(), eso)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_join_then_pairs_then_sets_on_device(ctx, sets4, mode):
+    """Filter, pair counts and set reduction all on the device: per-tile
+    sums and Jaccard equal the oracle's."""
+    wl, eI, eU = sets4
+    dA, dB, _, _ = device_workload(wl.A, wl.B, wl.pa, wl.pb)
+    pa, pb, so = ctx.join_sets(dA, dB, _dev_i64(wl.a_set_off), _dev_i64(wl.b_set_off))
+    I, U = ctx.area_pairs(dA, dB, pa.contiguous(), pb.contiguous(), mode=mode)
+    si, su, nn, j, jp = ctx.jaccard_sets(so, I, U)
+    ctx.sync()
+    osi, osu, onn, oj, ojp = oracle.jaccard_sets(wl.set_off, eI, eU)
+    assert np.array_equal(si.cpu().numpy(), osi) and np.array_equal(su.cpu().numpy(), osu)
+    assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(jp.cpu().numpy(), ojp)
