@@ -43,14 +43,33 @@ __global__ void k_join_init_sets(int64_t n_sets, int4* bbox) {
   if (s < n_sets) bbox[s] = make_int4(INT_MAX, INT_MAX, INT_MIN, INT_MIN);
 }
 
-// Extent of each set's A polygons.
+// Extent of each set's A polygons.  Sets are contiguous ranges, so the
+// lanes of a wave usually share one set: then the wave reduces first and one
+// lane updates the set (a set holds many thousand polygons; per-polygon
+// atomics on its four words would serialize).
 __global__ void k_join_bbox(Polys A, const Meta* metaA, const int64_t* a_off, int64_t n_sets, int4* bbox) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= A.n) return;
-  const int64_t s = set_of(a_off, n_sets, a);
-  if (s < 0) return;
-  const Meta m = load_meta(metaA, a);
-  if (meta_empty(m)) return;
+  int64_t s = -1;
+  Meta m{INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+  if (a < A.n) {
+    s = set_of(a_off, n_sets, a);
+    const Meta t = load_meta(metaA, a);
+    if (s >= 0 && !meta_empty(t)) m = t;
+  }
+  const int64_t s0 = uniform64(s);
+  if (ballot(s != s0) == 0ull) {
+    if (s0 < 0) return;
+    const int x0 = wave_min_i32(m.x0), y0 = wave_min_i32(m.y0);
+    const int x1 = wave_max_i32(m.x1), y1 = wave_max_i32(m.y1);
+    if (lane_id() == 0 && x0 < x1 && y0 < y1) {
+      atomicMin(&bbox[s0].x, x0);
+      atomicMin(&bbox[s0].y, y0);
+      atomicMax(&bbox[s0].z, x1);
+      atomicMax(&bbox[s0].w, y1);
+    }
+    return;
+  }
+  if (s < 0 || meta_empty(m)) return;
   atomicMin(&bbox[s].x, m.x0);
   atomicMin(&bbox[s].y, m.y0);
   atomicMax(&bbox[s].z, m.x1);

@@ -5,11 +5,8 @@
 
 namespace sccg {
 
-// Polygons with more vertices than this are handed to one wave each.
-constexpr int kThreadVerts = 192;
-
-// One polygon's extent and doubled signed area, accumulated by one thread
-// (or one lane's share of a ring).  The shoelace sum (Section 3.2) is taken
+// One polygon's extent and doubled signed area, accumulated over one lane's
+// share of a ring.  The shoelace sum (Section 3.2) is taken
 // in wrapping 64-bit arithmetic: partial sums may overflow, the final value
 // (twice the area, below 2^63) is exact.
 struct MetaAcc {
@@ -38,76 +35,62 @@ __device__ void write_meta(const MetaAcc& a, int64_t nv, int64_t k, Meta* meta, 
   area[k] = (t < 0 ? -t : t) / 2;
 }
 
-__global__ void __launch_bounds__(256) k_meta_thread(Polys P, Meta* meta, int64_t* area, int32_t* big,
-                                                     int32_t* big_count, uint32_t* err) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool is_big = false;
-  if (k < P.n) {
-    const int64_t o0 = P.off[k];
-    const int64_t nv = P.off[k + 1] - o0;
-    if (nv > kThreadVerts) {
-      is_big = true;
-    } else {
-      MetaAcc a;
-      if (nv > 0) {
-        const int2* r = P.xy + o0;
-        const int2 first = r[0];
-        int2 v = first;
-        for (int64_t i = 1; i < nv; ++i) {
-          int2 w = r[i];
-          a.add(v, w);
-          v = w;
-        }
-        a.add(v, first);
-      }
-      write_meta(a, nv, k, meta, area, err);
-    }
+
+// Eight lanes per polygon: lane j of a group walks vertices j, j + 8, ...
+// (eight consecutive vertices, 64 bytes, per step of the group), then the
+// group combines its partial extents and shoelace sums in three exchanges.
+constexpr int kGroup = 8;
+
+__device__ __forceinline__ int32_t group_min(int32_t v) {
+  v = min(v, __shfl_xor(v, 1, kWave));
+  v = min(v, __shfl_xor(v, 2, kWave));
+  return min(v, __shfl_xor(v, 4, kWave));
+}
+__device__ __forceinline__ int32_t group_max(int32_t v) {
+  v = max(v, __shfl_xor(v, 1, kWave));
+  v = max(v, __shfl_xor(v, 2, kWave));
+  return max(v, __shfl_xor(v, 4, kWave));
+}
+__device__ __forceinline__ uint64_t group_sum64(uint64_t v) {
+  for (int d = 1; d < kGroup; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, kWave);
+    v += ((uint64_t)hi << 32) | lo;
   }
-  const uint64_t b = ballot(is_big);
-  if (b) {
-    int base = 0;
-    if (lane_id() == 0) base = atomicAdd(big_count, __popcll(b));
-    base = __shfl(base, 0, kWave);
-    if (is_big) big[base + lanes_below(b)] = (int32_t)k;
-  }
+  return v;
 }
 
-// One wave per listed polygon; grid-stride over the list.
-__global__ void __launch_bounds__(256) k_meta_wave(Polys P, Meta* meta, int64_t* area, const int32_t* big,
-                                                   const int32_t* big_count, uint32_t* err) {
-  const int lane = lane_id();
-  const int waves = gridDim.x * (blockDim.x / kWave);
-  const int n = *big_count;
-  for (int w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; w < n; w += waves) {
-    const int64_t k = big[w];
-    const int64_t o0 = P.off[k];
-    const int64_t nv = P.off[k + 1] - o0;
-    MetaAcc a;
-    for (int64_t i = lane; i < nv; i += kWave) {
-      const int2 v = P.xy[o0 + i];
-      const int2 u = P.xy[o0 + (i + 1 == nv ? 0 : i + 1)];
-      a.add(v, u);
-    }
-    MetaAcc r;
-    r.x0 = wave_min_i32(a.x0);
-    r.y0 = wave_min_i32(a.y0);
-    r.x1 = wave_max_i32(a.x1);
-    r.y1 = wave_max_i32(a.y1);
-    r.twice = wave_sum_u64(a.twice);
-    if (lane == 0) write_meta(r, nv, k, meta, area, err);
+__global__ void __launch_bounds__(256) k_meta_group(Polys P, Meta* meta, int64_t* area, uint32_t* err) {
+  const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup;
+  const int j = (int)(threadIdx.x % kGroup);
+  const bool live = gid < P.n;
+  int64_t o0 = 0, nv = 0;
+  if (live) {
+    o0 = P.off[gid];
+    nv = P.off[gid + 1] - o0;
   }
+  MetaAcc a;
+  for (int64_t i = j; i < nv; i += kGroup) {
+    const int2 v = P.xy[o0 + i];
+    const int2 w = P.xy[o0 + (i + 1 == nv ? 0 : i + 1)];
+    a.add(v, w);
+  }
+  MetaAcc r;
+  r.x0 = group_min(a.x0);
+  r.y0 = group_min(a.y0);
+  r.x1 = group_max(a.x1);
+  r.y1 = group_max(a.y1);
+  r.twice = group_sum64(a.twice);
+  if (live && j == 0) write_meta(r, nv, gid, meta, area, err);
 }
-
-__global__ void k_zero_i32(int32_t* p) { *p = 0; }
 
 hipError_t launch_poly_meta(const Polys& P, Meta* meta, int64_t* area, int32_t* big_list, int32_t* big_count,
                             uint32_t* err, hipStream_t s) {
+  (void)big_list;
+  (void)big_count;
   if (P.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, big_count);
-  const int64_t blocks = (P.n + 255) / 256;
-  hipLaunchKernelGGL(k_meta_thread, dim3((unsigned)blocks), dim3(256), 0, s, P, meta, area, big_list, big_count,
-                     err);
-  hipLaunchKernelGGL(k_meta_wave, dim3(512), dim3(256), 0, s, P, meta, area, big_list, big_count, err);
+  const int64_t blocks = (P.n * kGroup + 255) / 256;
+  hipLaunchKernelGGL(k_meta_group, dim3((unsigned)blocks), dim3(256), 0, s, P, meta, area, err);
   return hipGetLastError();
 }
 
