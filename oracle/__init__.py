@@ -51,6 +51,9 @@ def load_library(path: str):
     lib.sccg_oracle_jaccard_sets.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
+    lib.sccg_oracle_relate_pairs.restype = None
+    lib.sccg_oracle_relate_pairs.argtypes = [ctypes.POINTER(_Polys), ctypes.POINTER(_Polys), ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.sccg_oracle_join_sets.restype = ctypes.c_int64
     lib.sccg_oracle_join_sets.argtypes = [ctypes.POINTER(_Polys), ctypes.POINTER(_Polys), ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -129,6 +132,25 @@ def jaccard_sets(set_off, I, U, include_zero: bool = False):
         n = len(i_k)
         jp[s] = math.fsum(ratios.tolist()) / n if n else 0.0
     return si, su, nn, j, jp
+
+
+#: relation bits of relate_pairs (Section 3.4)
+REL_INTERSECTS, REL_CONTAINS, REL_WITHIN, REL_EQUALS, REL_TOUCHES = 1, 2, 4, 8, 16
+
+
+def relate_pairs(A, B, pa, pb):
+    """Per pair the relation bits: intersects, A contains B, A within B,
+    equal (from the pixel counts and areas), touches (no common pixel, but
+    boundaries that share a point, by comparing every pair of edges)."""
+    lib = _load()
+    sa, ka = _polys(A)
+    sb, kb = _polys(B)
+    pa = _c(pa, np.int32)
+    pb = _c(pb, np.int32)
+    out = np.zeros(len(pa), np.uint32)
+    lib.sccg_oracle_relate_pairs(ctypes.byref(sa), ctypes.byref(sb), len(pa), pa.ctypes.data, pb.ctypes.data,
+                                 out.ctypes.data)
+    return out
 
 
 def join_sets(A, B, a_set_off, b_set_off):

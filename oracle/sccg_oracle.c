@@ -19,6 +19,10 @@
  *    are those whose MBRs intersect; here MBR = pixel extent of the vertices,
  *    and two MBRs intersect when they share a pixel.  Every pair of a set is
  *    tested (no index).
+ *  - Other operators (Section 3.4): containment when the intersection area
+ *    equals the contained polygon's area; touching when the polygons share
+ *    boundary points but no interior (here: no common pixel), tested by
+ *    comparing every edge of one polygon with every edge of the other.
  *  - Jaccard (Section 2.1): J = total intersection / total union of a set of
  *    pairs.  J' (Equation 1, the mean of the per-pair ratios over the pairs
  *    with non-zero intersection) is formed in the Python wrapper.
@@ -267,4 +271,45 @@ int64_t sccg_oracle_join_sets(const sccg_oracle_polys* A, const sccg_oracle_poly
   }
   if (out_set_off) out_set_off[n_sets] = total;
   return total;
+}
+
+/* Do the closed axis-parallel segments (a0-a1) and (b0-b1) share a point?
+ * Each segment equals its own bounding box. */
+static int segments_meet(const int32_t* a0, const int32_t* a1, const int32_t* b0, const int32_t* b1) {
+  const int64_t ax0 = a0[0] < a1[0] ? a0[0] : a1[0], ax1 = a0[0] < a1[0] ? a1[0] : a0[0];
+  const int64_t ay0 = a0[1] < a1[1] ? a0[1] : a1[1], ay1 = a0[1] < a1[1] ? a1[1] : a0[1];
+  const int64_t bx0 = b0[0] < b1[0] ? b0[0] : b1[0], bx1 = b0[0] < b1[0] ? b1[0] : b0[0];
+  const int64_t by0 = b0[1] < b1[1] ? b0[1] : b1[1], by1 = b0[1] < b1[1] ? b1[1] : b0[1];
+  return (ax0 > bx0 ? ax0 : bx0) <= (ax1 < bx1 ? ax1 : bx1) && (ay0 > by0 ? ay0 : by0) <= (ay1 < by1 ? ay1 : by1);
+}
+
+void sccg_oracle_relate_pairs(const sccg_oracle_polys* A, const sccg_oracle_polys* B, int64_t n_pairs,
+                              const int32_t* pair_a, const int32_t* pair_b, uint32_t* out_rel) {
+  for (int64_t k = 0; k < n_pairs; ++k) {
+    const int64_t a = pair_a[k], b = pair_b[k];
+    const int32_t* p = A->xy + 2 * A->offsets[a];
+    const int64_t np = A->offsets[a + 1] - A->offsets[a];
+    const int32_t* q = B->xy + 2 * B->offsets[b];
+    const int64_t nq = B->offsets[b + 1] - B->offsets[b];
+    int64_t I = 0, U = 0;
+    pair_pure(p, np, q, nq, &I, &U);
+    const int64_t ap = sccg_oracle_poly_area(A, a), aq = sccg_oracle_poly_area(B, b);
+    uint32_t r = 0;
+    if (I > 0) r |= 1u;
+    if (I > 0 && I == aq) r |= 2u;
+    if (I > 0 && I == ap) r |= 4u;
+    if (I > 0 && I == ap && I == aq) r |= 8u;
+    if (I == 0 && np > 0 && nq > 0) {
+      int meet = 0;
+      for (int64_t i = 0; i < np && !meet; ++i) {
+        const int64_t i1 = (i + 1 == np) ? 0 : i + 1;
+        for (int64_t j = 0; j < nq && !meet; ++j) {
+          const int64_t j1 = (j + 1 == nq) ? 0 : j + 1;
+          meet = segments_meet(p + 2 * i, p + 2 * i1, q + 2 * j, q + 2 * j1);
+        }
+      }
+      if (meet) r |= 16u;
+    }
+    out_rel[k] = r;
+  }
 }

@@ -60,6 +60,15 @@ int64_t sccg_oracle_join_sets(const sccg_oracle_polys* A, const sccg_oracle_poly
                               const int64_t* a_off, const int64_t* b_off, int64_t cap, int32_t* out_pa,
                               int32_t* out_pb, int64_t* out_set_off);
 
+/* Section 3.4's other operators, from the pixel counts: per pair a bit set
+ *   1 intersects (I > 0),  2 A contains B (I == |B| > 0),  4 A within B
+ *   (I == |A| > 0),  8 equal (I == |A| == |B| > 0),  16 touches (I == 0 and
+ *   the two boundaries, as closed point sets, share a point).
+ * The boundary test compares every edge of one ring with every edge of the
+ * other (axis-parallel closed segments).  I comes from the pure pixel count. */
+void sccg_oracle_relate_pairs(const sccg_oracle_polys* A, const sccg_oracle_polys* B, int64_t n_pairs,
+                              const int32_t* pair_a, const int32_t* pair_b, uint32_t* out_rel);
+
 #ifdef __cplusplus
 }
 #endif

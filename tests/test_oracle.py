@@ -375,3 +375,57 @@ def test_join_agrees_with_grid_join():
     wl = sccg_gen.sets(n_tiles=3, tile_side=1536, cell=64)
     pa, pb, so = oracle.join_sets(wl.A, wl.B, wl.a_set_off, wl.b_set_off)
     assert np.array_equal(pa, wl.pa) and np.array_equal(pb, wl.pb) and np.array_equal(so, wl.set_off)
+
+
+def test_relate_closed_forms():
+    """Section 3.4's operators from counts: shared side or corner touches;
+    a gap, or any common pixel, does not; containment both ways; equality;
+    an empty ring relates to nothing."""
+    sq = band_ring([0, 5], [0], [5])
+    small = band_ring([1, 3], [1], [3])
+    empty = np.zeros((0, 2), np.int32)
+    L = band_ring([0, 2, 5], [0, 0], [6, 2])       # L-shape; its notch touches the square below
+    cases = [
+        (sq, sq + np.array([5, 0], np.int32), oracle.REL_TOUCHES),     # shared side
+        (sq, sq + np.array([5, 5], np.int32), oracle.REL_TOUCHES),     # shared corner
+        (sq, sq + np.array([6, 0], np.int32), 0),                      # gap of one pixel
+        (sq, sq + np.array([4, 4], np.int32), oracle.REL_INTERSECTS),  # one common pixel
+        (sq, small, oracle.REL_INTERSECTS | oracle.REL_CONTAINS),
+        (small, sq, oracle.REL_INTERSECTS | oracle.REL_WITHIN),
+        (sq, sq[::-1].copy(), 15),                                     # equal (other orientation)
+        (sq, empty, 0),
+        (L, band_ring([2, 5], [2], [6]), oracle.REL_TOUCHES),           # fills the notch: touch along two sides
+    ]
+    A = concat([a for a, _, _ in cases])
+    B = concat([b for _, b, _ in cases])
+    idx = np.arange(len(cases), dtype=np.int32)
+    assert oracle.relate_pairs(A, B, idx, idx).tolist() == [r for _, _, r in cases]
+
+
+def test_relate_brute_force_on_tiny_masks(tiny_corpus):
+    """Random tiny-grid pairs with shifts: contains/within/equal/intersects
+    against mask set relations, touches against pixel adjacency (two
+    disjoint pixel sets touch iff some pixels share a side or a corner)."""
+    masks, rings = tiny_corpus
+    rng = np.random.default_rng(31)
+    n = 3000
+    ia = rng.integers(0, len(masks), n)
+    ib = rng.integers(0, len(masks), n)
+    sh = rng.integers(-5, 6, (n, 2))
+    A = concat([rings[j] for j in ia])
+    B = concat([rings[j] + sh[k].astype(np.int32) for k, j in enumerate(ib)])
+    idx = np.arange(n, dtype=np.int32)
+    rel = oracle.relate_pairs(A, B, idx, idx)
+    for k in range(n):
+        a = {(x, y) for y in range(4) for x in range(4) if masks[ia[k]] >> (y * 4 + x) & 1}
+        b = {(x + sh[k, 0], y + sh[k, 1]) for y in range(4) for x in range(4) if masks[ib[k]] >> (y * 4 + x) & 1}
+        i = a & b
+        exp = 0
+        if i:
+            exp |= oracle.REL_INTERSECTS
+            exp |= oracle.REL_CONTAINS if i == b else 0
+            exp |= oracle.REL_WITHIN if i == a else 0
+            exp |= oracle.REL_EQUALS if a == b else 0
+        elif any((x + dx, y + dy) in b for (x, y) in a for dx in (-1, 0, 1) for dy in (-1, 0, 1)):
+            exp |= oracle.REL_TOUCHES
+        assert rel[k] == exp, (k, rel[k], exp)
