@@ -180,6 +180,23 @@ int sccg_join_sets(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, int6
                    const int64_t* a_set_off, const int64_t* b_set_off, int32_t cell, int64_t cap,
                    int32_t* out_pa, int32_t* out_pb, int64_t* out_set_off, int64_t* out_total);
 
+/* sccg_relate_pairs result bits (Section 3.4's other spatial operators) */
+#define SCCG_REL_INTERSECTS 0x1u /* a common pixel: I > 0                                        */
+#define SCCG_REL_CONTAINS 0x2u   /* A contains B: I == |B| > 0 (ST_Contains from the counts)       */
+#define SCCG_REL_WITHIN 0x4u     /* A within B: I == |A| > 0                                       */
+#define SCCG_REL_EQUALS 0x8u     /* the same pixels: I == |A| == |B| > 0                           */
+#define SCCG_REL_TOUCHES 0x10u   /* no common pixel, but the boundaries share a point (ST_Touches) */
+
+/* Per pair k, the bits above for (A[pair_a[k]], B[pair_b[k]]), from
+ * inter[k] (the intersection counts of the same pairs, as sccg_area_pairs
+ * writes them), the polygon areas, and, for pairs with no common pixel whose
+ * closed MBRs meet, a test of every edge of one ring against every edge of
+ * the other (axis-parallel closed segments) -- Section 3.4's suggestion for
+ * ST_Contains and ST_Touches.  out_rel: device uint32 [n_pairs].  A pair
+ * index out of range gives 0 and latches SCCG_E_RANGE. */
+int sccg_relate_pairs(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, int64_t n_pairs,
+                      const int32_t* pair_a, const int32_t* pair_b, const int64_t* inter, uint32_t* out_rel);
+
 /* Check every ring of P: at least 4 vertices and every edge axis-aligned.
  * Writes the smallest bad polygon index, or -1, to *out_first_bad (device
  * int64).  Asynchronous; read the value after sccg_sync. */

@@ -36,6 +36,12 @@ SCCG_F_NO_GRAPH = 0x8
 SCCG_F_PIXEL_ONLY = 0x10
 SCCG_F_NO_SEP = 0x20
 
+SCCG_REL_INTERSECTS = 0x1
+SCCG_REL_CONTAINS = 0x2
+SCCG_REL_WITHIN = 0x4
+SCCG_REL_EQUALS = 0x8
+SCCG_REL_TOUCHES = 0x10
+
 SCCG_J_NONZERO_ONLY = 0
 SCCG_J_INCLUDE_ZERO = 1
 
@@ -43,7 +49,7 @@ SCCG_J_INCLUDE_ZERO = 1
 EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
            "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
            "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version",
-           "sccg_join_sets", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
+           "sccg_join_sets", "sccg_relate_pairs", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
            "sccg_server_clock", "sccg_server_last_error", "sccg_server_destroy")
 
 SERVER_STAT_KEYS = ("jobs_submitted", "jobs_done", "launches", "pairs_done", "peak_resident_vertices",
@@ -126,6 +132,8 @@ def load_library(path: str = LIB_PATH):
         "sccg_version": ([], ctypes.c_char_p),
         "sccg_join_sets": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, ctypes.c_int32,
                             i64, P, P, P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "sccg_relate_pairs": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P],
+                              ctypes.c_int),
         "sccg_server_create": ([ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(sccg_server_config),
                                 ctypes.POINTER(sccg_params)], ctypes.c_int),
         "sccg_server_submit": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P,
@@ -316,6 +324,20 @@ class Context:
                 return pa[:total.value], pb[:total.value], so
             cap = total.value
         raise SccgError(SCCG_E_STATE, "join output did not fit after resizing")
+
+    def relate_pairs(self, A: DevicePolys, B: DevicePolys, pair_a, pair_b, inter):
+        """Queue sccg_relate_pairs; returns the uint32 relation bits per pair
+        (as an int32 device tensor)."""
+        import torch
+        _check_dev(pair_a, torch.int32, "pair_a")
+        _check_dev(pair_b, torch.int32, "pair_b")
+        _check_dev(inter, torch.int64, "inter")
+        n = int(pair_a.shape[0])
+        out = torch.empty(n, dtype=torch.int32, device=pair_a.device)
+        cA, cB = A.c(), B.c()
+        self._rc(self.lib.sccg_relate_pairs(self.h, ctypes.byref(cA), ctypes.byref(cB), n, _ptr(pair_a), _ptr(pair_b),
+                                            _ptr(inter), _ptr(out)))
+        return out
 
     def validate_polys(self, P: DevicePolys):
         import torch

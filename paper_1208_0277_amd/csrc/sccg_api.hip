@@ -592,6 +592,27 @@ int sccg_join_sets(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64_
   return SCCG_OK;
 }
 
+int sccg_relate_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64_t n_pairs, const int32_t* pair_a,
+                      const int32_t* pair_b, const int64_t* inter, uint32_t* out_rel) {
+  if (!c) return SCCG_E_ARG;
+  int r;
+  if ((r = check_polys(c, A, "A")) || (r = check_polys(c, B, "B"))) return r;
+  if (n_pairs < 0) return fail(c, SCCG_E_ARG, "n_pairs < 0");
+  if (n_pairs == 0) return SCCG_OK;
+  if (!pair_a || !pair_b || !inter || !out_rel) return fail(c, SCCG_E_ARG, "NULL pair, count or output array");
+  HIP_TRY(c, hipSetDevice(c->device));
+  if ((r = ensure_polys(c, 0, A->n_polys)) || (r = ensure_polys(c, 1, B->n_polys))) return r;
+  hipError_t e;
+  const Polys pA = to_polys(A), pB = to_polys(B);
+  if ((e = launch_poly_meta(pA, c->metaA, c->areaA, c->bigA, c->big_count, c->err, c->stream)) != hipSuccess ||
+      (e = launch_poly_meta(pB, c->metaB, c->areaB, c->bigB, c->big_count + 1, c->err, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "poly meta");
+  if ((e = launch_relate(pA, pB, c->metaA, c->metaB, c->areaA, c->areaB, n_pairs, pair_a, pair_b, inter, out_rel,
+                         c->err, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "relate");
+  return SCCG_OK;
+}
+
 int sccg_validate_polys(sccg_ctx* c, const sccg_polys* P, int64_t* out_first_bad) {
   if (!c) return SCCG_E_ARG;
   int r = check_polys(c, P, "P");

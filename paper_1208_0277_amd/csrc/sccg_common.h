@@ -143,6 +143,11 @@ hipError_t launch_join_pairs(const Polys& B, const Meta* metaA, const Meta* meta
 hipError_t launch_join_set_off(int64_t n_sets, int64_t n_b, const int64_t* b_off, const int64_t* b_start,
                                int64_t* out_set_off, hipStream_t s);
 
+// Section 3.4's operators from counts and edges.
+hipError_t launch_relate(const Polys& A, const Polys& B, const Meta* metaA, const Meta* metaB, const int64_t* areaA,
+                         const int64_t* areaB, int64_t n_pairs, const int32_t* pa, const int32_t* pb,
+                         const int64_t* inter, uint32_t* out, uint32_t* err, hipStream_t s);
+
 // The device error word of a context (read and cleared by the server, which
 // owns its context and runs on the context's stream).
 uint32_t* ctx_error_word(sccg_ctx* c);

@@ -438,3 +438,40 @@ def test_join_then_pairs_then_sets_on_device(ctx, sets4, mode):
     osi, osu, onn, oj, ojp = oracle.jaccard_sets(wl.set_off, eI, eU)
     assert np.array_equal(si.cpu().numpy(), osi) and np.array_equal(su.cpu().numpy(), osu)
     assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(jp.cpu().numpy(), ojp)
+
+
+def _relate_cases():
+    sq = band_ring([0, 5], [0], [5])
+    small = band_ring([1, 3], [1], [3])
+    empty = np.zeros((0, 2), np.int32)
+    L = band_ring([0, 2, 5], [0, 0], [6, 2])
+    pairs = [(sq, sq + np.array([5, 0], np.int32)), (sq, sq + np.array([5, 5], np.int32)),
+             (sq, sq + np.array([6, 0], np.int32)), (sq, sq + np.array([4, 4], np.int32)), (sq, small), (small, sq),
+             (sq, sq[::-1].copy()), (sq, empty), (L, band_ring([2, 5], [2], [6]))]
+    return concat([a for a, _ in pairs]), concat([b for _, b in pairs])
+
+
+@pytest.mark.parametrize("which", ["closed_forms", "tiny_shifted", "workload1", "set_tiles"])
+def test_relate_pairs_equals_oracle(ctx, tiny, wl1, sets4, which):
+    """Section 3.4's operators on the device (counts from BATCHED mode, then
+    sccg_relate_pairs) equal the oracle's, bit for bit."""
+    if which == "closed_forms":
+        A, B = _relate_cases()
+        pa = pb = np.arange(A.n, dtype=np.int32)
+    elif which == "tiny_shifted":
+        A, B, pa, pb = tiny[0], tiny[1], tiny[2][:5000], tiny[3][:5000]
+    elif which == "workload1":
+        A, B, pa, pb = wl1[0].A, wl1[0].B, wl1[0].pa, wl1[0].pb
+    else:
+        wl = sets4[0]
+        A, B, pa, pb = wl.A, wl.B, wl.pa[:4000], wl.pb[:4000]
+    dA, dB, dpa, dpb = device_workload(A, B, pa, pb)
+    I, U = ctx.area_pairs(dA, dB, dpa, dpb, mode=sccg.SCCG_BATCHED)
+    rel = ctx.relate_pairs(dA, dB, dpa, dpb, I)
+    ctx.sync()
+    expect = oracle.relate_pairs(A, B, pa, pb)
+    got = rel.cpu().numpy().astype(np.uint32)
+    bad = np.nonzero(got != expect)[0]
+    assert len(bad) == 0, [(int(k), int(got[k]), int(expect[k])) for k in bad[:5]]
+    if which == "closed_forms":
+        assert got.tolist() == [16, 16, 0, 1, 3, 5, 15, 0, 16]
