@@ -342,7 +342,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the pair path has no cross-GPU "
-              f"exchange in this build; see DESIGN.md for how it would shard.", file=sys.stderr)
+              f"exchange: it would shard by pair ranges (or whole tiles) with one all-reduce of the per-set sums.",
+              file=sys.stderr)
         return 2
 
     if args.workload == 5:

@@ -197,6 +197,16 @@ int sccg_join_sets(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, int6
 int sccg_relate_pairs(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, int64_t n_pairs,
                       const int32_t* pair_a, const int32_t* pair_b, const int64_t* inter, uint32_t* out_rel);
 
+/* PixelBox on the host CPU (the PixelBox-CPU of Section 4.2): the same
+ * counts as sccg_area_pairs, from HOST arrays, on n_threads threads (< 1 =
+ * 1), synchronously; no context or GPU is needed.  Sampling boxes split in
+ * four down to boxes of at most 64 x 64 pixels below 4096 pixels, whose rows
+ * are tested as 64-bit masks.  The serving path runs it on jobs it moves
+ * off a congested device.  A pair index out of range returns SCCG_E_RANGE
+ * before any work; a pair box side above 32767 gives (0, 0). */
+int sccg_host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n_pairs, const int32_t* pair_a,
+                         const int32_t* pair_b, int64_t* out_inter, int64_t* out_union, int n_threads);
+
 /* Check every ring of P: at least 4 vertices and every edge axis-aligned.
  * Writes the smallest bad polygon index, or -1, to *out_first_bad (device
  * int64).  Asynchronous; read the value after sccg_sync. */

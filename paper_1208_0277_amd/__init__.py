@@ -49,7 +49,7 @@ SCCG_J_INCLUDE_ZERO = 1
 EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
            "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
            "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version",
-           "sccg_join_sets", "sccg_relate_pairs", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
+           "sccg_join_sets", "sccg_relate_pairs", "sccg_host_area_pairs", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
            "sccg_server_clock", "sccg_server_last_error", "sccg_server_destroy")
 
 SERVER_STAT_KEYS = ("jobs_submitted", "jobs_done", "launches", "pairs_done", "peak_resident_vertices",
@@ -134,6 +134,8 @@ def load_library(path: str = LIB_PATH):
                             i64, P, P, P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "sccg_relate_pairs": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P],
                               ctypes.c_int),
+        "sccg_host_area_pairs": ([ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P,
+                                  ctypes.c_int], ctypes.c_int),
         "sccg_server_create": ([ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(sccg_server_config),
                                 ctypes.POINTER(sccg_params)], ctypes.c_int),
         "sccg_server_submit": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P,
@@ -444,6 +446,29 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def host_area_pairs(a_off, a_xy, b_off, b_xy, pa, pb, threads: int = 1):
+    """PixelBox on the host CPU (sccg_host_area_pairs): (inter, union) int64
+    numpy arrays for host CSR rings and pair indices."""
+    lib = load_library()
+    a_off = _host(np.ascontiguousarray(a_off, np.int64), np.int64, "a_off")
+    b_off = _host(np.ascontiguousarray(b_off, np.int64), np.int64, "b_off")
+    a_xy = _host(np.ascontiguousarray(a_xy, np.int32).reshape(-1), np.int32, "a_xy")
+    b_xy = _host(np.ascontiguousarray(b_xy, np.int32).reshape(-1), np.int32, "b_xy")
+    pa = _host(np.ascontiguousarray(pa, np.int32), np.int32, "pa")
+    pb = _host(np.ascontiguousarray(pb, np.int32), np.int32, "pb")
+    n = len(pa)
+    I = np.zeros(n, np.int64)
+    U = np.zeros(n, np.int64)
+    A = sccg_polys(len(a_off) - 1, a_off.ctypes.data, a_xy.ctypes.data if a_xy.size else None)
+    B = sccg_polys(len(b_off) - 1, b_off.ctypes.data, b_xy.ctypes.data if b_xy.size else None)
+    rc = lib.sccg_host_area_pairs(ctypes.byref(A), ctypes.byref(B), n, pa.ctypes.data if n else None,
+                                  pb.ctypes.data if n else None, I.ctypes.data if n else None,
+                                  U.ctypes.data if n else None, threads)
+    if rc != SCCG_OK:
+        raise SccgError(rc, "sccg_host_area_pairs failed")
+    return I, U
 
 
 def version() -> str:

@@ -1,0 +1,68 @@
+"""PixelBox on the host CPU (sccg_host_area_pairs, the CPU path of the
+serving migration): its counts equal the oracle's exactly.  Runs without a
+GPU: the entry point is plain host code in the device library."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1208_0277_amd as sccg
+import sccg_gen
+from sccg_gen import concat
+from tests.shapes import random_bands, rects_area, rects_inter, transform
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sccg.LIB_PATH):
+        pytest.skip("device library not built")
+    return sccg.load_library()
+
+
+def _run(wl_A, wl_B, pa, pb, threads=4):
+    return sccg.host_area_pairs(wl_A.off, wl_A.xy, wl_B.off, wl_B.xy, pa, pb, threads=threads)
+
+
+def test_workload1_and_tiny(lib, cfg1):
+    I, U = _run(cfg1.A, cfg1.B, cfg1.pa, cfg1.pb)
+    eI, eU = oracle.area_pairs(cfg1.A, cfg1.B, cfg1.pa, cfg1.pb)
+    assert np.array_equal(I, eI) and np.array_equal(U, eU)
+
+
+def test_heavy_tailed_sample_with_blobs(lib):
+    wl = sccg_gen.pairs(3, 3000)
+    sel = np.concatenate([np.nonzero(wl.blob)[0][:15], np.arange(0, 3000, 5)])
+    I, U = _run(wl.A, wl.B, wl.pa[sel], wl.pb[sel])
+    eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa[sel], wl.pb[sel], form=oracle.ROWS)
+    assert np.array_equal(I, eI) and np.array_equal(U, eU)
+
+
+def test_band_polygons_closed_form(lib):
+    rng = np.random.default_rng(77)
+    ra, rb, expect = [], [], []
+    for _ in range(500):
+        a, ar = random_bands(rng, int(rng.integers(1, 10)), span=int(rng.integers(8, 300)),
+                            hmax=int(rng.integers(1, 80)))
+        b, br = random_bands(rng, int(rng.integers(1, 10)), x0=int(rng.integers(-30, 30)),
+                             y0=int(rng.integers(-30, 80)), span=int(rng.integers(8, 300)),
+                             hmax=int(rng.integers(1, 80)))
+        sx, sy, sw = (1 if rng.random() < 0.5 else -1), (1 if rng.random() < 0.5 else -1), bool(rng.random() < .5)
+        a, ar = transform(a, ar, sx, sy, sw)
+        b, br = transform(b, br, sx, sy, sw)
+        ra.append(a)
+        rb.append(b)
+        i = rects_inter(ar, br)
+        expect.append((i, rects_area(ar) + rects_area(br) - i))
+    A, B = concat(ra), concat(rb)
+    idx = np.arange(len(ra), dtype=np.int32)
+    I, U = _run(A, B, idx, idx, threads=1)
+    assert [tuple(t) for t in zip(I.tolist(), U.tolist())] == expect
+
+
+def test_range_error_and_empty(lib, cfg1):
+    with pytest.raises(sccg.SccgError):
+        _run(cfg1.A, cfg1.B, np.array([cfg1.A.n], np.int32), np.array([0], np.int32))
+    I, U = _run(cfg1.A, cfg1.B, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert len(I) == 0 and len(U) == 0
