@@ -75,11 +75,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# The translation unit of the persistent kernel: its source, the headers it
+# includes, and the compiler flags.  Counters taken on another version of any
+# of these are not reported.
+KERNEL_SOURCES = ("paper_1208_0277_amd/csrc/k_batched.hip", "paper_1208_0277_amd/csrc/sccg_device.h",
+                  "paper_1208_0277_amd/csrc/sccg_common.h", "include/sccg.h")
+
+
 def kernel_source_hash() -> str:
+    from paper_1208_0277_amd import build as _build
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1208_0277_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1208_0277_amd", "csrc", f), "rb") as fh:
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(_build.FLAGS).encode())
     return h.hexdigest()[:16]
 
 

@@ -203,7 +203,9 @@ int sccg_relate_pairs(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, i
  * four down to boxes of at most 64 x 64 pixels below 4096 pixels, whose rows
  * are tested as 64-bit masks.  The serving path runs it on jobs it moves
  * off a congested device.  A pair index out of range returns SCCG_E_RANGE
- * before any work; a pair box side above 32767 gives (0, 0). */
+ * before any work.  A pair box side above 32767 gives (0, 0) and a ring with
+ * a coordinate magnitude above 2^30 covers nothing; either makes the call
+ * return SCCG_E_RANGE after every count has been written. */
 int sccg_host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n_pairs, const int32_t* pair_a,
                          const int32_t* pair_b, int64_t* out_inter, int64_t* out_union, int n_threads);
 
@@ -278,18 +280,29 @@ typedef struct {
   int64_t max_step_pairs; /* pairs per launch; a larger job runs alone in its launch; 0 = 2^21        */
   int32_t max_inflight;   /* launches queued on the device at once, 1..4; 0 = 2                      */
   uint32_t jaccard_flags; /* SCCG_J_* for the per-job sums                                            */
+  /* Migration to the host CPU (Section 4.2's GPU-to-CPU direction): while at
+   * least cpu_trigger jobs wait for admission (the arenas, the device's input
+   * buffer, are full), the scheduler moves the waiting job with the fewest
+   * pairs, if it has at most cpu_max_pairs, to a migration thread that runs
+   * it with the host PixelBox on cpu_threads threads, one job at a time.
+   * Its result is bit-identical to the device's, with jobs_in_launch 0.      */
+  int32_t cpu_threads;    /* 0 = no migration; at most 256                                            */
+  int32_t cpu_trigger;    /* waiting jobs that wake the migration; 0 = 1                              */
+  int64_t cpu_max_pairs;  /* largest job that migrates; 0 = 2^16                                      */
 } sccg_server_config;
 
 typedef struct {
   uint64_t job_id;       /* as returned by sccg_server_submit                                        */
   int32_t status;        /* SCCG_OK, or SCCG_E_RANGE / SCCG_E_DEVICE latched by the job's launch, or
-                            SCCG_E_HIP if the server failed                                           */
-  int32_t jobs_in_launch;/* jobs that shared the job's launch                                        */
+                            SCCG_E_HIP if the server failed; a migrated job reports SCCG_E_RANGE for
+                            its own rejected pairs only                                               */
+  int32_t jobs_in_launch;/* jobs that shared the job's launch; 0 = run on host threads (migrated)     */
   int64_t n_pairs;
   int64_t sum_i, sum_u, n_contrib; /* as sccg_jaccard_sets over the job's pairs                      */
   double j, jprime;
   double t_submit, t_admit, t_launch, t_done; /* seconds on the server's clock: submitted, copied
-                             into the arenas, launched, results on the host                          */
+                             into the arenas (migrated: handed to the migration thread), launched
+                             (migrated: started on the host), results on the host                    */
 } sccg_job_result;
 
 /* Create a server on HIP device `hip_device`.  `config` and `params` may be
@@ -318,8 +331,9 @@ int sccg_server_poll(sccg_server* srv, sccg_job_result* out, int max_results, in
 /* Server counters: [0] jobs submitted [1] jobs done [2] launches [3] pairs
  * done [4] peak resident vertices [5] peak resident offset entries [6] peak
  * resident pairs [7] admission waits (the oldest queued job did not fit)
- * [8] most jobs in one launch [9] jobs rejected at submit.  Writes
- * min(n, 10) values; returns that count. */
+ * [8] most jobs in one launch [9] jobs rejected at submit [10] jobs run on
+ * host threads (migrated) [11] pairs run on host threads.  Writes
+ * min(n, 12) values; returns that count. */
 int sccg_server_get_stats(sccg_server* srv, int64_t* out, int n);
 
 /* Seconds since the server was created, on the clock of sccg_job_result. */

@@ -54,7 +54,7 @@ EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", 
 
 SERVER_STAT_KEYS = ("jobs_submitted", "jobs_done", "launches", "pairs_done", "peak_resident_vertices",
                     "peak_resident_slots", "peak_resident_pairs", "admission_waits", "max_jobs_per_launch",
-                    "jobs_rejected")
+                    "jobs_rejected", "jobs_migrated", "pairs_migrated")
 
 STAT_KEYS = ("leaf_pixel_tests", "leaf_boxes", "split_boxes", "queued_boxes", "kept_boxes", "small_pairs",
              "large_pairs", "empty_pairs", "leaf_edge_updates", "classify_edge_visits", "leaf_staging_edges",
@@ -85,7 +85,8 @@ class sccg_params(ctypes.Structure):
 class sccg_server_config(ctypes.Structure):
     _fields_ = [("vertex_cap", ctypes.c_int64), ("slot_cap", ctypes.c_int64), ("pair_cap", ctypes.c_int64),
                 ("max_step_pairs", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("jaccard_flags", ctypes.c_uint32)]
+                ("jaccard_flags", ctypes.c_uint32), ("cpu_threads", ctypes.c_int32), ("cpu_trigger", ctypes.c_int32),
+                ("cpu_max_pairs", ctypes.c_int64)]
 
 
 class sccg_job_result(ctypes.Structure):

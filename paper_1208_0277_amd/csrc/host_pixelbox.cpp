@@ -17,7 +17,7 @@
 #include <thread>
 #include <vector>
 
-#include "sccg.h"
+#include "host_pixelbox.h"
 
 namespace {
 
@@ -30,7 +30,7 @@ struct Ring {
 
 constexpr int64_t kMaxCoord = int64_t(1) << 30;
 
-Ring make_ring(const sccg_polys* P, int64_t k) {
+Ring make_ring(const sccg_polys* P, int64_t k, bool* rejected) {
   Ring r;
   r.xy = P->xy + 2 * P->offsets[k];
   r.n = P->offsets[k + 1] - P->offsets[k];
@@ -47,6 +47,7 @@ Ring make_ring(const sccg_polys* P, int64_t k) {
     twice += (int64_t)x * r.xy[2 * j + 1] - (int64_t)r.xy[2 * j] * y;
   }
   const bool bad = r.n > 0 && (r.x0 < -kMaxCoord || r.y0 < -kMaxCoord || r.x1 > kMaxCoord || r.y1 > kMaxCoord);
+  *rejected = bad;
   if (r.n == 0 || bad) {
     r.n = 0;  // an empty or rejected ring covers nothing
     r.x0 = r.y0 = INT32_MAX;
@@ -147,21 +148,29 @@ int64_t pair_intersection(const Ring& p, const Ring& q, std::vector<Box>& stack)
 namespace sccg {
 
 // Pairs [0, n) on `threads` host threads (chunks of 64 from a shared counter).
-void host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n, const int32_t* pa, const int32_t* pb,
-                     int64_t* out_i, int64_t* out_u, int threads) {
+// Returns the rejections seen: kHostErrSide for a pair-box side above 32767,
+// kHostErrCoord for a ring with a coordinate magnitude above 2^30 (the bits
+// the device latches for the same cases).
+uint32_t host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n, const int32_t* pa, const int32_t* pb,
+                         int64_t* out_i, int64_t* out_u, int threads) {
   std::atomic<int64_t> next{0};
+  std::atomic<uint32_t> err{0};
   auto work = [&]() {
     std::vector<Box> stack;
     stack.reserve(256);
+    uint32_t e = 0;
     for (;;) {
       const int64_t k0 = next.fetch_add(64);
       if (k0 >= n) break;
       const int64_t k1 = std::min(k0 + 64, n);
       for (int64_t k = k0; k < k1; ++k) {
-        const Ring p = make_ring(A, pa[k]), q = make_ring(B, pb[k]);
-        const int32_t bw = std::min(p.x1, q.x1) - std::max(p.x0, q.x0);
-        const int32_t bh = std::min(p.y1, q.y1) - std::max(p.y0, q.y0);
+        bool bad_p = false, bad_q = false;
+        const Ring p = make_ring(A, pa[k], &bad_p), q = make_ring(B, pb[k], &bad_q);
+        if (bad_p || bad_q) e |= kHostErrCoord;
+        const int64_t bw = (int64_t)std::min(p.x1, q.x1) - std::max(p.x0, q.x0);
+        const int64_t bh = (int64_t)std::min(p.y1, q.y1) - std::max(p.y0, q.y0);
         if (bw > 32767 || bh > 32767) {  // rejected like the device rejects it
+          e |= kHostErrSide;
           out_i[k] = 0;
           out_u[k] = 0;
           continue;
@@ -171,15 +180,17 @@ void host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n, const 
         out_u[k] = p.area + q.area - I;
       }
     }
+    err.fetch_or(e);
   };
   threads = std::max(1, threads);
   if (threads == 1 || n < 256) {
     work();
-    return;
+    return err.load();
   }
   std::vector<std::thread> pool;
   for (int t = 0; t < threads; ++t) pool.emplace_back(work);
   for (auto& t : pool) t.join();
+  return err.load();
 }
 
 }  // namespace sccg
@@ -191,6 +202,6 @@ extern "C" int sccg_host_area_pairs(const sccg_polys* A, const sccg_polys* B, in
   if (!pair_a || !pair_b || !out_inter || !out_union) return SCCG_E_ARG;
   for (int64_t k = 0; k < n_pairs; ++k)
     if (pair_a[k] < 0 || pair_a[k] >= A->n_polys || pair_b[k] < 0 || pair_b[k] >= B->n_polys) return SCCG_E_RANGE;
-  sccg::host_area_pairs(A, B, n_pairs, pair_a, pair_b, out_inter, out_union, n_threads);
-  return SCCG_OK;
+  const uint32_t e = sccg::host_area_pairs(A, B, n_pairs, pair_a, pair_b, out_inter, out_union, n_threads);
+  return e ? SCCG_E_RANGE : SCCG_OK;
 }

@@ -1,0 +1,21 @@
+// PixelBox on the host CPU: the entry the serving path calls for jobs it
+// moves off the device.
+#pragma once
+
+#include <stdint.h>
+
+#include "sccg.h"
+
+namespace sccg {
+
+enum : uint32_t {
+  kHostErrSide = 2u,   // a pair-box side above 32767: the pair gets (0, 0)
+  kHostErrCoord = 4u,  // a ring with |coordinate| above 2^30: it covers nothing
+};
+
+// Counts of pairs (A[pa[k]], B[pb[k]]), k < n, on `threads` host threads;
+// indices must already be checked.  Returns the kHostErr* bits seen.
+uint32_t host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n, const int32_t* pa, const int32_t* pb,
+                         int64_t* out_i, int64_t* out_u, int threads);
+
+}  // namespace sccg

@@ -1,6 +1,7 @@
 // Per-polygon prepass, ring validation and the set-level Jaccard reduction.
 #include <limits.h>
 
+#include "fix192.h"
 #include "sccg_device.h"
 
 namespace sccg {
@@ -125,66 +126,7 @@ hipError_t launch_validate(const Polys& P, int64_t* first_bad, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------- Jaccard
-// Exact sum of binary64 ratios in [0, 1]: a 192-bit fixed-point integer in
-// units of 2^-128.  A ratio I/U with I >= 1 and U < 2^63 is at least 2^-63,
-// so its lowest mantissa bit is at least 2^-115 and the conversion is exact;
-// the sum of up to 2^62 ratios stays below 2^191.
-struct Fix192 {
-  uint64_t w[3] = {0, 0, 0};  // little-endian limbs
-  __device__ void add(const Fix192& o) {
-    uint64_t c = 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      uint64_t s = w[i] + o.w[i];
-      uint64_t c1 = s < w[i];
-      uint64_t s2 = s + c;
-      uint64_t c2 = s2 < s;
-      w[i] = s2;
-      c = c1 | c2;
-    }
-  }
-  __device__ void add_ratio(double r) {
-    if (!(r > 0.0)) return;
-    uint64_t bits = __double_as_longlong(r);
-    int e = (int)((bits >> 52) & 0x7ff);
-    uint64_t m = bits & ((1ull << 52) - 1);
-    if (e == 0) return;  // subnormal: impossible for a ratio >= 2^-63
-    m |= 1ull << 52;
-    // r = m * 2^(e - 1075); in 2^-128 units: m << (e - 1075 + 128)
-    int sh = e - 947;
-    if (sh < 0) return;
-    Fix192 t;
-    int limb = sh >> 6, off = sh & 63;
-    if (limb < 3) t.w[limb] = m << off;
-    if (off && limb + 1 < 3) t.w[limb + 1] = m >> (64 - off);
-    add(t);
-  }
-  // round to nearest binary64 (ties to even): the leading 64 bits with a
-  // sticky bit for everything below are exact enough for one correct rounding
-  __device__ double to_double() const {
-    int top = 2;
-    while (top >= 0 && w[top] == 0) --top;
-    if (top < 0) return 0.0;
-    int lz = __clzll(w[top]);
-    int msb = top * 64 + (63 - lz);  // bit index of the leading one
-    uint64_t lead;
-    bool sticky = false;
-    int lo_bit = msb - 63;  // bit index that lands in lead's bit 0
-    if (lo_bit <= 0) {
-      // the whole value fits in 64 bits
-      lead = w[0];
-      return ldexp((double)lead, -128);
-    }
-    int limb = lo_bit >> 6, off = lo_bit & 63;
-    lead = w[limb] >> off;
-    if (off && limb + 1 < 3) lead |= w[limb + 1] << (64 - off);
-    for (int i = 0; i < limb; ++i) sticky |= w[i] != 0;
-    sticky |= off ? (w[limb] & ((1ull << off) - 1)) != 0 : false;
-    lead |= sticky ? 1ull : 0ull;
-    return ldexp((double)lead, lo_bit - 128);
-  }
-};
-
+// Per-set sums; J' by the exact ratio sum of fix192.h.
 __global__ void __launch_bounds__(256) k_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter,
                                                  const int64_t* uni, uint32_t flags, int64_t* sum_i,
                                                  int64_t* sum_u, int64_t* n_contrib, double* jout,

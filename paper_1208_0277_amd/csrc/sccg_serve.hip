@@ -10,6 +10,11 @@
 // memory, a clear of the error word, and an event.  Uploads (DMA of the
 // job's host CSR and pairs, then a kernel that moves offsets and pair
 // indices into arena coordinates) run on a second stream.
+//
+// Migration (Section 4.2, GPU to CPU): when jobs wait for admission because
+// the arenas are full, the scheduler hands the smallest waiting job to a
+// migration thread, which runs it with the host PixelBox and sums it on the
+// host with the same exact arithmetic as the device.
 #include <string.h>
 
 #include <algorithm>
@@ -21,6 +26,8 @@
 #include <thread>
 #include <vector>
 
+#include "fix192.h"
+#include "host_pixelbox.h"
 #include "sccg_common.h"
 #include "serve_core.h"
 
@@ -31,7 +38,8 @@ namespace {
 
 constexpr int kMaxInflight = 4;
 constexpr int kStepJobs = 1024;  // most jobs in one launch (size of the per-launch sum arrays)
-constexpr int kServerStats = 10;
+constexpr int kServerStats = 12;
+constexpr int kMaxCpuThreads = 256;
 
 // Offsets of A and B move by their vertex shift; pair indices by the slot of
 // their set's first polygon.
@@ -112,12 +120,17 @@ struct sccg_server {
   Pipeline<Job> pipe;  // scheduler thread only (too_big reads fixed capacities)
   std::chrono::steady_clock::time_point t0;
   std::thread thread;
+  std::thread migrator;  // only with cfg.cpu_threads > 0
 
   std::mutex mu;
   std::condition_variable cv_work;
   std::condition_variable cv_done;
+  std::condition_variable cv_host;
   // guarded by mu
   std::deque<Job*> incoming;
+  std::deque<Job*> to_host;  // migrated jobs not started yet
+  int host_jobs = 0;         // migrated jobs not finished yet
+  bool host_stop = false;    // the migration thread may end
   std::deque<sccg_job_result> results;
   bool stop = false;
   int fatal = 0;
@@ -281,6 +294,87 @@ struct HipExec {
   }
 };
 
+// One migrated job on the host: the host PixelBox for the counts, then the
+// set sums of sccg_jaccard_sets (the same integer sums, the same binary64
+// divisions and the same exact ratio sum, so the same bits).
+sccg_job_result run_on_host(sccg_server* s, Job* j) {
+  j->t_launch = s->now();
+  std::vector<int64_t> bi, bu;
+  int64_t* oi = j->out_i;
+  int64_t* ou = j->out_u;
+  if (!oi) {
+    bi.resize((size_t)j->n_pairs);
+    oi = bi.data();
+  }
+  if (!ou) {
+    bu.resize((size_t)j->n_pairs);
+    ou = bu.data();
+  }
+  const uint32_t e = host_area_pairs(&j->A, &j->B, j->n_pairs, j->pa, j->pb, oi, ou, s->cfg.cpu_threads);
+  const bool include_zero = (s->cfg.jaccard_flags & SCCG_J_INCLUDE_ZERO) != 0;
+  uint64_t si = 0, su = 0, nn = 0;
+  Fix192 acc;
+  for (int64_t k = 0; k < j->n_pairs; ++k) {
+    const int64_t I = oi[k], U = ou[k];
+    if (!include_zero && I == 0) continue;
+    si += (uint64_t)I;
+    su += (uint64_t)U;
+    nn += 1;
+    if (U > 0) acc.add_ratio((double)I / (double)U);
+  }
+  sccg_job_result r = result_of(j, e ? SCCG_E_RANGE : SCCG_OK);
+  r.jobs_in_launch = 0;
+  r.sum_i = (int64_t)si;
+  r.sum_u = (int64_t)su;
+  r.n_contrib = (int64_t)nn;
+  r.j = r.sum_u > 0 ? (double)r.sum_i / (double)r.sum_u : 0.0;
+  r.jprime = nn > 0 ? acc.to_double() / (double)r.n_contrib : 0.0;
+  r.t_done = s->now();
+  return r;
+}
+
+// Scheduler thread: while the migration thread is idle and at least
+// cpu_trigger jobs wait for admission, move the smallest waiting job to it.
+int migrate(sccg_server* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->host_jobs > 0) return 0;
+  }
+  if ((int64_t)s->pipe.waiting() < s->cfg.cpu_trigger) return 0;
+  Job* j = s->pipe.take_smallest(s->cfg.cpu_max_pairs);
+  if (!j) return 0;
+  j->t_admit = s->now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->to_host.push_back(j);
+    s->host_jobs += 1;
+  }
+  s->cv_host.notify_one();
+  return 1;
+}
+
+void migration_thread(sccg_server* s) {
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_host.wait(lk, [s] { return !s->to_host.empty() || s->host_stop; });
+    if (s->to_host.empty()) break;
+    Job* j = s->to_host.front();
+    s->to_host.pop_front();
+    lk.unlock();
+    const sccg_job_result r = run_on_host(s, j);
+    delete j;
+    lk.lock();
+    s->results.push_back(r);
+    s->stats[1] += 1;
+    s->stats[3] += r.n_pairs;
+    s->stats[10] += 1;
+    s->stats[11] += r.n_pairs;
+    s->host_jobs -= 1;
+    s->cv_done.notify_all();
+    s->cv_work.notify_one();
+  }
+}
+
 // After a failure: wait for the streams, then complete every held job with
 // the error.
 void fail_all(sccg_server* s) {
@@ -327,13 +421,18 @@ void scheduler(sccg_server* s) {
       if (moved < 0) {
         fail_all(s);  // the executor recorded the failure
         moved = 1;
+      } else if (s->cfg.cpu_threads > 0) {
+        moved += migrate(s);
       }
     }
     lk.lock();
-    if (stopping && s->incoming.empty() && s->pipe.empty()) break;
+    if (stopping && s->incoming.empty() && s->pipe.empty() && s->host_jobs == 0) break;
     if (moved > 0 || !s->incoming.empty()) continue;
     if (!s->pipe.in_flight() && (s->pipe.empty() || s->fatal)) {
-      if (!s->stop) s->cv_work.wait(lk, [s] { return !s->incoming.empty() || s->stop; });
+      if (!s->stop)
+        s->cv_work.wait(lk, [s] { return !s->incoming.empty() || s->stop; });
+      else
+        s->cv_work.wait(lk, [s] { return !s->incoming.empty() || s->host_jobs == 0; });
     } else {
       s->cv_work.wait_for(lk, std::chrono::microseconds(20));
     }
@@ -393,9 +492,12 @@ int sccg_server_create(sccg_server** out, int hip_device, const sccg_server_conf
   if (c.pair_cap == 0) c.pair_cap = (int64_t)1 << 23;
   if (c.max_step_pairs == 0) c.max_step_pairs = (int64_t)1 << 21;
   if (c.max_inflight == 0) c.max_inflight = 2;
+  if (c.cpu_trigger == 0) c.cpu_trigger = 1;
+  if (c.cpu_max_pairs == 0) c.cpu_max_pairs = (int64_t)1 << 16;
   if (c.vertex_cap < 1 || c.vertex_cap > ((int64_t)1 << 36) || c.slot_cap < 3 || c.slot_cap > INT32_MAX ||
       c.pair_cap < 1 || c.pair_cap >= ((int64_t)1 << 31) || c.max_step_pairs < 1 || c.max_inflight < 1 ||
-      c.max_inflight > kMaxInflight || (c.jaccard_flags & ~SCCG_J_INCLUDE_ZERO))
+      c.max_inflight > kMaxInflight || (c.jaccard_flags & ~SCCG_J_INCLUDE_ZERO) || c.cpu_threads < 0 ||
+      c.cpu_threads > kMaxCpuThreads || c.cpu_trigger < 0 || c.cpu_max_pairs < 0)
     return SCCG_E_ARG;
   sccg_params p{};
   if (params) p = *params;
@@ -443,6 +545,7 @@ int sccg_server_create(sccg_server** out, int hip_device, const sccg_server_conf
     free_server(s);
     return SCCG_E_NOMEM;
   }
+  if (c.cpu_threads > 0) s->migrator = std::thread(migration_thread, s);
   s->thread = std::thread(scheduler, s);
   *out = s;
   return SCCG_OK;
@@ -546,6 +649,12 @@ int sccg_server_destroy(sccg_server* s) {
   }
   s->cv_work.notify_all();
   if (s->thread.joinable()) s->thread.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->host_stop = true;
+  }
+  s->cv_host.notify_all();
+  if (s->migrator.joinable()) s->migrator.join();
   (void)hipSetDevice(s->device);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->copy) (void)hipStreamSynchronize(s->copy);

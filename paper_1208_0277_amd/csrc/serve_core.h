@@ -216,6 +216,20 @@ class Pipeline {
   size_t waiting() const { return pending_.size(); }
   const Arenas& arenas() const { return arenas_; }
 
+  // Remove and return the waiting (not yet admitted) job with the fewest
+  // pairs among those with at most max_pairs, the earliest on a tie; nullptr
+  // if there is none.  The host-migration of Section 4.2 takes the smallest
+  // tasks out of a congested device's input buffer.
+  Job* take_smallest(int64_t max_pairs) {
+    auto best = pending_.end();
+    for (auto it = pending_.begin(); it != pending_.end(); ++it)
+      if ((*it)->n_pairs <= max_pairs && (best == pending_.end() || (*it)->n_pairs < (*best)->n_pairs)) best = it;
+    if (best == pending_.end()) return nullptr;
+    Job* j = *best;
+    pending_.erase(best);
+    return j;
+  }
+
   template <class Exec>
   int pump(Exec& ex) {
     int moved = 0;

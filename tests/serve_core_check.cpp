@@ -4,6 +4,7 @@
 // number of polls, and can be told to fail.  Built and run by
 // tests/test_serve_core.py; prints "ALL OK" and exits 0 on success.
 #include <stdio.h>
+#include <stdint.h>
 #include <stdlib.h>
 
 #include <random>
@@ -114,6 +115,7 @@ struct FJob {
   int64_t n_pairs = 0;
   bool counted_wait = false;
   int waits = 0;
+  bool uploaded = false, migrated = false;
 };
 
 struct FakeExec {
@@ -124,8 +126,9 @@ struct FakeExec {
   std::vector<int> own[3];  // owner job id of each arena element, 0 = free
   std::deque<std::pair<int, int>> launches;  // (slot, polls left)
   std::vector<bool> slot_busy;
-  int next_launch_id = 1;  // next job expected in a launch
-  int next_retire_id = 1;  // next job expected to finish
+  int last_upload_id = 0;  // admissions and launches follow submission order
+  int last_launch_id = 0;
+  std::deque<int> launched_ids;  // jobs finish in launch order
   int admitted = 0, finished = 0, launched_n = 0, waits = 0;
   int fail_at = -1, calls = 0;  // fail the fail_at-th executor call
   bool ok = true;
@@ -169,6 +172,12 @@ struct FakeExec {
   }
   bool upload(FJob* j) {
     if (failing()) return false;
+    if (j->id <= last_upload_id || j->migrated) {
+      fprintf(stderr, "FAIL: job %d admitted out of order or after migrating\n", j->id);
+      ok = false;
+    }
+    last_upload_id = j->id;
+    j->uploaded = true;
     if (!mark(j, true)) ok = false;
     admitted += 1;
     return ok;
@@ -185,14 +194,15 @@ struct FakeExec {
     if (slot_busy[slot]) fail("slot reused while its launch is in flight");
     int64_t pos = st.pair_off, total = 0;
     for (int c = 0; c < st.count; ++c) {
-      if (jobs[c]->id != next_launch_id + c) fail("jobs not launched in submission order");
+      if (jobs[c]->id <= last_launch_id) fail("jobs not launched in submission order");
+      last_launch_id = jobs[c]->id;
+      launched_ids.push_back(jobs[c]->id);
       if (jobs[c]->pl.pair_off != pos) fail("pair range not contiguous");
       pos += jobs[c]->n_pairs;
       total += jobs[c]->n_pairs;
     }
     if (total != st.n_pairs) fail("n_pairs is not the jobs' sum");
     if (st.count > 1 && st.n_pairs > max_step_pairs) fail("launch above max_step_pairs");
-    next_launch_id += st.count;
     launches.push_back({slot, (int)(rng() % 4)});
     slot_busy[slot] = true;
     launched_n += 1;
@@ -201,11 +211,11 @@ struct FakeExec {
   }
   void finish(const Step& st, FJob* const* jobs, int slot) {
     for (int c = 0; c < st.count; ++c) {
-      if (jobs[c]->id != next_retire_id) {
-        fprintf(stderr, "FAIL: job %d finished, expected %d\n", jobs[c]->id, next_retire_id);
+      if (launched_ids.empty() || jobs[c]->id != launched_ids.front()) {
+        fprintf(stderr, "FAIL: job %d finished out of launch order\n", jobs[c]->id);
         ok = false;
       }
-      next_retire_id += 1;
+      if (!launched_ids.empty()) launched_ids.pop_front();
       if (!mark(jobs[c], false)) ok = false;
       finished += 1;
     }
@@ -214,7 +224,11 @@ struct FakeExec {
   }
 };
 
-static bool pipeline_random(uint64_t seed, int fail_at) {
+// With `migrate`, some pumps are followed by take_smallest (the host
+// migration): the job it returns must be the waiting one with the fewest
+// pairs under the bound (the earliest on a tie), and it never runs on the
+// device.
+static bool pipeline_random(uint64_t seed, int fail_at, bool migrate = false) {
   std::mt19937_64 rng(seed);
   const int64_t vcap = 50 + (int64_t)(rng() % 400), scap = 20 + (int64_t)(rng() % 100),
                 pcap = 10 + (int64_t)(rng() % 200);
@@ -234,7 +248,7 @@ static bool pipeline_random(uint64_t seed, int fail_at) {
   ex.fail_at = fail_at;
   std::vector<FJob*> all;
   const int n_jobs = 300;
-  int submitted = 0, rejected = 0, dropped = 0;
+  int submitted = 0, rejected = 0, dropped = 0, migrated = 0;
   bool failed = false;
   for (int round = 0; round < 100000 && !failed; ++round) {
     if (submitted < n_jobs && rng() % 3 == 0) {
@@ -255,6 +269,24 @@ static bool pipeline_random(uint64_t seed, int fail_at) {
     }
     const int moved = pipe.pump(ex);
     if (!ex.ok) return false;
+    if (migrate && moved >= 0 && rng() % 4 == 0) {
+      const int64_t bound = rng() % 2 ? INT64_MAX : 1 + (int64_t)(rng() % (uint64_t)(pcap / 2));
+      const FJob* want = nullptr;
+      size_t n_waiting = 0;
+      for (const FJob* w : all) {
+        if (w->uploaded || w->migrated) continue;
+        n_waiting += 1;
+        if (w->n_pairs <= bound && (!want || w->n_pairs < want->n_pairs)) want = w;
+      }
+      CHECK(n_waiting == pipe.waiting(), "waiting() %zu, expected %zu", pipe.waiting(), n_waiting);
+      FJob* got = pipe.take_smallest(bound);
+      CHECK(got == want, "take_smallest returned job %d, expected job %d", got ? got->id : 0, want ? want->id : 0);
+      if (got) {
+        got->migrated = true;
+        migrated += 1;
+        CHECK(pipe.waiting() == n_waiting - 1, "the migrated job is still waiting");
+      }
+    }
     if (moved < 0) {
       CHECK(fail_at > 0, "pump failed without an injected failure");
       pipe.drain([&](FJob* j) {
@@ -266,16 +298,18 @@ static bool pipeline_random(uint64_t seed, int fail_at) {
     if (submitted >= n_jobs && pipe.empty()) break;
   }
   const int accepted = submitted;
+  if (migrate && fail_at < 0) CHECK(migrated > 0, "seed %llu: nothing migrated", (unsigned long long)seed);
   if (!failed) {
     CHECK(pipe.empty(), "pipeline did not drain (%d of %d finished)", ex.finished, accepted);
-    CHECK(ex.finished == accepted, "%d of %d jobs finished", ex.finished, accepted);
+    CHECK(ex.finished + migrated == accepted, "%d finished + %d migrated of %d jobs", ex.finished, migrated,
+          accepted);
     CHECK(pipe.arenas().vertices().used() == 0 && pipe.arenas().slots().used() == 0 &&
               pipe.arenas().pairs().used() == 0,
           "arenas not empty at the end");
   } else {
     // every accepted job is either finished or handed back by drain, once
-    CHECK(ex.finished + dropped == accepted, "%d finished + %d dropped != %d accepted", ex.finished, dropped,
-          accepted);
+    CHECK(ex.finished + dropped + migrated == accepted, "%d finished + %d dropped + %d migrated != %d accepted",
+          ex.finished, dropped, migrated, accepted);
     CHECK(pipe.empty() && !pipe.in_flight(), "drain left state behind");
   }
   for (FJob* j : all) {
@@ -292,6 +326,8 @@ int main() {
   n += plan_cases();
   for (uint64_t seed = 1; seed <= 200; ++seed) n += pipeline_random(seed, -1);
   for (uint64_t seed = 1; seed <= 50; ++seed) n += pipeline_random(1000 + seed, 5 + (int)(seed * 13 % 200));
+  for (uint64_t seed = 1; seed <= 100; ++seed) n += pipeline_random(2000 + seed, -1, true);
+  for (uint64_t seed = 1; seed <= 30; ++seed) n += pipeline_random(3000 + seed, 5 + (int)(seed * 17 % 200), true);
   if (g_fail) {
     fprintf(stderr, "%d checks passed before the failure\n", n);
     return 1;

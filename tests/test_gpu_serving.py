@@ -58,13 +58,13 @@ def collect(srv, n, deadline_s=120.0):
     return out
 
 
-def check_job(r, outs, wl_res, s, n):
+def check_job(r, outs, wl_res, s, n, flags=sccg.SCCG_J_NONZERO_ONLY):
     I, U = wl_res
     gi, gu = outs
     assert r["status"] == sccg.SCCG_OK
     assert r["n_pairs"] == n
     assert np.array_equal(gi, I[s:s + n]) and np.array_equal(gu, U[s:s + n]), f"job window {s}+{n} counts differ"
-    si, su, nn, j, jp = expected_sets(I[s:s + n], U[s:s + n])
+    si, su, nn, j, jp = expected_sets(I[s:s + n], U[s:s + n], flags)
     assert (r["sum_i"], r["sum_u"], r["n_contrib"]) == (si, su, nn)
     assert r["j"] == j and r["jprime"] == jp
     assert r["t_submit"] <= r["t_admit"] <= r["t_launch"] <= r["t_done"]
@@ -216,3 +216,45 @@ def test_range_error_is_reported_per_launch(corpus):
             check_job(res[j2], (oi, ou), (I, U), s, n)
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("flags", [sccg.SCCG_J_NONZERO_ONLY, sccg.SCCG_J_INCLUDE_ZERO])
+def test_migration_to_host_threads(corpus, flags):
+    """Arenas too small for the offered load: jobs wait for admission, and the
+    smallest waiting ones (at most cpu_max_pairs) run on host threads.  Every
+    job, migrated or not, equals the oracle bit for bit, J' included."""
+    wl, I, U = corpus
+    rng = np.random.default_rng(21)
+    windows = [(int(rng.integers(0, wl.n_pairs - 800)), int(rng.integers(1, 800))) for _ in range(80)]
+    vmax = max(int(wl.A.off[s + n] - wl.A.off[s] + wl.B.off[s + n] - wl.B.off[s]) for s, n in windows)
+    srv = sccg.Server(0, vertex_cap=int(vmax * 2.5), slot_cap=4000, pair_cap=2000, max_step_pairs=700,
+                      max_inflight=2, jaccard_flags=flags, cpu_threads=4, cpu_trigger=1, cpu_max_pairs=400)
+    try:
+        jobs = submit_windows(srv, wl, windows)
+        res = collect(srv, len(jobs))
+        for jid, (s, n, oi, ou) in jobs.items():
+            check_job(res[jid], (oi, ou), (I, U), s, n, flags)
+        st = srv.stats()
+    finally:
+        srv.close()
+    moved = [jid for jid, r in res.items() if r["jobs_in_launch"] == 0]
+    assert st["admission_waits"] > 0
+    assert st["jobs_migrated"] == len(moved) > 0
+    assert st["pairs_migrated"] == sum(jobs[jid][1] for jid in moved)
+    assert all(jobs[jid][1] <= 400 for jid in moved)
+    assert st["jobs_done"] == len(windows) and st["pairs_done"] == sum(n for _, n in windows)
+
+
+def test_migration_off_by_default(corpus):
+    wl, I, U = corpus
+    srv = sccg.Server(0, vertex_cap=200000, slot_cap=4000, pair_cap=2000, max_step_pairs=700)
+    try:
+        rng = np.random.default_rng(22)
+        jobs = submit_windows(srv, wl, [(int(rng.integers(0, 19000)), int(rng.integers(1, 800))) for _ in range(30)])
+        res = collect(srv, len(jobs))
+        for jid, (s, n, oi, ou) in jobs.items():
+            check_job(res[jid], (oi, ou), (I, U), s, n)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["jobs_migrated"] == 0 and all(r["jobs_in_launch"] >= 1 for r in res.values())

@@ -66,3 +66,17 @@ def test_range_error_and_empty(lib, cfg1):
         _run(cfg1.A, cfg1.B, np.array([cfg1.A.n], np.int32), np.array([0], np.int32))
     I, U = _run(cfg1.A, cfg1.B, np.zeros(0, np.int32), np.zeros(0, np.int32))
     assert len(I) == 0 and len(U) == 0
+
+
+def test_rejections_report_range_after_writing(lib):
+    """A ring beyond 2^30 covers nothing and a pair box wider than 32767
+    gives (0, 0); both make the call fail with SCCG_E_RANGE."""
+    sq = lambda x, y, w, h: np.array([[x, y], [x + w, y], [x + w, y + h], [x, y + h]], np.int32)
+    off = np.array([0, 4, 8], np.int64)
+    a_xy = np.concatenate([sq((1 << 30) + 5, 0, 10, 10), sq(0, 0, 40000, 3)]).reshape(-1)
+    b_xy = np.concatenate([sq((1 << 30) + 6, 1, 4, 4), sq(0, 0, 40000, 3)]).reshape(-1)
+    for k in range(2):
+        idx = np.array([k], np.int32)
+        with pytest.raises(sccg.SccgError) as e:
+            sccg.host_area_pairs(off, a_xy, off, b_xy, idx, idx)
+        assert e.value.code == sccg.SCCG_E_RANGE
