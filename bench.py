@@ -176,7 +176,7 @@ def serve_bench(args):
     log(f"corpus: {corpus_n} pairs, {len(wl.A.xy) + len(wl.B.xy)} vertices (pinned), oracle counts in "
         f"{time.perf_counter() - t0:.1f} s")
     local = np.arange(5 * 10 ** 5, dtype=np.int32)
-    srv = sccg.Server(0)
+    srv = sccg.Server(0, cpu_threads=args.cpu_threads)
     rng = np.random.default_rng(sccg_gen.BASE_SEED + 5)
     out_rates, all_exact = [], True
     try:
@@ -188,7 +188,7 @@ def serve_bench(args):
             n_jobs = args.jobs
             sizes = np.exp(rng.uniform(math.log(1e3), math.log(5e5), n_jobs)).astype(np.int64)
             starts = rng.integers(0, corpus_n - sizes + 1)
-            arrive = np.cumsum(rng.exponential(1.0 / lam, n_jobs))
+            arrive = np.cumsum(rng.exponential(1.0 / lam, n_jobs))  # rate inf: all at once
             outs, errors = {}, []
             lock = threading.Lock()
 
@@ -241,11 +241,15 @@ def serve_bench(args):
             rec = {"rate_jobs_per_s": lam, "jobs": n_jobs, "measured_jobs": len(meas),
                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                    "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
-                   "pairs_per_s": pairs / span, "offered_pairs_per_s": float(sizes.mean() * lam),
+                   "pairs_per_s": pairs / span,
+                   "offered_pairs_per_s": float(sizes.mean() * lam) if math.isfinite(lam) else None,
                    "launches": st1["launches"] - st0["launches"], "max_jobs_per_launch": st1["max_jobs_per_launch"],
-                   "admission_waits": st1["admission_waits"] - st0["admission_waits"], "bit_exact": bool(exact)}
+                   "admission_waits": st1["admission_waits"] - st0["admission_waits"],
+                   "jobs_migrated": st1["jobs_migrated"] - st0["jobs_migrated"],
+                   "pairs_migrated": st1["pairs_migrated"] - st0["pairs_migrated"], "bit_exact": bool(exact)}
             log(f"rate {lam:g}/s: p50 {rec['p50_ms']:.2f} ms, p99 {rec['p99_ms']:.2f} ms, "
-                f"{rec['pairs_per_s'] / 1e6:.2f} Mpairs/s served, {rec['launches']} launches, exact {exact}")
+                f"{rec['pairs_per_s'] / 1e6:.2f} Mpairs/s served, {rec['launches']} launches, "
+                f"{rec['jobs_migrated']} jobs migrated, exact {exact}")
             out_rates.append(rec)
     finally:
         srv.close()
@@ -254,8 +258,9 @@ def serve_bench(args):
         "metric": METRIC, "value": top["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
         "steps": args.jobs, "warmup": 20, "ms_per_step": top["mean_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": WORKLOADS[5], "corpus_pairs": corpus_n, "rates": rates,
-                   "parallelism": "none (1 GPU)"},
+        "config": {"workload": WORKLOADS[5], "corpus_pairs": corpus_n,
+                   "rates": [r if math.isfinite(r) else "all at once" for r in rates],
+                   "cpu_threads": args.cpu_threads, "parallelism": "none (1 GPU)"},
         "serving": out_rates, "bit_exact_oracle_sample": bool(all_exact), "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -339,6 +344,8 @@ def main(argv=None):
     ap.add_argument("--workload", type=int, default=3, choices=[1, 2, 3, 4, 5, 6])
     ap.add_argument("--rates", type=str, default="5,20,80", help="workload 5: arrival rates (jobs/s)")
     ap.add_argument("--jobs", type=int, default=600, help="workload 5: jobs per rate")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="workload 5: host threads for jobs migrated off a full device (0 = no migration)")
     ap.add_argument("--tiles", type=int, default=64, help="workload 4: number of tiles")
     ap.add_argument("--pairs", type=int, default=None, help="override the pair count (not the headline)")
     ap.add_argument("--plain-steps", type=int, default=1)
