@@ -186,10 +186,10 @@ __device__ __forceinline__ int2 lane_value(int2 v, int l) {
 // Load the first two 64-vertex chunks of a ring with one coalesced load each;
 // each vertex's successor comes from the neighbouring lane, lane 63's from
 // the next chunk, and the last vertex's is vertex 0.
-__device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int64_t nv, int lane, RingRegs& r,
+__device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int nv, int lane, RingRegs& r,
                                            int2& first, const int2* pre) {
   // pre: the prefetched first two chunks (pre[0] = vertex lane, pre[1] = vertex lane + 64)
-  const int64_t k0 = lane, k1 = lane + kWave;
+  const int k0 = lane, k1 = lane + kWave;
   r.v0 = pre ? pre[0] : (k0 < nv ? xy[o + k0] : make_int2(0, 0));
   r.v1 = pre ? pre[1] : (k1 < nv ? xy[o + k1] : make_int2(0, 0));
   first = lane_value(r.v0, 0);
@@ -207,69 +207,70 @@ __device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int64_t nv
 }
 
 // Extent and |shoelace|/2 of one ring (Section 3.2's area formula), reduced
-// across the wave.  Fast form: coordinates relative to the first vertex fit in
-// [-2^14, 2^14), so (dx, dy) pack into int16 pairs (one packed min and one
-// packed max reduction) and twice the area, below 2^31, is exact in wrapping
-// 32-bit arithmetic with 24-bit multiplies.  Rings that do not fit are
-// rescanned in 32/64-bit.  Empty rings and rings with |coordinate| > 2^30
-// come back empty.
-__device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t nv, int lane, RingRegs& r, Meta& m,
+// across the wave.  Lanes past the end of the ring stand at the first vertex:
+// they leave the extent alone and add a zero shoelace term.  The terms use
+// coordinates relative to the first vertex in wrapping 32-bit arithmetic with
+// 24-bit multiplies, which is exact when the extent is below 2^14 on both
+// axes (twice the area is then below 2^29); a wider ring has its area summed
+// again in 64 bits.  Empty rings and rings with |coordinate| > 2^30 come back
+// empty.
+__device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t nv64, int lane, RingRegs& r, Meta& m,
                                             int64_t& area, const int2* pre = nullptr) {
+  const int nv = uniform((int)nv64);
   int2 first;
   load_ring2(xy, o, nv, lane, r, first, pre);
-  uint32_t pmin = 0x7fff7fffu, pmax = 0x80008000u, twice = 0u, wide = 0u;
-  for (int base = 0; base < (int)nv; base += kWave) {
+  int x0, y0, x1, y1;
+  uint32_t twice;
+  {
+    const bool ok = lane < nv;
+    const int vx = ok ? r.v0.x : first.x, vy = ok ? r.v0.y : first.y;
+    x0 = x1 = vx;
+    y0 = y1 = vy;
+    const int dx = vx - first.x, dy = vy - first.y;
+    twice = (uint32_t)__mul24(dx, r.w0.y - first.y) - (uint32_t)__mul24(r.w0.x - first.x, dy);
+  }
+  if (nv > kWave) {
+    const bool ok = lane + kWave < nv;
+    const int vx = ok ? r.v1.x : first.x, vy = ok ? r.v1.y : first.y;
+    x0 = min(x0, vx);
+    y0 = min(y0, vy);
+    x1 = max(x1, vx);
+    y1 = max(y1, vy);
+    const int dx = vx - first.x, dy = vy - first.y;
+    twice += (uint32_t)__mul24(dx, r.w1.y - first.y) - (uint32_t)__mul24(r.w1.x - first.x, dy);
+  }
+#pragma unroll 1
+  for (int base = 2 * kWave; base < nv; base += kWave) {
     const int k = base + lane;
     int2 v, w;
-    if (base == 0) {
-      v = r.v0;
-      w = r.w0;
-    } else if (base == kWave) {
-      v = r.v1;
-      w = r.w1;
-    } else {
-      load_edge(xy, o, nv, k, v, w);
-    }
-    if (k < nv) {
-      const int dx = v.x - first.x, dy = v.y - first.y;
-      const int ex = w.x - first.x, ey = w.y - first.y;
-      wide |= (uint32_t)((dx + 16384) | (dy + 16384)) >> 15;
-      const uint32_t pk = ((uint32_t)dx & 0xffffu) | ((uint32_t)dy << 16);
-      pmin = op_pkmin_i16(pmin, pk);
-      pmax = op_pkmax_i16(pmax, pk);
-      twice += (uint32_t)__mul24(dx, ey) - (uint32_t)__mul24(ex, dy);
-    }
+    load_edge(xy, o, nv, k, v, w);
+    const bool ok = k < nv;
+    const int vx = ok ? v.x : first.x, vy = ok ? v.y : first.y;
+    x0 = min(x0, vx);
+    y0 = min(y0, vy);
+    x1 = max(x1, vx);
+    y1 = max(y1, vy);
+    const int dx = vx - first.x, dy = vy - first.y;
+    twice += (uint32_t)__mul24(dx, w.y - first.y) - (uint32_t)__mul24(w.x - first.x, dy);
   }
-  const bool any_wide = ballot(wide != 0u) != 0ull;
-  if (!any_wide) {
-    const uint32_t mn = wave_pkmin_i16(pmin), mx = wave_pkmax_i16(pmax);
-    const int32_t t = (int32_t)wave_sum_u32(twice);
-    m.x0 = first.x + (int32_t)(int16_t)(mn & 0xffffu);
-    m.y0 = first.y + (int32_t)(int16_t)(mn >> 16);
-    m.x1 = first.x + (int32_t)(int16_t)(mx & 0xffffu);
-    m.y1 = first.y + (int32_t)(int16_t)(mx >> 16);
+  m.x0 = wave_min_i32(x0);
+  m.y0 = wave_min_i32(y0);
+  m.x1 = wave_max_i32(x1);
+  m.y1 = wave_max_i32(y1);
+  const int32_t t = (int32_t)wave_sum_u32(twice);
+  if ((uint32_t)(m.x1 - m.x0) < 16384u && (uint32_t)(m.y1 - m.y0) < 16384u) {
     area = (int64_t)(t < 0 ? -(int64_t)t : (int64_t)t) / 2;
   } else {
-    int32_t x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
     uint64_t tw = 0;
-    for (int base = 0; base < (int)nv; base += kWave) {
+#pragma unroll 1
+    for (int base = 0; base < nv; base += kWave) {
       const int k = base + lane;
       int2 v, w;
       load_edge(xy, o, nv, k, v, w);
-      if (k < nv) {
-        x0 = min(x0, v.x);
-        y0 = min(y0, v.y);
-        x1 = max(x1, v.x);
-        y1 = max(y1, v.y);
-        tw += (uint64_t)((int64_t)v.x * w.y) - (uint64_t)((int64_t)w.x * v.y);
-      }
+      if (k < nv) tw += (uint64_t)((int64_t)v.x * w.y) - (uint64_t)((int64_t)w.x * v.y);
     }
-    m.x0 = wave_min_i32(x0);
-    m.y0 = wave_min_i32(y0);
-    m.x1 = wave_max_i32(x1);
-    m.y1 = wave_max_i32(y1);
-    const int64_t t = (int64_t)wave_sum_u64(tw);
-    area = (t < 0 ? -t : t) / 2;
+    const int64_t t64 = (int64_t)wave_sum_u64(tw);
+    area = (t64 < 0 ? -t64 : t64) / 2;
   }
   if (nv <= 0 || m.x0 < -kMaxCoord || m.y0 < -kMaxCoord || m.x1 > kMaxCoord || m.y1 > kMaxCoord) {
     m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};  // covers nothing
@@ -398,6 +399,18 @@ __device__ __forceinline__ void scatter_ring(Ctx& c, const int2* xy, int64_t o, 
   }
 }
 
+// Zero for clearing leaf slots, made where it is stored: a zero the compiler
+// hoists into a long-lived register pair gets spilled to scratch under this
+// kernel's register pressure.
+template <typename M>
+__device__ __forceinline__ M fresh_zero() {
+  uint32_t lo, hi;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(lo));
+  if (sizeof(M) == 4) return (M)lo;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(hi));
+  return (M)(((uint64_t)hi << 32) | lo);
+}
+
 // Intersection count of a small pair (box <= 64 x 64 = one leaf tile).
 // Narrow boxes (w <= 32) run p in lanes 0-31 and q in lanes 32-63 with one
 // scan; short boxes (h <= 32) use 32-bit row masks.
@@ -412,7 +425,7 @@ __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const 
   const bool direct = direct_union(a);
   uint32_t n = 0, nu = 0;
   if (tw <= 32) {
-    slots[lane] = 0;
+    slots[lane] = fresh_zero<M>();
     wave_sync_lds();
     scatter_ring(c, a.A.xy, pi.op, pi.np, &rp, tx0, ty0, th, 32, slots, 0);
     scatter_ring(c, a.B.xy, pi.oq, pi.nq, &rq, tx0, ty0, th, 32, slots, 32);
@@ -433,8 +446,8 @@ __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const 
       nu = (uint32_t)__popcll((uint64_t)(m | mq));
     }
   } else {
-    slots[lane] = 0;
-    slots[kWave + lane] = 0;
+    slots[lane] = fresh_zero<M>();
+    slots[kWave + lane] = fresh_zero<M>();
     wave_sync_lds();
     scatter_ring(c, a.A.xy, pi.op, pi.np, &rp, tx0, ty0, th, kWave, slots, 0);
     scatter_ring(c, a.B.xy, pi.oq, pi.nq, &rq, tx0, ty0, th, kWave, slots, kWave);
@@ -461,8 +474,8 @@ __device__ __forceinline__ uint64_t leaf_count(Ctx& c, const PairInfo& pi, int t
   const BatchArgs& a = *c.a;
   const int lane = c.lane;
   uint64_t* slots = c.slots;
-  slots[lane] = 0;
-  slots[kWave + lane] = 0;
+  slots[lane] = fresh_zero<uint64_t>();
+  slots[kWave + lane] = fresh_zero<uint64_t>();
   wave_sync_lds();
   uint64_t fp = 0, fq = 0;
   if (!kp) scatter_ring(c, a.A.xy, pi.op, pi.np, (const RingRegs*)nullptr, tx0, ty0, th, kWave, slots, 0, &fp);
@@ -552,8 +565,8 @@ __device__ __forceinline__ void scatter_band(Ctx& c, const uint32_t* list, int n
 __device__ __forceinline__ uint64_t leaf_from_band(Ctx& c, int np, int nq, int off, int tw, int th) {
   const int lane = c.lane;
   uint64_t* slots = c.slots;
-  slots[lane] = 0;
-  slots[kWave + lane] = 0;
+  slots[lane] = fresh_zero<uint64_t>();
+  slots[kWave + lane] = fresh_zero<uint64_t>();
   wave_sync_lds();
   uint64_t fp = 0, fq = 0;
   if (np >= 0) scatter_band(c, c.band, np, off, slots, 0, fp);

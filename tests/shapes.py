@@ -29,6 +29,14 @@ def band_ring(y, a, b):
     return np.array(pts, np.int32)
 
 
+def staircase(n_bands, height, step, width):
+    """Bands (y, a, b) of a staircase: n_bands bands over [0, height), band k
+    spanning [step*k, step*k + width); step < width keeps it one polygon."""
+    y = [round(k * height / n_bands) for k in range(n_bands + 1)]
+    a = [step * k for k in range(n_bands)]
+    return y, a, [x + width for x in a]
+
+
 def band_rects(y, a, b):
     return [(a[k], y[k], b[k], y[k + 1]) for k in range(len(a))]
 

@@ -10,7 +10,7 @@ import paper_1208_0277_amd as sccg
 import sccg_gen
 from sccg_gen import Polys, concat
 from tests.gpu_util import assert_exact, device_workload, run
-from tests.shapes import band_ring, random_bands, rects_area, rects_inter, transform
+from tests.shapes import band_rects, band_ring, random_bands, rects_area, rects_inter, staircase, transform
 
 pytestmark = pytest.mark.gpu
 
@@ -283,6 +283,34 @@ def test_range_errors_latch_and_zero(ctx, mode):
     assert gI.tolist() == [25, 0, 0, 0]
     assert gU.tolist()[0] == 25 and gU.tolist()[1] == 0 and gU.tolist()[3] == 0
     assert gU.tolist()[2] == 25  # the rejected polygon counts as empty
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_wide_rings_exact_areas(ctx, mode):
+    """Rings whose extent reaches 2^14 or more on an axis take the 64-bit
+    area path; each is paired with a small ring so that the pair box stays in
+    range.  Counts are closed forms of band rectangles."""
+    sq = lambda x, y, s: ([y, y + s], [x], [x + s])
+    cases = [
+        (([0, 10], [0], [20000]), sq(100, -5, 30)),                # 20000 x 10 band
+        (staircase(150, 30000, 200, 1000), sq(15100, 15050, 50)),  # 600 vertices, 30800 x 30000
+        (staircase(300, 30000, 100, 2000), sq(15100, 15050, 50)),  # 1200 vertices (heavy pair)
+        (([-(1 << 29), 1 << 29], [-(1 << 29)], [1 << 29]), sq(7, -3, 10)),  # twice its area needs 62 bits
+        (staircase(150, 30000, 200, 1000), sq(29000, 100, 40)),    # wide ring, no common pixel
+    ]
+    rings_a, rings_b, expect = [], [], []
+    for pa_b, pb_b in cases:
+        rings_a.append(band_ring(*pa_b))
+        rings_b.append(band_ring(*pb_b))
+        ra, rb = band_rects(*pa_b), band_rects(*pb_b)
+        i = rects_inter(ra, rb)
+        expect.append((i, rects_area(ra) + rects_area(rb) - i))
+    A, B = concat(rings_a), concat(rings_b)
+    idx = np.arange(len(cases), dtype=np.int32)
+    I, U = ctx.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
+    assert ctx.sync_code() == sccg.SCCG_OK
+    got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
+    assert got == expect
 
 
 def test_validate_polys(ctx):

@@ -11,7 +11,7 @@ import oracle
 import paper_1208_0277_amd as sccg
 import sccg_gen
 from sccg_gen import concat
-from tests.shapes import random_bands, rects_area, rects_inter, transform
+from tests.shapes import band_rects, band_ring, random_bands, rects_area, rects_inter, staircase, transform
 
 
 @pytest.fixture(scope="module")
@@ -80,3 +80,19 @@ def test_rejections_report_range_after_writing(lib):
         with pytest.raises(sccg.SccgError) as e:
             sccg.host_area_pairs(off, a_xy, off, b_xy, idx, idx)
         assert e.value.code == sccg.SCCG_E_RANGE
+
+
+def test_wide_rings_closed_form(lib):
+    sq = lambda x, y, s: ([y, y + s], [x], [x + s])
+    cases = [(([0, 10], [0], [20000]), sq(100, -5, 30)),
+             (staircase(300, 30000, 100, 2000), sq(15100, 15050, 50)),
+             (([-(1 << 29), 1 << 29], [-(1 << 29)], [1 << 29]), sq(7, -3, 10))]
+    A = concat([band_ring(*p) for p, _ in cases])
+    B = concat([band_ring(*q) for _, q in cases])
+    expect = []
+    for p, q in cases:
+        i = rects_inter(band_rects(*p), band_rects(*q))
+        expect.append((i, rects_area(band_rects(*p)) + rects_area(band_rects(*q)) - i))
+    idx = np.arange(len(cases), dtype=np.int32)
+    I, U = _run(A, B, idx, idx)
+    assert list(zip(I.tolist(), U.tolist())) == expect
