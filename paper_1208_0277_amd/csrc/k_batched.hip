@@ -98,8 +98,7 @@ __device__ __forceinline__ uint64_t spread(uint32_t colbyte) { return (uint64_t)
 __device__ __forceinline__ uint32_t cols_bits(int i0, int i1) { return (0xFFu >> (7 - i1)) & (0xFFu << i0) & 0xFFu; }
 // rows [lo, hi) of a 64-row tile, 0 <= lo < hi <= 64
 __device__ __forceinline__ uint64_t row_range(int lo, int hi) {
-  const uint64_t top = (hi >= 64) ? ~0ull : ((1ull << hi) - 1);
-  return top & ~((1ull << lo) - 1);
+  return (~0ull << lo) & (~0ull >> (64 - hi));
 }
 
 // ----------------------------------------------------------------- context
@@ -164,15 +163,6 @@ struct RingRegs {
   int2 v0, w0, v1, w1;
 };
 
-__device__ __forceinline__ void load_edge(const int2* xy, int64_t o, int64_t nv, int64_t k, int2& v, int2& w) {
-  if (k < nv) {
-    v = xy[o + k];
-    w = xy[o + (k + 1 == nv ? 0 : k + 1)];
-  } else {
-    v = w = make_int2(0, 0);
-  }
-}
-
 // The value of the next lane (DPP wave shift left by one; lane 63 reads 0).
 __device__ __forceinline__ int2 next_lane(int2 v) {
   return make_int2(__builtin_amdgcn_update_dpp(0, v.x, 0x130, 0xf, 0xf, false),
@@ -182,6 +172,45 @@ __device__ __forceinline__ int2 next_lane(int2 v) {
 __device__ __forceinline__ int2 lane_value(int2 v, int l) {
   return make_int2(__builtin_amdgcn_readlane(v.x, l), __builtin_amdgcn_readlane(v.y, l));
 }
+
+// A ring read 64 vertices at a time with one chunk in flight ahead: lane L
+// holds vertex base + L in `cur` and vertex base + 64 + L in `nxt`, whose
+// load was issued one chunk earlier.  A vertex's successor is the next
+// lane's vertex; lane 63's is lane 0 of `nxt`, and the last vertex's is the
+// first.  `nv` (>= 1) must be wave-uniform.  Lanes past the end load the
+// last vertex again (the index is clamped, so the loads need no branch) and
+// must be masked with valid(): the successor shift reads across lanes, so
+// no lane may be switched off around it, and a per-lane branch in the loop
+// body lets the compiler split the wave.
+struct RingStream {
+  const int2* p;
+  int nv, base, lane;
+  int2 first, cur, nxt;
+
+  __device__ __forceinline__ int2 at(int k) const { return p[min(k, nv - 1)]; }
+  __device__ __forceinline__ RingStream(const int2* xy, int64_t o, int nv_, int lane_, int base0 = 0,
+                                        const int2* first_ = nullptr)
+      : p(xy + o), nv(uniform(nv_)), base(uniform(base0)), lane(lane_) {
+    cur = at(base + lane);
+    nxt = at(base + kWave + lane);
+    first = first_ ? *first_ : lane_value(cur, 0);
+  }
+  __device__ __forceinline__ bool valid() const { return base + lane < nv; }
+  // successor of this lane's vertex (every lane takes part)
+  __device__ __forceinline__ int2 succ() const {
+    const int2 s = next_lane(cur);
+    const int2 n0 = lane_value(nxt, 0);
+    const bool wrap = base + lane + 1 == nv, last = lane == kWave - 1;
+    return make_int2(wrap ? first.x : (last ? n0.x : s.x), wrap ? first.y : (last ? n0.y : s.y));
+  }
+  __device__ __forceinline__ bool next() {
+    base = uniform(base + kWave);
+    if (base >= nv) return false;
+    cur = nxt;
+    nxt = at(base + kWave + lane);
+    return true;
+  }
+};
 
 // Load the first two 64-vertex chunks of a ring with one coalesced load each;
 // each vertex's successor comes from the neighbouring lane, lane 63's from
@@ -239,19 +268,20 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
     const int dx = vx - first.x, dy = vy - first.y;
     twice += (uint32_t)__mul24(dx, r.w1.y - first.y) - (uint32_t)__mul24(r.w1.x - first.x, dy);
   }
+  if (nv > 2 * kWave) {
+    RingStream rs(xy, o, nv, lane, 2 * kWave, &first);
 #pragma unroll 1
-  for (int base = 2 * kWave; base < nv; base += kWave) {
-    const int k = base + lane;
-    int2 v, w;
-    load_edge(xy, o, nv, k, v, w);
-    const bool ok = k < nv;
-    const int vx = ok ? v.x : first.x, vy = ok ? v.y : first.y;
-    x0 = min(x0, vx);
-    y0 = min(y0, vy);
-    x1 = max(x1, vx);
-    y1 = max(y1, vy);
-    const int dx = vx - first.x, dy = vy - first.y;
-    twice += (uint32_t)__mul24(dx, w.y - first.y) - (uint32_t)__mul24(w.x - first.x, dy);
+    do {
+      const int2 w = rs.succ();
+      const bool ok = rs.valid();
+      const int vx = ok ? rs.cur.x : first.x, vy = ok ? rs.cur.y : first.y;
+      x0 = min(x0, vx);
+      y0 = min(y0, vy);
+      x1 = max(x1, vx);
+      y1 = max(y1, vy);
+      const int dx = vx - first.x, dy = vy - first.y;
+      twice += (uint32_t)__mul24(dx, w.y - first.y) - (uint32_t)__mul24(w.x - first.x, dy);
+    } while (rs.next());
   }
   m.x0 = wave_min_i32(x0);
   m.y0 = wave_min_i32(y0);
@@ -262,13 +292,12 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
     area = (int64_t)(t < 0 ? -(int64_t)t : (int64_t)t) / 2;
   } else {
     uint64_t tw = 0;
+    RingStream rs(xy, o, nv, lane);
 #pragma unroll 1
-    for (int base = 0; base < nv; base += kWave) {
-      const int k = base + lane;
-      int2 v, w;
-      load_edge(xy, o, nv, k, v, w);
-      if (k < nv) tw += (uint64_t)((int64_t)v.x * w.y) - (uint64_t)((int64_t)w.x * v.y);
-    }
+    do {
+      const int2 w = rs.succ();
+      if (rs.valid()) tw += (uint64_t)((int64_t)rs.cur.x * w.y) - (uint64_t)((int64_t)w.x * rs.cur.y);
+    } while (rs.next());
     const int64_t t64 = (int64_t)wave_sum_u64(tw);
     area = (t64 < 0 ? -t64 : t64) / 2;
   }
@@ -362,29 +391,12 @@ __device__ __forceinline__ void scatter_ring(Ctx& c, const int2* xy, int64_t o, 
                                              int tx0, int ty0, int th, int W, M* slots, int base,
                                              uint64_t* full = nullptr) {
   const int lane = c.lane;
+  const int n = uniform((int)nv);
   uint32_t kept = 0;
-#pragma unroll 1
-  for (int b0 = 0; b0 < (int)nv; b0 += kWave) {
-    int2 v, w;
-    if (r && b0 == 0) {
-      v = r->v0;
-      w = r->w0;
-    } else if (r && b0 == kWave) {
-      v = r->v1;
-      w = r->w1;
-    } else {
-      // one coalesced load per chunk; successors from the next lane, lane
-      // 63's from the next chunk, the last vertex's is the first (single-lane
-      // loads)
-      const int k = b0 + lane;
-      v = k < (int)nv ? xy[o + k] : make_int2(0, 0);
-      w = next_lane(v);
-      if (lane == kWave - 1 && k + 1 < (int)nv) w = xy[o + k + 1];
-      if (k + 1 == (int)nv) w = xy[o];
-    }
+  auto one = [&](int2 v, int2 w, bool ok) {
     int slot = 0;
     uint64_t rr = 0;
-    const bool keep = (b0 + lane < (int)nv) && leaf_edge(v, w, tx0, ty0, th, W, slot, rr);
+    const bool keep = ok && leaf_edge(v, w, tx0, ty0, th, W, slot, rr);
     if (keep) {
       if (full && slot == 0)
         *full ^= rr;
@@ -392,6 +404,23 @@ __device__ __forceinline__ void scatter_ring(Ctx& c, const int2* xy, int64_t o, 
         slot_xor(slots, base + slot, rr);
     }
     if (c.a->stats_on) kept += (uint32_t)__popcll(ballot(keep));
+  };
+  int b0 = 0;
+  int2 first;
+  if (r) {
+    // the first two chunks are in registers
+    one(r->v0, r->w0, lane < n);
+    if (n > kWave) one(r->v1, r->w1, kWave + lane < n);
+    b0 = 2 * kWave;
+    first = lane_value(r->v0, 0);
+  }
+  if (b0 < n) {
+    RingStream rs(xy, o, n, lane, b0, r ? &first : nullptr);
+#pragma unroll 1
+    do {
+      const int2 w = rs.succ();
+      one(rs.cur, w, rs.valid());
+    } while (rs.next());
   }
   if (c.a->stats_on) {
     stat_add(c, 8, (unsigned long long)kept);
@@ -507,16 +536,14 @@ __device__ __forceinline__ int stage_band(Ctx& c, const int2* xy, int64_t o, int
                                           uint32_t* list) {
   const int lane = c.lane;
   int cnt = 0;
+  if (uniform((int)nv) <= 0) return 0;
+  RingStream rs(xy, o, uniform((int)nv), lane);
 #pragma unroll 1
-  for (int b0 = 0; b0 < (int)nv; b0 += kWave) {
-    const int k = b0 + lane;
-    int2 v = k < (int)nv ? xy[o + k] : make_int2(0, 0);
-    int2 w = next_lane(v);
-    if (lane == kWave - 1 && k + 1 < (int)nv) w = xy[o + k + 1];
-    if (k + 1 == (int)nv) w = xy[o];
+  do {
+    const int2 v = rs.cur, w = rs.succ();
     bool keep = false;
     uint32_t rec = 0;
-    if (k < (int)nv && v.x == w.x) {
+    if (rs.valid() && v.x == w.x) {
       const int lo = max(min(v.y, w.y) - ty0, 0);
       const int hi = min(max(v.y, w.y) - ty0, th);
       const int dx = v.x - xs;
@@ -530,7 +557,7 @@ __device__ __forceinline__ int stage_band(Ctx& c, const int2* xy, int64_t o, int
     if (cnt + nk > kBandCap) return -1;
     if (keep) list[cnt + lanes_below(b)] = rec;
     cnt += nk;
-  }
+  } while (rs.next());
   stat_add(c, 10, (unsigned long long)nv);
   return cnt;
 }
@@ -629,12 +656,18 @@ __device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int6
                          int gx, int gy, uint64_t& H, uint64_t& P) {
   const int S = 1 << ls;
   uint64_t h = 0, p = 0;
-  for (int base = 0; base < (int)nv; base += kWave) {
-    const int k = base + c.lane;
-    if (k >= nv) break;
-    const int2 v = xy[o + k];
-    const int2 w = xy[o + (k + 1 == nv ? 0 : k + 1)];
-    if (v.x == w.x) {
+  if (uniform((int)nv) <= 0) {
+    H = 0;
+    P = 0;
+    return;
+  }
+  RingStream rs(xy, o, uniform((int)nv), c.lane);
+#pragma unroll 1
+  do {
+    const int2 v = rs.cur, w = rs.succ();
+    if (!rs.valid()) {
+      // past the end of the ring
+    } else if (v.x == w.x) {
       const int X = v.x, lo = min(v.y, w.y), hi = max(v.y, w.y);
       const int dx = X - bx0;
       if (dx > 0 && hi > by0) {
@@ -661,7 +694,7 @@ __device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int6
         if (i0 <= i1) h |= rows_bits(j, j) & spread(cols_bits(i0, i1));
       }
     }
-  }
+  } while (rs.next());
   H = wave_or64(h);
   P = wave_xor64(p);
   stat_add(c, 9, (unsigned long long)nv);
