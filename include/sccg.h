@@ -114,6 +114,9 @@ typedef struct {
   int32_t n_queues;       /* BATCHED: device queues, 1..8 (default 8, one per XCD)                   */
   int32_t heavy_verts;    /* BATCHED: pairs with at least this many vertices (both rings) are claimed
                              first and may share their boxes through the queue (default 512)        */
+  int32_t min_classify_cells; /* BATCHED: a split into 64-pixel leaf tiles classifies its tiles (Lemma
+                             1) only when it has at least this many, 1..65; a smaller split pixelizes
+                             every tile of a polygon not known to contain it (default 26)           */
 } sccg_params;
 
 /* Create a context on HIP device `hip_device` using stream `hip_stream`

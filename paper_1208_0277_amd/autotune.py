@@ -24,6 +24,7 @@ BATCHED_SPACE = [
     ("queue_chunk", [16, 8, 32, 64]),
     ("waves_per_wg", [4, 2, 8]),
     ("heavy_verts", [512, 1024, 2048]),
+    ("min_classify_cells", [26, 1, 10, 65]),
 ]
 
 #: plain-mode candidates: the pixelization threshold T (Section 3.4 puts the

@@ -823,6 +823,12 @@ __device__ __forceinline__ void split_box(Ctx& c, const PairInfo& pi, int bx0, i
   uint64_t Hp = 0, Pp = valid, Hq = 0, Pq = valid;
   if (a.flags & SCCG_F_PIXEL_ONLY) {
     Hp = Hq = valid;  // PixelOnly: no sampling boxes, every cell is pixelized
+  } else if (cl == 0 && gx * gy < a.min_classify_cells) {
+    // a split into a few leaf tiles: classifying them costs two ring passes
+    // and rarely decides a tile, so every tile is pixelized (a polygon known
+    // to contain the box still counts as inside)
+    if (!kp) Hp = valid;
+    if (!kq) Hq = valid;
   } else {
     if (!kp) classify(c, a.A.xy, pi.op, pi.np, bx0, by0, bx1, by1, ls, gx, gy, Hp, Pp);
     if (!kq) classify(c, a.B.xy, pi.oq, pi.nq, bx0, by0, bx1, by1, ls, gx, gy, Hq, Pq);

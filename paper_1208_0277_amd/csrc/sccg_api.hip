@@ -122,6 +122,9 @@ int resolve_params(sccg_ctx* c, const sccg_params* in, sccg_params* out) {
   if (p.n_queues < 1 || p.n_queues > kMaxGrid) return fail(c, SCCG_E_ARG, "n_queues outside [1, 8]");
   if (p.heavy_verts == 0) p.heavy_verts = 512;
   if (p.heavy_verts < 1) return fail(c, SCCG_E_ARG, "heavy_verts < 1");
+  if (p.min_classify_cells == 0) p.min_classify_cells = 26;
+  if (p.min_classify_cells < 1 || p.min_classify_cells > 65)
+    return fail(c, SCCG_E_ARG, "min_classify_cells outside [1, 65]");
   *out = p;
   return SCCG_OK;
 }
@@ -460,6 +463,7 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   ba.chunk = c->p.queue_chunk;
   ba.heavy_verts = c->p.heavy_verts;
   ba.min_cells_to_queue = c->p.min_queue_cells;
+  ba.min_classify_cells = c->p.min_classify_cells;
   ba.flags = c->p.flags;
   ba.stats_on = c->stats_on;
   int grid = c->p.grid;
@@ -468,11 +472,11 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   if (!use_graph) return launch_batched(c, ba, grid);
   // the graph is keyed on every launch argument
   char key[512];
-  snprintf(key, sizeof(key), "%lld/%p/%p|%lld/%p/%p|%lld/%p/%p/%p/%p|%d/%d/%d/%d/%d/%u/%d/%d",
+  snprintf(key, sizeof(key), "%lld/%p/%p|%lld/%p/%p|%lld/%p/%p/%p/%p|%d/%d/%d/%d/%d/%d/%u/%d/%d",
            (long long)A->n_polys, (const void*)A->offsets, (const void*)A->xy,
            (long long)B->n_polys, (const void*)B->offsets, (const void*)B->xy, (long long)n_pairs,
            (const void*)pair_a, (const void*)pair_b, (void*)out_inter, (void*)out_union, ba.queue_cap, ba.n_queues,
-           ba.chunk, ba.heavy_verts, ba.min_cells_to_queue, ba.flags, ba.stats_on, grid);
+           ba.chunk, ba.heavy_verts, ba.min_cells_to_queue, ba.min_classify_cells, ba.flags, ba.stats_on, grid);
   if (!c->gexec || c->gkey != key) {
     drop_graph(c);
     hipGraph_t g = nullptr;

@@ -110,6 +110,7 @@ struct BatchArgs {
   int32_t chunk;                 // small pairs per claim
   int32_t heavy_verts;           // pairs with at least this many vertices are claimed first
   int32_t min_cells_to_queue;    // a split pushes its boxes to the queue only from this many boxes
+  int32_t min_classify_cells;    // a leaf-level split classifies its tiles only from this many cells
   uint32_t flags;                // SCCG_F_*
   int32_t stats_on;
 };

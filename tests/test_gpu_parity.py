@@ -151,6 +151,7 @@ BATCH_TUNINGS = [
     dict(flags=sccg.SCCG_F_NO_LPT), dict(flags=sccg.SCCG_F_NO_GRAPH), dict(queue_chunk=1), dict(queue_chunk=64), dict(queue_chunk=37),
     dict(waves_per_wg=1), dict(waves_per_wg=8), dict(n_queues=1), dict(grid=3), dict(heavy_verts=1),
     dict(heavy_verts=1, min_queue_cells=1, queue_cap=50), dict(heavy_verts=100000),
+    dict(min_classify_cells=1), dict(min_classify_cells=65), dict(min_classify_cells=65, heavy_verts=1, min_queue_cells=1),
     dict(flags=sccg.SCCG_F_NO_SEP), dict(flags=sccg.SCCG_F_PIXEL_ONLY),
     dict(flags=sccg.SCCG_F_NO_SEP, heavy_verts=1, min_queue_cells=1),
     dict(flags=sccg.SCCG_F_PIXEL_ONLY | sccg.SCCG_F_NO_KNOWN_INSIDE, heavy_verts=1, min_queue_cells=1),
