@@ -173,11 +173,12 @@ __device__ __forceinline__ int2 lane_value(int2 v, int l) {
   return make_int2(__builtin_amdgcn_readlane(v.x, l), __builtin_amdgcn_readlane(v.y, l));
 }
 
-// A ring read 64 vertices at a time with one chunk in flight ahead: lane L
-// holds vertex base + L in `cur` and vertex base + 64 + L in `nxt`, whose
-// load was issued one chunk earlier.  A vertex's successor is the next
-// lane's vertex; lane 63's is lane 0 of `nxt`, and the last vertex's is the
-// first.  `nv` (>= 1) must be wave-uniform.  Lanes past the end load the
+// A ring read 64 vertices at a time with loads running ahead: lane L holds
+// vertex base + L in `cur` and vertex base + 64 + L in `nxt`; ahead(), called
+// at the top of each iteration, starts the load of the chunk after `nxt`, so
+// that it arrives while the current chunk is processed.  A vertex's
+// successor is the next lane's vertex; lane 63's is lane 0 of `nxt`, and the
+// last vertex's is the first.  `nv` (>= 1) must be wave-uniform.  Lanes past the end load the
 // last vertex again (the index is clamped, so the loads need no branch) and
 // must be masked with valid(): the successor shift reads across lanes, so
 // no lane may be switched off around it, and a per-lane branch in the loop
@@ -185,7 +186,7 @@ __device__ __forceinline__ int2 lane_value(int2 v, int l) {
 struct RingStream {
   const int2* p;
   int nv, base, lane;
-  int2 first, cur, nxt;
+  int2 first, cur, nxt, nn;
 
   __device__ __forceinline__ int2 at(int k) const { return p[min(k, nv - 1)]; }
   __device__ __forceinline__ RingStream(const int2* xy, int64_t o, int nv_, int lane_, int base0 = 0,
@@ -195,6 +196,7 @@ struct RingStream {
     nxt = at(base + kWave + lane);
     first = first_ ? *first_ : lane_value(cur, 0);
   }
+  __device__ __forceinline__ void ahead() { nn = at(base + 2 * kWave + lane); }
   __device__ __forceinline__ bool valid() const { return base + lane < nv; }
   // successor of this lane's vertex (every lane takes part)
   __device__ __forceinline__ int2 succ() const {
@@ -207,7 +209,7 @@ struct RingStream {
     base = uniform(base + kWave);
     if (base >= nv) return false;
     cur = nxt;
-    nxt = at(base + kWave + lane);
+    nxt = nn;
     return true;
   }
 };
@@ -272,6 +274,7 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
     RingStream rs(xy, o, nv, lane, 2 * kWave, &first);
 #pragma unroll 1
     do {
+      rs.ahead();
       const int2 w = rs.succ();
       const bool ok = rs.valid();
       const int vx = ok ? rs.cur.x : first.x, vy = ok ? rs.cur.y : first.y;
@@ -295,6 +298,7 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
     RingStream rs(xy, o, nv, lane);
 #pragma unroll 1
     do {
+      rs.ahead();
       const int2 w = rs.succ();
       if (rs.valid()) tw += (uint64_t)((int64_t)rs.cur.x * w.y) - (uint64_t)((int64_t)w.x * rs.cur.y);
     } while (rs.next());
@@ -418,6 +422,7 @@ __device__ __forceinline__ void scatter_ring(Ctx& c, const int2* xy, int64_t o, 
     RingStream rs(xy, o, n, lane, b0, r ? &first : nullptr);
 #pragma unroll 1
     do {
+      rs.ahead();
       const int2 w = rs.succ();
       one(rs.cur, w, rs.valid());
     } while (rs.next());
@@ -540,6 +545,7 @@ __device__ __forceinline__ int stage_band(Ctx& c, const int2* xy, int64_t o, int
   RingStream rs(xy, o, uniform((int)nv), lane);
 #pragma unroll 1
   do {
+    rs.ahead();
     const int2 v = rs.cur, w = rs.succ();
     bool keep = false;
     uint32_t rec = 0;
@@ -664,6 +670,7 @@ __device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int6
   RingStream rs(xy, o, uniform((int)nv), c.lane);
 #pragma unroll 1
   do {
+    rs.ahead();
     const int2 v = rs.cur, w = rs.succ();
     if (!rs.valid()) {
       // past the end of the ring
