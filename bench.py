@@ -56,6 +56,8 @@ WORKLOADS = {
 #                         cell masks (12), first-pixel parity range and masks (12)
 #   ring_scan_vertices:   one vertex of a pair's rings: extent (4 min/max),
 #                         shoelace term (2 multiplies and a subtract in 64 bits: 6)
+#   union_tile_vertices:  one vertex of a pair counted on one leaf tile: union
+#                         extent only (4 min/max)
 #   leaf_boxes:           one leaf tile: per ring a 64-bit prefix XOR over the
 #                         64 column lanes (6 steps x 2 words), then the AND and
 #                         popcount of both masks -> (2 x 12 + 2) x 64
@@ -64,6 +66,7 @@ ALGO_OPS = {
     "leaf_staging_edges": 12,
     "classify_edge_visits": 24,
     "ring_scan_vertices": 10,
+    "union_tile_vertices": 4,
     "leaf_boxes": 26 * 64,
 }
 # int32 VALU peak of MI355X: 256 CUs x 4 SIMD16 = 64 lanes per CU per clock at 2.4 GHz
@@ -281,12 +284,14 @@ def fig8_bench(args):
     base = sccg_gen.pairs(2, 15724, seed=sccg_gen.BASE_SEED + 6)
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(dev)
-    # PixelBox and NoSep classify every split (min_classify_cells 1), as the
-    # paper's design does; "PixelBox, tuned" lets the autotuner skip the
-    # classification of leaf-level splits of a few tiles
+    # PixelBox and NoSep classify every split (min_classify_cells 1) and
+    # PixelBox derives every union from the areas, as the paper's design
+    # does; "PixelBox, tuned" lets the autotuner skip the classification of
+    # leaf-level splits of a few tiles and counts pairs that fit one leaf
+    # tile directly there
     variants = [("PixelOnly", sccg.SCCG_BATCHED, {"flags": sccg.SCCG_F_PIXEL_ONLY}),
                 ("PixelBox-NoSep", sccg.SCCG_BATCHED, {"flags": sccg.SCCG_F_NO_SEP, "min_classify_cells": 1}),
-                ("PixelBox", sccg.SCCG_BATCHED, {"min_classify_cells": 1}),
+                ("PixelBox", sccg.SCCG_BATCHED, {"min_classify_cells": 1, "flags": sccg.SCCG_F_NO_UNION_TILE}),
                 ("PixelBox, tuned", sccg.SCCG_BATCHED, {}),
                 ("Algorithm 1 (plain)", sccg.SCCG_PLAIN, {})]
     rows, exact, ref1 = [], True, None

@@ -81,6 +81,12 @@ extern "C" {
  * Counts are identical to the default; only the work differs. */
 #define SCCG_F_PIXEL_ONLY 0x10u
 #define SCCG_F_NO_SEP 0x20u
+/* batched: by default a pair (not shared through the queue, rings of at most
+ * 128 vertices) whose MBR(p) ∪ MBR(q) fits one 64 x 64 leaf tile is counted
+ * directly on that tile: the intersection and the union are popcounts of the
+ * AND and the OR of the two row masks, so the ring areas are not needed.
+ * This flag turns that off (every pair derives U from the areas). */
+#define SCCG_F_NO_UNION_TILE 0x40u
 
 /* sccg_jaccard_sets flags */
 #define SCCG_J_NONZERO_ONLY 0u /* default: only pairs with I > 0 contribute (Equation 1's filter) */
@@ -237,6 +243,7 @@ int sccg_sync(sccg_ctx* ctx);
  *   [10] ring edges read while staging leaf tiles (BATCHED)
  *   [11] covered pixels: sum of the non-empty pair-box areas (BATCHED)
  *   [12] vertices reduced for MBRs and areas inside the persistent kernel (BATCHED)
+ *   [13] vertices reduced for union boxes only, of pairs counted on one leaf tile (BATCHED)
  * Writes min(n, 16) values to out; returns that count (or an error < 0). */
 int sccg_set_stats(sccg_ctx* ctx, int enable);
 int sccg_get_stats(sccg_ctx* ctx, int64_t* out, int n);

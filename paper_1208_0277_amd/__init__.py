@@ -35,6 +35,7 @@ SCCG_F_NO_SPLIT_QUEUE = 0x4
 SCCG_F_NO_GRAPH = 0x8
 SCCG_F_PIXEL_ONLY = 0x10
 SCCG_F_NO_SEP = 0x20
+SCCG_F_NO_UNION_TILE = 0x40
 
 SCCG_REL_INTERSECTS = 0x1
 SCCG_REL_CONTAINS = 0x2
@@ -58,7 +59,7 @@ SERVER_STAT_KEYS = ("jobs_submitted", "jobs_done", "launches", "pairs_done", "pe
 
 STAT_KEYS = ("leaf_pixel_tests", "leaf_boxes", "split_boxes", "queued_boxes", "kept_boxes", "small_pairs",
              "large_pairs", "empty_pairs", "leaf_edge_updates", "classify_edge_visits", "leaf_staging_edges",
-             "covered_pixels", "ring_scan_vertices")
+             "covered_pixels", "ring_scan_vertices", "union_tile_vertices")
 
 
 class SccgError(RuntimeError):

@@ -163,6 +163,13 @@ struct RingRegs {
   int2 v0, w0, v1, w1;
 };
 
+// The first two chunks of a ring when they are already in registers
+// (vertex lane in v0, vertex lane + 64 in v1, (0, 0) past the end).
+struct Held {
+  bool have;
+  int2 v0, v1;
+};
+
 // The value of the next lane (DPP wave shift left by one; lane 63 reads 0).
 __device__ __forceinline__ int2 next_lane(int2 v) {
   return make_int2(__builtin_amdgcn_update_dpp(0, v.x, 0x130, 0xf, 0xf, false),
@@ -218,11 +225,10 @@ struct RingStream {
 // each vertex's successor comes from the neighbouring lane, lane 63's from
 // the next chunk, and the last vertex's is vertex 0.
 __device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int nv, int lane, RingRegs& r,
-                                           int2& first, const int2* pre) {
-  // pre: the prefetched first two chunks (pre[0] = vertex lane, pre[1] = vertex lane + 64)
+                                           int2& first, const Held& pre) {
   const int k0 = lane, k1 = lane + kWave;
-  r.v0 = pre ? pre[0] : (k0 < nv ? xy[o + k0] : make_int2(0, 0));
-  r.v1 = pre ? pre[1] : (k1 < nv ? xy[o + k1] : make_int2(0, 0));
+  r.v0 = pre.have ? pre.v0 : (k0 < nv ? xy[o + k0] : make_int2(0, 0));
+  r.v1 = pre.have ? pre.v1 : (k1 < nv ? xy[o + k1] : make_int2(0, 0));
   first = lane_value(r.v0, 0);
   const int2 a64 = nv > kWave ? lane_value(r.v1, 0) : first;
   const int2 a128 = nv > 2 * kWave ? xy[o + 2 * kWave] : first;
@@ -246,7 +252,7 @@ __device__ __forceinline__ void load_ring2(const int2* xy, int64_t o, int nv, in
 // again in 64 bits.  Empty rings and rings with |coordinate| > 2^30 come back
 // empty.
 __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t nv64, int lane, RingRegs& r, Meta& m,
-                                            int64_t& area, const int2* pre = nullptr) {
+                                            int64_t& area, const Held& pre = Held{false, {0, 0}, {0, 0}}) {
   const int nv = uniform((int)nv64);
   int2 first;
   load_ring2(xy, o, nv, lane, r, first, pre);
@@ -314,6 +320,26 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
 __device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv, int lane, Meta& m, int64_t& area) {
   RingRegs r;
   ring_extent(xy, o, nv, lane, r, m, area);
+}
+
+// Union box of two rings of at most 128 vertices each, both non-empty, from
+// their first two chunks (loaded here into rp and rq, which the leaf reuses):
+// four wave reductions over both rings at once.  Lanes past the end of a ring
+// stand at p's first vertex.
+__device__ __forceinline__ Meta union_extent(const int2* xa, int64_t oa, int np, const int2* xb, int64_t ob, int nq,
+                                             int lane, RingRegs& rp, RingRegs& rq, const Held& pre_p,
+                                             const Held& pre_q) {
+  int2 fp, fq;
+  load_ring2(xa, oa, np, lane, rp, fp, pre_p);
+  load_ring2(xb, ob, nq, lane, rq, fq, pre_q);
+  const int2 p0 = lane < np ? rp.v0 : fp, p1 = lane + kWave < np ? rp.v1 : fp;
+  const int2 q0 = lane < nq ? rq.v0 : fp, q1 = lane + kWave < nq ? rq.v1 : fp;
+  Meta u;
+  u.x0 = wave_min_i32(min(min(p0.x, p1.x), min(q0.x, q1.x)));
+  u.y0 = wave_min_i32(min(min(p0.y, p1.y), min(q0.y, q1.y)));
+  u.x1 = wave_max_i32(max(max(p0.x, p1.x), max(q0.x, q1.x)));
+  u.y1 = wave_max_i32(max(max(p0.y, p1.y), max(q0.y, q1.y)));
+  return u;
 }
 
 __device__ __forceinline__ bool coords_bad(const Meta& m, int64_t nv) {
@@ -450,13 +476,12 @@ __device__ __forceinline__ M fresh_zero() {
 // scan; short boxes (h <= 32) use 32-bit row masks.
 template <bool kRows64>
 __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const RingRegs& rp, const RingRegs& rq,
-                                              int tw, int th) {
+                                              int tw, int th, bool direct) {
   using M = typename std::conditional<kRows64, uint64_t, uint32_t>::type;
   const BatchArgs& a = *c.a;
   const int lane = c.lane;
   const int tx0 = pi.box.x0, ty0 = pi.box.y0;
   M* slots = reinterpret_cast<M*>(c.slots);
-  const bool direct = direct_union(a);
   uint32_t n = 0, nu = 0;
   if (tw <= 32) {
     slots[lane] = fresh_zero<M>();
@@ -1097,13 +1122,41 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
 
     // ------------------------------------------------------ small-pair path
     int64_t I = 0;
+    bool union_tile = false;  // I holds direct counts: intersection low, union high
+    bool in_regs = false;     // rp, rq hold the first two chunks of both rings
+    RingRegs rp, rq;
     if (task == 0) {
-      // MBRs and areas from the pair's own rings, then the pair box
+      const int np = uniform((int)pi.np), nq = uniform((int)pi.nq);
+      const bool try_union = !shared && !direct_union(a) && !(a.flags & SCCG_F_NO_UNION_TILE) && np > 0 &&
+                             nq > 0 && np <= 2 * kWave && nq <= 2 * kWave;
+      if (try_union) {
+        // both polygons inside one leaf tile: count I and U there directly
+        const Meta u = union_extent(a.A.xy, pi.op, np, a.B.xy, pi.oq, nq, c.lane, rp, rq,
+                                    Held{use_pf, cur_vp[0], cur_vp[1]}, Held{use_pf, cur_vq[0], cur_vq[1]});
+        in_regs = true;
+        if (u.x0 >= -kMaxCoord && u.y0 >= -kMaxCoord && u.x1 <= kMaxCoord && u.y1 <= kMaxCoord &&
+            u.x1 - u.x0 <= kTile && u.y1 - u.y0 <= kTile && u.x0 < u.x1 && u.y0 < u.y1) {
+          const int uw = u.x1 - u.x0, uh = u.y1 - u.y0;
+          pi.box = u;
+          I = uh > 32 ? leaf_small<true>(c, pi, rp, rq, uw, uh, true) : leaf_small<false>(c, pi, rp, rq, uw, uh, true);
+          union_tile = true;
+          if (a.stats_on && c.lane == 0) {
+            atomicAdd(&a.st->stats[5], 1ull);
+            atomicAdd(&a.st->stats[11], (unsigned long long)uw * uh);
+            atomicAdd(&a.st->stats[13], (unsigned long long)(np + nq));
+          }
+        }
+      }
+    }
+    if (task == 0 && !union_tile) {
+      // MBRs and areas from the pair's own rings, then the pair box (the
+      // first 128 vertices of each ring may already be in registers)
       Meta mp, mq;
       int64_t ap, aq;
-      RingRegs rp, rq;
-      ring_extent(a.A.xy, pi.op, pi.np, c.lane, rp, mp, ap, use_pf ? cur_vp : nullptr);
-      ring_extent(a.B.xy, pi.oq, pi.nq, c.lane, rq, mq, aq, use_pf ? cur_vq : nullptr);
+      const Held hp{in_regs || use_pf, in_regs ? rp.v0 : cur_vp[0], in_regs ? rp.v1 : cur_vp[1]};
+      const Held hq{in_regs || use_pf, in_regs ? rq.v0 : cur_vq[0], in_regs ? rq.v1 : cur_vq[1]};
+      ring_extent(a.A.xy, pi.op, pi.np, c.lane, rp, mp, ap, hp);
+      ring_extent(a.B.xy, pi.oq, pi.nq, c.lane, rq, mq, aq, hq);
       if (c.lane == 0 && (coords_bad(mp, pi.np) || coords_bad(mq, pi.nq))) latch_error(a.err, kErrCoord);
       if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[12], (unsigned long long)(pi.np + pi.nq));
       pi.area_sum = ap + aq;
@@ -1117,7 +1170,8 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
         if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
         pi.area_sum = 0;
       } else if (bw <= kTile && bh <= kTile) {
-        I = bh > 32 ? leaf_small<true>(c, pi, rp, rq, bw, bh) : leaf_small<false>(c, pi, rp, rq, bw, bh);
+        I = bh > 32 ? leaf_small<true>(c, pi, rp, rq, bw, bh, direct_union(a))
+                    : leaf_small<false>(c, pi, rp, rq, bw, bh, direct_union(a));
         if (a.stats_on && c.lane == 0) {
           atomicAdd(&a.st->stats[5], 1ull);
           atomicAdd(&a.st->stats[11], (unsigned long long)bw * bh);
@@ -1142,7 +1196,7 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
     if (c.lane == 0) {
       if (shared) {
         add_counts(a, pi.pair, (uint64_t)I);
-      } else if (direct_union(a)) {
+      } else if (direct_union(a) || union_tile) {
         a.inter[pi.pair] = I & 0xffffffffll;
         a.uni[pi.pair] = (I >> 32) & 0xffffffffll;
       } else {

@@ -109,7 +109,7 @@ int resolve_params(sccg_ctx* c, const sccg_params* in, sccg_params* out) {
   if (p.lds_vertex_cap < 1 || p.lds_vertex_cap > 4096)
     return fail(c, SCCG_E_ARG, "lds_vertex_cap outside [1, 4096]");
   const uint32_t known = SCCG_F_NO_LPT | SCCG_F_NO_KNOWN_INSIDE | SCCG_F_NO_SPLIT_QUEUE | SCCG_F_NO_GRAPH |
-                         SCCG_F_PIXEL_ONLY | SCCG_F_NO_SEP;
+                         SCCG_F_PIXEL_ONLY | SCCG_F_NO_SEP | SCCG_F_NO_UNION_TILE;
   if (p.flags & ~known) return fail(c, SCCG_E_ARG, "unknown flag bits 0x%x", p.flags & ~known);
   if (p.grid < 0 || p.grid > (1 << 20)) return fail(c, SCCG_E_ARG, "grid outside [0, 2^20]");
   if (p.queue_cap == 0) p.queue_cap = 1 << 20;

@@ -151,7 +151,7 @@ BATCH_TUNINGS = [
     dict(flags=sccg.SCCG_F_NO_LPT), dict(flags=sccg.SCCG_F_NO_GRAPH), dict(queue_chunk=1), dict(queue_chunk=64), dict(queue_chunk=37),
     dict(waves_per_wg=1), dict(waves_per_wg=8), dict(n_queues=1), dict(grid=3), dict(heavy_verts=1),
     dict(heavy_verts=1, min_queue_cells=1, queue_cap=50), dict(heavy_verts=100000),
-    dict(min_classify_cells=1), dict(min_classify_cells=65), dict(min_classify_cells=65, heavy_verts=1, min_queue_cells=1),
+    dict(min_classify_cells=1), dict(min_classify_cells=65), dict(flags=sccg.SCCG_F_NO_UNION_TILE), dict(min_classify_cells=65, heavy_verts=1, min_queue_cells=1),
     dict(flags=sccg.SCCG_F_NO_SEP), dict(flags=sccg.SCCG_F_PIXEL_ONLY),
     dict(flags=sccg.SCCG_F_NO_SEP, heavy_verts=1, min_queue_cells=1),
     dict(flags=sccg.SCCG_F_PIXEL_ONLY | sccg.SCCG_F_NO_KNOWN_INSIDE, heavy_verts=1, min_queue_cells=1),
@@ -352,7 +352,7 @@ def test_jaccard_sets(ctx, wl3s, include_zero):
 
 def test_batched_stats(wl3s):
     wl, _, _ = wl3s
-    c = sccg.Context(0)
+    c = sccg.Context(0, min_classify_cells=1)
     c.set_stats(True)
     run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
     s = c.get_stats()
@@ -361,6 +361,7 @@ def test_batched_stats(wl3s):
     assert s["leaf_pixel_tests"] > 0 and s["leaf_boxes"] >= s["small_pairs"]
     assert s["large_pairs"] > 0 and s["split_boxes"] >= s["large_pairs"]
     assert s["leaf_edge_updates"] > 0 and s["classify_edge_visits"] > 0
+    assert s["union_tile_vertices"] > 0 and s["ring_scan_vertices"] > 0
 
 
 def test_kernel_timing(wl3s):
