@@ -55,11 +55,7 @@ constexpr int kLocalCap = 256;          // per-wave stack of boxes to process in
 constexpr uint32_t kSpinLimit = 1u << 22;
 // per-wave LDS: leaf slots, band-edge lists, the inline box stack, the
 // metadata of one chunk
-struct ChunkMeta {
-  int64_t op, oq;
-  int32_t np, nq;
-  int32_t cls, pad;
-};
+using ChunkMeta = PairRec;
 constexpr int kLdsPerWave = kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta);
 constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
 
@@ -358,8 +354,11 @@ __device__ __forceinline__ bool direct_union(const BatchArgs& a) {
 // Wave total of a lane's intersection count n and, when `direct`, of its
 // union count nu, packed.
 __device__ __forceinline__ uint64_t pack_counts(uint32_t n, uint32_t nu, bool direct) {
-  const uint64_t i = wave_sum_u32(n);
-  return direct ? i | ((uint64_t)wave_sum_u32(nu) << 32) : i;
+  if (!direct) return wave_sum_u32(n);
+  // a lane holds at most 64 pixels of each, so both wave sums stay below
+  // 2^13 and travel in the two halves of one 32-bit sum
+  const uint32_t t = wave_sum_u32(n | (nu << 16));
+  return (uint64_t)(t & 0xffffu) | ((uint64_t)(t >> 16) << 32);
 }
 
 // ------------------------------------------------------------------ leaves
@@ -1061,20 +1060,9 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
           ch_i0 = (int64_t)g * a.chunk;
           ch_cnt = (int)min((int64_t)a.chunk, a.n_pairs - ch_i0);
           ch_j = 0;
-          // one lane per pair of the chunk fetches its class, indices and ring offsets
+          // one lane per pair of the chunk copies its setup record
           wave_sync_lds();
-          if (c.lane < ch_cnt) {
-            const int64_t i = ch_i0 + c.lane;
-            ChunkMeta m{0, 0, 0, 0, a.cls[i], 0};
-            if (m.cls == kClsSweep) {
-              const int64_t ia = a.pa[i], ib = a.pb[i];
-              m.op = a.A.off[ia];
-              m.np = (int32_t)(a.A.off[ia + 1] - m.op);
-              m.oq = a.B.off[ib];
-              m.nq = (int32_t)(a.B.off[ib + 1] - m.oq);
-            }
-            c.meta[c.lane] = m;
-          }
+          if (c.lane < ch_cnt) c.meta[c.lane] = a.rec[ch_i0 + c.lane];
           wave_sync_lds();
         }
         if (!got) break;
@@ -1233,19 +1221,25 @@ __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a) {
   if (i < a.n_pairs) {
     const int64_t ia = a.pa[i], ib = a.pb[i];
     uint8_t cls = kClsSweep;
+    PairRec r{0, 0, 0, 0, 0, 0};
     if (ia < 0 || ia >= a.A.n || ib < 0 || ib >= a.B.n) {
       latch_error(a.err, kErrIndex);
       a.inter[i] = 0;
       a.uni[i] = 0;
       cls = kClsDone;
-    } else if (!(a.flags & SCCG_F_NO_LPT)) {
-      const int64_t nv = (a.A.off[ia + 1] - a.A.off[ia]) + (a.B.off[ib + 1] - a.B.off[ib]);
-      if (nv >= a.heavy_verts) {
+    } else {
+      r.op = a.A.off[ia];
+      r.np = (int32_t)(a.A.off[ia + 1] - r.op);
+      r.oq = a.B.off[ib];
+      r.nq = (int32_t)(a.B.off[ib + 1] - r.oq);
+      if (!(a.flags & SCCG_F_NO_LPT) && (int64_t)r.np + r.nq >= a.heavy_verts) {
         heavy = true;
         cls = kClsHeavy;
       }
     }
+    r.cls = cls;
     a.cls[i] = cls;
+    a.rec[i] = r;
   }
   const uint64_t bh = ballot(heavy);
   unsigned long long base = 0;

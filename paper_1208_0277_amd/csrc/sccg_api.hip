@@ -30,6 +30,7 @@ struct sccg_ctx {
   uint32_t* err = nullptr;
   // per-pair scratch
   uint8_t* cls = nullptr;
+  PairRec* rec = nullptr;
   int32_t* l_list = nullptr;
   Meta* hbox = nullptr;
   int64_t cap_pairs = 0;
@@ -164,8 +165,8 @@ int ensure_pairs(sccg_ctx* c, int64_t n) {
   (void)hipStreamSynchronize(c->stream);
   int64_t want = n + n / 4 + 1024;
   int r;
-  if ((r = grow(c, &c->cls, want, "pair classes")) || (r = grow(c, &c->l_list, want, "heavy list")) ||
-      (r = grow(c, &c->hbox, want, "heavy boxes"))) {
+  if ((r = grow(c, &c->cls, want, "pair classes")) || (r = grow(c, &c->rec, want, "pair records")) ||
+      (r = grow(c, &c->l_list, want, "heavy list")) || (r = grow(c, &c->hbox, want, "heavy boxes"))) {
     c->cap_pairs = 0;
     return r;
   }
@@ -290,7 +291,8 @@ int sccg_destroy(sccg_ctx* c) {
   drop_graph(c);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   void* ptrs[] = {c->metaA,  c->areaA,  c->bigA,        c->metaB,  c->areaB,   c->bigB,    c->big_count,
-                  c->err,    c->cls,    c->l_list,      c->hbox,   c->st,      c->queue,   c->plain_stats,
+                  c->err,    c->cls,    c->rec,         c->l_list, c->hbox,    c->st,      c->queue,
+                  c->plain_stats,
                   c->j_bbox, c->j_grid, c->j_cells,     c->j_cell_base, c->j_sums, c->j_count, c->j_start,
                   c->j_list, c->j_bcount, c->j_bstart};
   for (void* p : ptrs)
@@ -454,6 +456,7 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   ba.uni = out_union;
   ba.err = c->err;
   ba.cls = c->cls;
+  ba.rec = c->rec;
   ba.l_list = c->l_list;
   ba.hbox = c->hbox;
   ba.st = c->st;

@@ -92,6 +92,15 @@ struct BatchState {
   unsigned long long stats[kNumStats];
 };
 
+// Per-pair record written by the batched setup pass: ring offsets and
+// vertex counts of both polygons and the pair's class, so that the sweep
+// fetches a chunk of pairs with one coalesced 32-byte load per pair.
+struct PairRec {
+  int64_t op, oq;
+  int32_t np, nq;
+  int32_t cls, pad;
+};
+
 struct BatchArgs {
   Polys A, B;
   int64_t n_pairs;
@@ -101,6 +110,7 @@ struct BatchArgs {
   int64_t* uni;
   uint32_t* err;
   uint8_t* cls;                  // [n_pairs]
+  PairRec* rec;                  // [n_pairs]
   int32_t* l_list;               // [n_pairs] heavy pairs
   Meta* hbox;                    // [n_pairs] pair box of heavy-list entry k
   BatchState* st;
