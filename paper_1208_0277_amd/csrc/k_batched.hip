@@ -56,7 +56,8 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 // per-wave LDS: leaf slots, band-edge lists, the inline box stack, the
 // metadata of one chunk
 using ChunkMeta = PairRec;
-constexpr int kLdsPerWave = kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta);
+constexpr int kLdsPerWave =
+    kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta) + kWave * 16;
 constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
 
 int batch_lds_bytes_per_wave() { return kLdsPerWave; }
@@ -105,6 +106,7 @@ struct Ctx {
   uint32_t* band;   // per-wave band-edge lists: p at [0, kBandCap), q at [kBandCap, 2 kBandCap)
   uint64_t* local;  // per-wave inline stack, kLocalCap entries
   ChunkMeta* meta;  // per-wave metadata of the pairs of one chunk
+  int64_t* res;     // per-wave (I, U) of the chunk's sweep pairs, written out when the chunk is done
   int lsp;          // inline stack depth (wave-uniform)
   int home;         // preferred queue
   int xcd;          // first claim stream (the workgroup's XCD under round-robin dispatch)
@@ -986,6 +988,8 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   c.band = reinterpret_cast<uint32_t*>(lds + kLeafSlots * 8);
   c.local = reinterpret_cast<uint64_t*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4);
   c.meta = reinterpret_cast<ChunkMeta*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8);
+  c.res = reinterpret_cast<int64_t*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8 +
+                                     kWave * sizeof(ChunkMeta));
   c.lsp = 0;
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
@@ -1043,6 +1047,17 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
     // then the sweep over the other pairs, a chunk at a time
     while (!have) {
       if (ch_j >= ch_cnt) {
+        // the chunk in hand is done: its sweep pairs' counts go out in one
+        // coalesced store per array
+        if (ch_cnt > 0) {
+          wave_sync_lds();
+          if (c.lane < ch_cnt && c.meta[c.lane].cls == kClsSweep) {
+            a.inter[ch_i0 + c.lane] = c.res[2 * c.lane];
+            a.uni[ch_i0 + c.lane] = c.res[2 * c.lane + 1];
+          }
+          ch_cnt = ch_j = 0;
+          wave_sync_lds();
+        }
         bool got = false;
         while (!got && s_empty != 0xffu) {
           int st = c.xcd;
@@ -1184,12 +1199,12 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
     if (c.lane == 0) {
       if (shared) {
         add_counts(a, pi.pair, (uint64_t)I);
-      } else if (direct_union(a) || union_tile) {
-        a.inter[pi.pair] = I & 0xffffffffll;
-        a.uni[pi.pair] = (I >> 32) & 0xffffffffll;
       } else {
-        a.inter[pi.pair] = I;
-        a.uni[pi.pair] = pi.area_sum - I;
+        // a sweep pair of the chunk in hand
+        const int j = (int)(pi.pair - ch_i0);
+        const bool packed = direct_union(a) || union_tile;
+        c.res[2 * j] = packed ? (I & 0xffffffffll) : I;
+        c.res[2 * j + 1] = packed ? ((I >> 32) & 0xffffffffll) : pi.area_sum - I;
       }
     }
   }
