@@ -43,6 +43,8 @@
 //     bounded anyway and latches SCCG_E_DEVICE if the bound is hit.
 #include <limits.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "sccg_device.h"
@@ -59,6 +61,7 @@ using ChunkMeta = PairRec;
 constexpr int kLdsPerWave =
     kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta) + kWave * 16;
 constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
+constexpr int kSetupPerThread = 16;         // most pairs per thread of the setup pass
 
 int batch_lds_bytes_per_wave() { return kLdsPerWave; }
 
@@ -1230,10 +1233,18 @@ __global__ void k_batch_clear_counters(BatchArgs a) {
 }
 
 // Per pair: index check; pairs with many vertices go to the heavy list.
-__global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool heavy = false;
-  if (i < a.n_pairs) {
+__global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a, int per) {
+  // a block takes per x 256 consecutive pairs (coalesced rows of 256) and
+  // reserves room for its heavy pairs in the heavy list with one atomic:
+  // one per wave contended on the list counter
+  __shared__ uint32_t scan[256];
+  __shared__ unsigned long long base_s;
+  const int tid = threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * 256 * per;
+  uint32_t hmask = 0;
+  for (int t = 0; t < per; ++t) {
+    const int64_t i = b0 + (int64_t)t * 256 + tid;
+    if (i >= a.n_pairs) break;
     const int64_t ia = a.pa[i], ib = a.pb[i];
     uint8_t cls = kClsSweep;
     PairRec r{0, 0, 0, 0, 0, 0};
@@ -1248,7 +1259,7 @@ __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a) {
       r.oq = a.B.off[ib];
       r.nq = (int32_t)(a.B.off[ib + 1] - r.oq);
       if (!(a.flags & SCCG_F_NO_LPT) && (int64_t)r.np + r.nq >= a.heavy_verts) {
-        heavy = true;
+        hmask |= 1u << t;
         cls = kClsHeavy;
       }
     }
@@ -1256,11 +1267,22 @@ __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a) {
     a.cls[i] = cls;
     a.rec[i] = r;
   }
-  const uint64_t bh = ballot(heavy);
-  unsigned long long base = 0;
-  if (lane_id() == 0 && bh) base = atomicAdd(&a.st->l_count.v, (unsigned long long)__popcll(bh));
-  base = (unsigned long long)__shfl((long long)base, 0, kWave);
-  if (heavy) a.l_list[base + lanes_below(bh)] = (int32_t)i;
+  // exclusive prefix of the per-thread heavy counts over the block
+  const uint32_t cnt = (uint32_t)__popc(hmask);
+  scan[tid] = cnt;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    const uint32_t v = tid >= d ? scan[tid - d] : 0u;
+    __syncthreads();
+    scan[tid] += v;
+    __syncthreads();
+  }
+  const uint32_t total = scan[255];
+  if (tid == 0) base_s = total ? atomicAdd(&a.st->l_count.v, (unsigned long long)total) : 0ull;
+  __syncthreads();
+  unsigned long long pos = base_s + (scan[tid] - cnt);
+  for (uint32_t m = hmask; m; m &= m - 1)
+    a.l_list[pos++] = (int32_t)(b0 + (int64_t)(__ffs((int)m) - 1) * 256 + tid);
 }
 
 // One wave per heavy pair: MBRs and areas of both rings, the pair box and the
@@ -1312,8 +1334,11 @@ hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s) {
 
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((a.n_pairs + 255) / 256);
-  hipLaunchKernelGGL(k_batch_setup, dim3(blocks), dim3(256), 0, s, a);
+  // enough blocks to fill the chip (about 1024), at most kSetupPerThread pairs per thread
+  const int per = (int)std::max<int64_t>(1, std::min<int64_t>(kSetupPerThread, a.n_pairs / (256 * 1024)));
+  const int64_t per_block = 256 * (int64_t)per;
+  const unsigned blocks = (unsigned)((a.n_pairs + per_block - 1) / per_block);
+  hipLaunchKernelGGL(k_batch_setup, dim3(blocks), dim3(256), 0, s, a, per);
   hipLaunchKernelGGL(k_batch_heavy_meta, dim3(2048), dim3(256), 0, s, a);
   return hipGetLastError();
 }
