@@ -116,6 +116,14 @@ struct Ctx {
 };
 
 // Work counters (only with sccg_set_stats): one atomic per event from lane 0.
+// The first stream at or after `from` (cyclically, kStreams of them) not in
+// the exhausted mask `empty` (wave-uniform; at least one must be left).
+__device__ __forceinline__ int next_stream(uint32_t empty, int from) {
+  const uint32_t avail = ~empty & ((1u << kStreams) - 1u);
+  const uint32_t rot = ((avail >> from) | (avail << (kStreams - from))) & ((1u << kStreams) - 1u);
+  return uniform((from + __ffs((int)rot) - 1) % kStreams);
+}
+
 __device__ __forceinline__ void stat_add(const Ctx& c, int k, unsigned long long v) {
   if (c.a->stats_on && c.lane == 0 && v) atomicAdd(&c.a->st->stats[k], v);
 }
@@ -1025,14 +1033,13 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
     }
     // heavy pairs first: a largest-first order over the pairs with most vertices
     while (!have && l_empty != 0xffu) {
-      int st = c.xcd;
-      while ((l_empty >> st) & 1u) st = (st + 1) % kStreams;
+      const int st = next_stream(l_empty, c.xcd);
       unsigned long long k = 0;
       if (c.lane == 0) k = atomicAdd(&a.st->l_next[st].v, 1ull);
       k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
       const unsigned long long e = k * kStreams + st;
       if (e >= n_heavy) {
-        l_empty |= 1u << st;
+        l_empty = uniform_u(l_empty | (1u << st));
         continue;
       }
       pi = heavy_info(a, (int64_t)e);
@@ -1063,20 +1070,19 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
         }
         bool got = false;
         while (!got && s_empty != 0xffu) {
-          int st = c.xcd;
-          while ((s_empty >> st) & 1u) st = (st + 1) % kStreams;
+          const int st = next_stream(s_empty, c.xcd);
           unsigned long long k = 0;
           if (c.lane == 0) k = atomicAdd(&a.st->s_next[st].v, 1ull);
           k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
           const unsigned long long g = k * kStreams + st;
           if (g >= n_chunks) {
-            s_empty |= 1u << st;
+            s_empty = uniform_u(s_empty | (1u << st));
             continue;
           }
           got = true;
           pf_j = -1;
-          ch_i0 = (int64_t)g * a.chunk;
-          ch_cnt = (int)min((int64_t)a.chunk, a.n_pairs - ch_i0);
+          ch_i0 = uniform64((int64_t)g * a.chunk);
+          ch_cnt = uniform((int)min((int64_t)a.chunk, a.n_pairs - ch_i0));
           ch_j = 0;
           // one lane per pair of the chunk copies its setup record
           wave_sync_lds();
@@ -1086,7 +1092,8 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
         if (!got) break;
       }
       const ChunkMeta m = c.meta[ch_j];
-      const int j = ch_j++;
+      const int j = ch_j;
+      ch_j = uniform(ch_j + 1);
       if (uniform(m.cls) != kClsSweep) continue;
       pi.pair = ch_i0 + j;
       pi.hidx = -1;
@@ -1097,7 +1104,7 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
       have = true;
       // the first 128 vertices of both rings of this pair may already be in
       // registers; start those of the next pair of the chunk
-      use_pf = pf_j == j;
+      use_pf = uniform(pf_j) == j;
       if (use_pf) {
         cur_vp[0] = pf_vp[0];
         cur_vp[1] = pf_vp[1];
