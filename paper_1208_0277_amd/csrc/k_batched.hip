@@ -11,13 +11,19 @@
 //   - A pair box that fits one 64x64 leaf tile (the small pairs, most of any
 //     pathology workload) is pixelized at once: it is below the pixelization
 //     threshold T = 64*64, the n^2 end of Section 3.4's range for n = 64.
+//     When even the union of the two MBRs fits one tile, that tile is used
+//     and I and U are both counted there, so the ring areas are not needed
+//     (SCCG_F_NO_UNION_TILE turns this off).
 //   - Larger boxes are split into at most 8x8 cells whose side is 64*8^l, so
 //     that every split lands on leaf tiles after l more levels.  One wave
 //     classifies all cells of a box in one pass over the edges: each lane
 //     takes one edge and sets the bits of the cells it hovers and of the
 //     cells whose first pixel it crosses, in two 64-bit masks, which are then
 //     OR- and XOR-reduced across the wave.  Cost O(edges) per split instead of
-//     O(cells x edges).
+//     O(cells x edges).  A split into fewer than min_classify_cells leaf
+//     tiles is not classified: its tiles are pixelized directly.
+//   - Rings are read 64 vertices at a time with the next chunk in flight
+//     (RingStream); a vertex's successor comes from the next lane.
 //   - Leaf tiles use bit-sliced crossing tests: a lane holds one column of
 //     the tile as a row mask.  Each vertical edge of the tile's band XORs its
 //     row mask into the LDS slot of the rightmost column it toggles (one
