@@ -314,6 +314,54 @@ def test_wide_rings_exact_areas(ctx, mode):
     assert got == expect
 
 
+def _stair_bands(n_bands, x0, y0, width, step=1, h=1):
+    """Bands of a staircase whose ring has 4 * n_bands vertices (band_ring
+    keeps every corner): band k is [x0 + step*k, x0 + step*k + width) x
+    [y0 + h*k, y0 + h*k + h)."""
+    y = [y0 + h * k for k in range(n_bands + 1)]
+    a = [x0 + step * k for k in range(n_bands)]
+    return y, a, [v + width for v in a]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_tile_and_chunk_boundaries(ctx, mode):
+    """Union boxes of width and height 63..65 around the one-tile limit and
+    the 32-row mask switch, and rings of 16, 17, 32, 33 bands (64, 68, 128,
+    132 vertices) around the register chunks: counts equal closed forms."""
+    rng = np.random.default_rng(31)
+    cases = []
+    for uw in (31, 32, 33, 63, 64, 65):
+        for uh in (32, 33, 64, 65):
+            # p: [0, uw - 5) x [0, uh - 3); q: [5, uw) x [3, uh): union exactly uw x uh
+            cases.append((([0, uh - 3], [0], [uw - 5]), ([3, uh], [5], [uw])))
+    for nb in (16, 17, 32, 33):
+        for dx in (0, 7, 40):
+            cases.append((_stair_bands(nb, 0, 0, 20, 1, 1), _stair_bands(nb, dx, 2, 15, 1, 1)))
+    for _ in range(20):
+        nb_p, nb_q = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+        cases.append((_stair_bands(nb_p, 0, 0, int(rng.integers(3, 40)), int(rng.integers(0, 2)), 1),
+                      _stair_bands(nb_q, int(rng.integers(-10, 30)), int(rng.integers(-10, 30)),
+                                   int(rng.integers(3, 40)), int(rng.integers(0, 2)), int(rng.integers(1, 3)))))
+    rings_a, rings_b, expect = [], [], []
+    for pb_, qb_ in cases:
+        rings_a.append(band_ring(*pb_))
+        rings_b.append(band_ring(*qb_))
+        ra, rb = band_rects(*pb_), band_rects(*qb_)
+        i = rects_inter(ra, rb)
+        expect.append((i, rects_area(ra) + rects_area(rb) - i))
+    A, B = concat(rings_a), concat(rings_b)
+    assert {4 * 16, 4 * 17, 4 * 32, 4 * 33} <= set(np.diff(A.off).tolist())
+    idx = np.arange(len(cases), dtype=np.int32)
+    for flags in (0, sccg.SCCG_F_NO_UNION_TILE):
+        c = sccg.Context(0, flags=flags) if mode == sccg.SCCG_BATCHED else ctx
+        I, U = c.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
+        assert c.sync_code() == sccg.SCCG_OK
+        got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
+        if c is not ctx:
+            c.close()
+        assert got == expect, f"flags {flags}"
+
+
 def test_validate_polys(ctx):
     sq = band_ring([0, 5], [0], [5])
     diag = np.array([[0, 0], [5, 0], [5, 5], [1, 4]], np.int32)
