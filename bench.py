@@ -80,17 +80,41 @@ def log(msg):
 
 # The translation unit of the persistent kernel: its source, the headers it
 # includes, and the compiler flags.  Counters taken on another version of any
-# of these are not reported.
+# of these are not reported.  Comments and spacing are left out of the hash,
+# so that editing documentation does not void counters of the same code.
 KERNEL_SOURCES = ("paper_1208_0277_amd/csrc/k_batched.hip", "paper_1208_0277_amd/csrc/sccg_device.h",
                   "paper_1208_0277_amd/csrc/sccg_common.h", "include/sccg.h")
+
+
+def _code_only(text: str) -> str:
+    import re
+    out, i, n = [], 0, len(text)
+    while i < n:
+        if text.startswith("//", i):
+            i = text.find("\n", i)
+            i = n if i < 0 else i
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif text[i] in "\"'":
+            q, j = text[i], i + 1
+            while j < n and text[j] != q:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(text[i])
+            i += 1
+    return re.sub(r"\s+", " ", "".join(out)).strip()
 
 
 def kernel_source_hash() -> str:
     from paper_1208_0277_amd import build as _build
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     h.update(" ".join(_build.FLAGS).encode())
     return h.hexdigest()[:16]
 
@@ -179,7 +203,7 @@ def serve_bench(args):
     log(f"corpus: {corpus_n} pairs, {len(wl.A.xy) + len(wl.B.xy)} vertices (pinned), oracle counts in "
         f"{time.perf_counter() - t0:.1f} s")
     local = np.arange(5 * 10 ** 5, dtype=np.int32)
-    srv = sccg.Server(0, cpu_threads=args.cpu_threads)
+    srv = sccg.Server(0, cpu_threads=args.cpu_threads, cpu_max_pairs=args.cpu_max_pairs)
     rng = np.random.default_rng(sccg_gen.BASE_SEED + 5)
     out_rates, all_exact = [], True
     try:
@@ -263,7 +287,8 @@ def serve_bench(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": WORKLOADS[5], "corpus_pairs": corpus_n,
                    "rates": [r if math.isfinite(r) else "all at once" for r in rates],
-                   "cpu_threads": args.cpu_threads, "parallelism": "none (1 GPU)"},
+                   "cpu_threads": args.cpu_threads, "cpu_max_pairs": args.cpu_max_pairs,
+                   "parallelism": "none (1 GPU)"},
         "serving": out_rates, "bit_exact_oracle_sample": bool(all_exact), "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -355,6 +380,8 @@ def main(argv=None):
     ap.add_argument("--jobs", type=int, default=600, help="workload 5: jobs per rate")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="workload 5: host threads for jobs migrated off a full device (0 = no migration)")
+    ap.add_argument("--cpu-max-pairs", type=int, default=0,
+                    help="workload 5: largest job that migrates (0 = the server's default)")
     ap.add_argument("--tiles", type=int, default=64, help="workload 4: number of tiles")
     ap.add_argument("--pairs", type=int, default=None, help="override the pair count (not the headline)")
     ap.add_argument("--plain-steps", type=int, default=1)

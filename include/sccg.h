@@ -275,17 +275,21 @@ const char* sccg_last_error(const sccg_ctx* ctx);
  * sccg_jaccard_sets over the job's pairs, whatever else runs beside it.
  *
  * Unlike the calls above, sccg_server_submit takes HOST pointers.  They are
- * borrowed until the job's result has been returned by sccg_server_poll;
- * memory from hipHostMalloc (pinned) is copied by DMA without staging.  A
+ * borrowed until the job's result has been returned by sccg_server_poll.
+ * Offsets and pair indices are copied on admission into pinned mirrors of
+ * the arenas and sent from there; vertices are sent straight from the
+ * caller's memory, so they should be pinned (hipHostMalloc): a copy from
+ * pageable memory holds the scheduler until the copy stream reaches it.  A
  * server runs its own scheduler thread and two streams on its device;
  * submit, poll, stats and clock may be called from any thread. */
 typedef struct sccg_server sccg_server;
 
 typedef struct {
   int64_t vertex_cap;     /* resident vertex arena, in vertices (8 B each); 0 = 2^28                  */
-  int64_t slot_cap;       /* resident offset arena, in entries (8 B each): a job takes
-                             n_polys(A) + n_polys(B) + 2; 0 = 2^24, at most 2^31 - 1                 */
-  int64_t pair_cap;       /* resident pair arena, in pairs (24 B of device and 16 B of pinned host
+  int64_t slot_cap;       /* resident offset arena, in entries (8 B of device and 8 B of pinned host
+                             memory each): a job takes n_polys(A) + n_polys(B) + 2; 0 = 2^24, at most
+                             2^31 - 1                                                                 */
+  int64_t pair_cap;       /* resident pair arena, in pairs (24 B of device and 24 B of pinned host
                              memory each); 0 = 2^23                                                   */
   int64_t max_step_pairs; /* pairs per launch; a larger job runs alone in its launch; 0 = 2^21        */
   int32_t max_inflight;   /* launches queued on the device at once, 1..4; 0 = 2                      */
@@ -294,11 +298,12 @@ typedef struct {
    * least cpu_trigger jobs wait for admission (the arenas, the device's input
    * buffer, are full), the scheduler moves the waiting job with the fewest
    * pairs, if it has at most cpu_max_pairs, to a migration thread that runs
-   * it with the host PixelBox on cpu_threads threads, one job at a time.
-   * Its result is bit-identical to the device's, with jobs_in_launch 0.      */
+   * it with the host PixelBox on cpu_threads threads (a pool kept for the
+   * server's life), one job at a time.  Its result is bit-identical to the
+   * device's, with jobs_in_launch 0.                                         */
   int32_t cpu_threads;    /* 0 = no migration; at most 256                                            */
   int32_t cpu_trigger;    /* waiting jobs that wake the migration; 0 = 1                              */
-  int64_t cpu_max_pairs;  /* largest job that migrates; 0 = 2^16                                      */
+  int64_t cpu_max_pairs;  /* largest job that migrates; 0 = 2^20                                      */
 } sccg_server_config;
 
 typedef struct {

@@ -104,6 +104,19 @@ class sccg_job_result(ctypes.Structure):
 _lib = None
 
 
+def _init_torch_gpu() -> None:
+    """PyTorch ships its own HIP runtime and the library links the system's:
+    both end up in one process, and a runtime that starts after the other has
+    taken the device sees no GPU.  PyTorch's (which allocates the tensors the
+    calls take) is therefore started first, when it can see a GPU at all."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load_library(path: str = LIB_PATH):
     """Load libsccg.so (raises if it has not been built)."""
     global _lib
@@ -111,6 +124,7 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"device library not built: {path} (run __graft_entry__.build())")
+    _init_torch_gpu()
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i64 = ctypes.c_int64

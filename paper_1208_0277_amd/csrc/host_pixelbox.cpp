@@ -147,48 +147,45 @@ int64_t pair_intersection(const Ring& p, const Ring& q, std::vector<Box>& stack)
 
 namespace sccg {
 
-// Pairs [0, n) on `threads` host threads (chunks of 64 from a shared counter).
-// Returns the rejections seen: kHostErrSide for a pair-box side above 32767,
-// kHostErrCoord for a ring with a coordinate magnitude above 2^30 (the bits
-// the device latches for the same cases).
+// One participant's share of a HostWork: chunks of 64 pairs taken from the
+// shared counter until none is left.  Returns the kHostErr* bits it saw.
+uint32_t host_area_worker(HostWork& w) {
+  std::vector<Box> stack;
+  stack.reserve(256);
+  uint32_t e = 0;
+  for (;;) {
+    const int64_t k0 = w.next.fetch_add(64);
+    if (k0 >= w.n) break;
+    const int64_t k1 = std::min(k0 + 64, w.n);
+    for (int64_t k = k0; k < k1; ++k) {
+      bool bad_p = false, bad_q = false;
+      const Ring p = make_ring(w.A, w.pa[k], &bad_p), q = make_ring(w.B, w.pb[k], &bad_q);
+      if (bad_p || bad_q) e |= kHostErrCoord;
+      const int64_t bw = (int64_t)std::min(p.x1, q.x1) - std::max(p.x0, q.x0);
+      const int64_t bh = (int64_t)std::min(p.y1, q.y1) - std::max(p.y0, q.y0);
+      if (bw > 32767 || bh > 32767) {  // rejected like the device rejects it
+        e |= kHostErrSide;
+        w.out_i[k] = 0;
+        w.out_u[k] = 0;
+        continue;
+      }
+      const int64_t I = pair_intersection(p, q, stack);
+      w.out_i[k] = I;
+      w.out_u[k] = p.area + q.area - I;
+    }
+  }
+  return e;
+}
+
+// Pairs [0, n) on `threads` host threads started for this call.
 uint32_t host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n, const int32_t* pa, const int32_t* pb,
                          int64_t* out_i, int64_t* out_u, int threads) {
-  std::atomic<int64_t> next{0};
-  std::atomic<uint32_t> err{0};
-  auto work = [&]() {
-    std::vector<Box> stack;
-    stack.reserve(256);
-    uint32_t e = 0;
-    for (;;) {
-      const int64_t k0 = next.fetch_add(64);
-      if (k0 >= n) break;
-      const int64_t k1 = std::min(k0 + 64, n);
-      for (int64_t k = k0; k < k1; ++k) {
-        bool bad_p = false, bad_q = false;
-        const Ring p = make_ring(A, pa[k], &bad_p), q = make_ring(B, pb[k], &bad_q);
-        if (bad_p || bad_q) e |= kHostErrCoord;
-        const int64_t bw = (int64_t)std::min(p.x1, q.x1) - std::max(p.x0, q.x0);
-        const int64_t bh = (int64_t)std::min(p.y1, q.y1) - std::max(p.y0, q.y0);
-        if (bw > 32767 || bh > 32767) {  // rejected like the device rejects it
-          e |= kHostErrSide;
-          out_i[k] = 0;
-          out_u[k] = 0;
-          continue;
-        }
-        const int64_t I = pair_intersection(p, q, stack);
-        out_i[k] = I;
-        out_u[k] = p.area + q.area - I;
-      }
-    }
-    err.fetch_or(e);
-  };
+  HostWork w{A, B, pa, pb, out_i, out_u, n};
   threads = std::max(1, threads);
-  if (threads == 1 || n < 256) {
-    work();
-    return err.load();
-  }
+  if (threads == 1 || n < 256) return host_area_worker(w);
+  std::atomic<uint32_t> err{0};
   std::vector<std::thread> pool;
-  for (int t = 0; t < threads; ++t) pool.emplace_back(work);
+  for (int t = 0; t < threads; ++t) pool.emplace_back([&] { err.fetch_or(host_area_worker(w)); });
   for (auto& t : pool) t.join();
   return err.load();
 }

@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -114,6 +115,12 @@ struct sccg_server {
   int32_t* d_pb = nullptr;
   int64_t* d_i = nullptr;
   int64_t* d_u = nullptr;
+  // pinned mirrors of the offset and pair arenas: a job's offsets and pair
+  // indices are copied there first, so that their DMA is asynchronous (an
+  // asynchronous copy from pageable memory waits for the copy stream)
+  int64_t* h_off = nullptr;  // pinned [slot_cap]
+  int32_t* h_pa = nullptr;   // pinned [pair_cap]
+  int32_t* h_pb = nullptr;
   int64_t* h_i = nullptr;  // pinned [pair_cap]
   int64_t* h_u = nullptr;
   Slot slots[kMaxInflight];
@@ -121,6 +128,16 @@ struct sccg_server {
   std::chrono::steady_clock::time_point t0;
   std::thread thread;
   std::thread migrator;  // only with cfg.cpu_threads > 0
+  // host worker pool: cpu_threads - 1 helpers that join the migration
+  // thread on each migrated job
+  std::vector<std::thread> helpers;
+  std::mutex pmu;
+  std::condition_variable pcv_go, pcv_done;
+  HostWork* pwork = nullptr;  // guarded by pmu
+  uint64_t pgen = 0;          // guarded by pmu: bumped for each job
+  int pbusy = 0;              // guarded by pmu: helpers still on the current job
+  bool pstop = false;         // guarded by pmu
+  std::atomic<uint32_t> perr{0};
 
   std::mutex mu;
   std::condition_variable cv_work;
@@ -199,11 +216,14 @@ struct HipExec {
     if (j->vB > 0)
       SERVE_TRY(s, hipMemcpyAsync(s->d_xy + 2 * (v + j->vA), j->B.xy + 2 * j->B.offsets[0], (size_t)j->vB * 8,
                                   hipMemcpyHostToDevice, s->copy));
-    SERVE_TRY(s, hipMemcpyAsync(s->d_off + sl, j->A.offsets, (size_t)(nA + 1) * 8, hipMemcpyHostToDevice, s->copy));
-    SERVE_TRY(s, hipMemcpyAsync(s->d_off + sl + nA + 1, j->B.offsets, (size_t)(nB + 1) * 8, hipMemcpyHostToDevice,
+    memcpy(s->h_off + sl, j->A.offsets, (size_t)(nA + 1) * 8);
+    memcpy(s->h_off + sl + nA + 1, j->B.offsets, (size_t)(nB + 1) * 8);
+    memcpy(s->h_pa + p, j->pa, (size_t)j->n_pairs * 4);
+    memcpy(s->h_pb + p, j->pb, (size_t)j->n_pairs * 4);
+    SERVE_TRY(s, hipMemcpyAsync(s->d_off + sl, s->h_off + sl, (size_t)(nA + nB + 2) * 8, hipMemcpyHostToDevice,
                                 s->copy));
-    SERVE_TRY(s, hipMemcpyAsync(s->d_pa + p, j->pa, (size_t)j->n_pairs * 4, hipMemcpyHostToDevice, s->copy));
-    SERVE_TRY(s, hipMemcpyAsync(s->d_pb + p, j->pb, (size_t)j->n_pairs * 4, hipMemcpyHostToDevice, s->copy));
+    SERVE_TRY(s, hipMemcpyAsync(s->d_pa + p, s->h_pa + p, (size_t)j->n_pairs * 4, hipMemcpyHostToDevice, s->copy));
+    SERVE_TRY(s, hipMemcpyAsync(s->d_pb + p, s->h_pb + p, (size_t)j->n_pairs * 4, hipMemcpyHostToDevice, s->copy));
     const int64_t total = nA + 1 + nB + 1 + j->n_pairs;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 1024);
     hipLaunchKernelGGL(k_serve_rebase, dim3(blocks), dim3(256), 0, s->copy, s->d_off + sl, nA + 1,
@@ -310,7 +330,23 @@ sccg_job_result run_on_host(sccg_server* s, Job* j) {
     bu.resize((size_t)j->n_pairs);
     ou = bu.data();
   }
-  const uint32_t e = host_area_pairs(&j->A, &j->B, j->n_pairs, j->pa, j->pb, oi, ou, s->cfg.cpu_threads);
+  // the job's pairs are shared by this thread and the pool's helpers
+  HostWork w{&j->A, &j->B, j->pa, j->pb, oi, ou, j->n_pairs};
+  const int nh = (int)s->helpers.size();
+  if (nh > 0 && j->n_pairs > 64) {
+    std::lock_guard<std::mutex> lk(s->pmu);
+    s->pwork = &w;
+    s->pgen += 1;
+    s->pbusy = nh;
+  }
+  if (nh > 0 && j->n_pairs > 64) s->pcv_go.notify_all();
+  uint32_t e = host_area_worker(w);
+  if (nh > 0 && j->n_pairs > 64) {
+    std::unique_lock<std::mutex> lk(s->pmu);
+    s->pcv_done.wait(lk, [s] { return s->pbusy == 0; });
+    s->pwork = nullptr;
+    e |= s->perr.exchange(0);
+  }
   const bool include_zero = (s->cfg.jaccard_flags & SCCG_J_INCLUDE_ZERO) != 0;
   uint64_t si = 0, su = 0, nn = 0;
   Fix192 acc;
@@ -351,6 +387,24 @@ int migrate(sccg_server* s) {
   }
   s->cv_host.notify_one();
   return 1;
+}
+
+// A helper of the host pool: takes part in every job the migration thread
+// posts, until the pool stops.
+void pool_helper(sccg_server* s) {
+  uint64_t seen = 0;
+  std::unique_lock<std::mutex> lk(s->pmu);
+  for (;;) {
+    s->pcv_go.wait(lk, [&] { return s->pstop || s->pgen != seen; });
+    if (s->pstop) break;
+    seen = s->pgen;
+    HostWork* w = s->pwork;
+    lk.unlock();
+    const uint32_t e = host_area_worker(*w);
+    if (e) s->perr.fetch_or(e);
+    lk.lock();
+    if (--s->pbusy == 0) s->pcv_done.notify_one();
+  }
 }
 
 void migration_thread(sccg_server* s) {
@@ -461,6 +515,9 @@ void free_server(sccg_server* s) {
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (s->h_i) (void)hipHostFree(s->h_i);
+  if (s->h_off) (void)hipHostFree(s->h_off);
+  if (s->h_pa) (void)hipHostFree(s->h_pa);
+  if (s->h_pb) (void)hipHostFree(s->h_pb);
   if (s->h_u) (void)hipHostFree(s->h_u);
   if (s->ctx) (void)sccg_destroy(s->ctx);
   if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -493,7 +550,7 @@ int sccg_server_create(sccg_server** out, int hip_device, const sccg_server_conf
   if (c.max_step_pairs == 0) c.max_step_pairs = (int64_t)1 << 21;
   if (c.max_inflight == 0) c.max_inflight = 2;
   if (c.cpu_trigger == 0) c.cpu_trigger = 1;
-  if (c.cpu_max_pairs == 0) c.cpu_max_pairs = (int64_t)1 << 16;
+  if (c.cpu_max_pairs == 0) c.cpu_max_pairs = (int64_t)1 << 20;
   if (c.vertex_cap < 1 || c.vertex_cap > ((int64_t)1 << 36) || c.slot_cap < 3 || c.slot_cap > INT32_MAX ||
       c.pair_cap < 1 || c.pair_cap >= ((int64_t)1 << 31) || c.max_step_pairs < 1 || c.max_inflight < 1 ||
       c.max_inflight > kMaxInflight || (c.jaccard_flags & ~SCCG_J_INCLUDE_ZERO) || c.cpu_threads < 0 ||
@@ -528,6 +585,9 @@ int sccg_server_create(sccg_server** out, int hip_device, const sccg_server_conf
             hipMalloc((void**)&s->d_i, (size_t)c.pair_cap * 8) == hipSuccess &&
             hipMalloc((void**)&s->d_u, (size_t)c.pair_cap * 8) == hipSuccess &&
             hipHostMalloc((void**)&s->h_i, (size_t)c.pair_cap * 8, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&s->h_off, (size_t)c.slot_cap * 8, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&s->h_pa, (size_t)c.pair_cap * 4, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&s->h_pb, (size_t)c.pair_cap * 4, hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void**)&s->h_u, (size_t)c.pair_cap * 8, hipHostMallocDefault) == hipSuccess;
   for (int k = 0; ok && k < c.max_inflight; ++k) {
     Slot& sl = s->slots[k];
@@ -545,7 +605,10 @@ int sccg_server_create(sccg_server** out, int hip_device, const sccg_server_conf
     free_server(s);
     return SCCG_E_NOMEM;
   }
-  if (c.cpu_threads > 0) s->migrator = std::thread(migration_thread, s);
+  if (c.cpu_threads > 0) {
+    for (int t = 1; t < c.cpu_threads; ++t) s->helpers.emplace_back(pool_helper, s);
+    s->migrator = std::thread(migration_thread, s);
+  }
   s->thread = std::thread(scheduler, s);
   *out = s;
   return SCCG_OK;
@@ -655,6 +718,12 @@ int sccg_server_destroy(sccg_server* s) {
   }
   s->cv_host.notify_all();
   if (s->migrator.joinable()) s->migrator.join();
+  {
+    std::lock_guard<std::mutex> lk(s->pmu);
+    s->pstop = true;
+  }
+  s->pcv_go.notify_all();
+  for (std::thread& t : s->helpers) t.join();
   (void)hipSetDevice(s->device);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   if (s->copy) (void)hipStreamSynchronize(s->copy);
