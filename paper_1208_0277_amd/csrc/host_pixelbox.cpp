@@ -7,8 +7,9 @@
 // interior; otherwise the centre of its first pixel decides), boxes inside
 // both add their size, boxes outside either are dropped, the rest are split
 // in four until they are at most 64 pixels wide and below the pixelization
-// threshold, where each row is tested at once: a 64-bit mask per row whose
-// bit c is the crossing parity of pixel column x0 + c (Section 3.1).  The
+// threshold.  Such a box is not classified: each of its rows is tested at
+// once, a 64-bit mask per row whose bit c is the crossing parity of pixel
+// column x0 + c (Section 3.1).  The
 // union is |p| + |q| - I.  The counts equal the device's exactly.
 #include <stdint.h>
 
@@ -80,9 +81,11 @@ Pos position(const Ring& r, int32_t x0, int32_t y0, int32_t x1, int32_t y1) {
 }
 
 // Row masks of a box at most 64 wide: bit c of rows[y - y0] is the parity of
-// pixel (x0 + c, y).
+// pixel (x0 + c, y).  Each vertical edge toggles the same mask on a run of
+// rows, so its mask is XORed at the run's first row and just past its last,
+// and a prefix XOR down the rows then gives every row's mask.
 void row_masks(const Ring& r, int32_t x0, int32_t y0, int32_t w, int32_t h, uint64_t* rows) {
-  std::fill(rows, rows + h, 0ull);
+  std::fill(rows, rows + h + 1, 0ull);
   for (int64_t i = 0; i < r.n; ++i) {
     const int64_t j = i + 1 == r.n ? 0 : i + 1;
     const int32_t ax = r.xy[2 * i], ay = r.xy[2 * i + 1], bx = r.xy[2 * j], by = r.xy[2 * j + 1];
@@ -91,8 +94,10 @@ void row_masks(const Ring& r, int32_t x0, int32_t y0, int32_t w, int32_t h, uint
     if (lo >= hi) continue;
     const int32_t c = std::min(ax - x0, w);
     const uint64_t m = c >= 64 ? ~0ull : ((1ull << c) - 1);
-    for (int32_t y = lo; y < hi; ++y) rows[y - y0] ^= m;
+    rows[lo - y0] ^= m;
+    rows[hi - y0] ^= m;
   }
+  for (int32_t y = 1; y < h; ++y) rows[y] ^= rows[y - 1];
 }
 
 struct Box {
@@ -105,22 +110,25 @@ int64_t pair_intersection(const Ring& p, const Ring& q, std::vector<Box>& stack)
   const int32_t bx1 = std::min(p.x1, q.x1), by1 = std::min(p.y1, q.y1);
   if (bx0 >= bx1 || by0 >= by1) return 0;
   int64_t acc = 0;
-  uint64_t rp[64], rq[64];
+  uint64_t rp[65], rq[65];
   stack.clear();
   stack.push_back(Box{bx0, by0, bx1, by1, false, false});
   while (!stack.empty()) {
     const Box b = stack.back();
     stack.pop_back();
-    const Pos sp = b.kp ? kIn : position(p, b.x0, b.y0, b.x1, b.y1);
-    if (sp == kOut) continue;
-    const Pos sq = b.kq ? kIn : position(q, b.x0, b.y0, b.x1, b.y1);
-    if (sq == kOut) continue;
     const int32_t w = b.x1 - b.x0, h = b.y1 - b.y0;
+    const bool leaf = w <= 64 && h <= 64 && (int64_t)w * h < 4096;
+    // a box that is pixelized anyway is not classified first: its row masks
+    // give the same count
+    const Pos sp = b.kp ? kIn : (leaf ? kHover : position(p, b.x0, b.y0, b.x1, b.y1));
+    if (sp == kOut) continue;
+    const Pos sq = b.kq ? kIn : (leaf ? kHover : position(q, b.x0, b.y0, b.x1, b.y1));
+    if (sq == kOut) continue;
     if (sp == kIn && sq == kIn) {
       acc += (int64_t)w * h;
       continue;
     }
-    if (w <= 64 && h <= 64 && (int64_t)w * h < 4096) {
+    if (leaf) {
       if (sp == kIn)
         std::fill(rp, rp + h, w >= 64 ? ~0ull : ((1ull << w) - 1));
       else

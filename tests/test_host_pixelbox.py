@@ -96,3 +96,26 @@ def test_wide_rings_closed_form(lib):
     idx = np.arange(len(cases), dtype=np.int32)
     I, U = _run(A, B, idx, idx)
     assert list(zip(I.tolist(), U.tolist())) == expect
+
+
+def test_leaf_limit_boxes_closed_form(lib):
+    """Pair boxes of 1, 63, 64 and 65 pixels a side around the 64-wide leaf
+    limit, with staircases whose edges toggle runs of rows that start and end
+    at the box's first and last rows: counts equal closed forms."""
+    cases = []
+    for w in (1, 63, 64, 65, 130):
+        for h in (1, 63, 64, 65, 130):
+            # p: [0, w) x [0, h), q covers p's box with a notch cut at its
+            # left side, so the pair box is exactly p's box
+            cases.append((([0, h], [0], [w]), ([-2, h // 3, h + 2], [-1, w // 2], [w + 1, w + 1])))
+            cases.append((staircase(max(1, h // 4), h, 1, max(2, w - h // 4)), ([0, h], [0], [w])))
+    A = concat([band_ring(*p) for p, _ in cases])
+    B = concat([band_ring(*q) for _, q in cases])
+    expect = []
+    for p, q in cases:
+        i = rects_inter(band_rects(*p), band_rects(*q))
+        expect.append((i, rects_area(band_rects(*p)) + rects_area(band_rects(*q)) - i))
+    idx = np.arange(len(cases), dtype=np.int32)
+    for threads in (1, 3):
+        I, U = _run(A, B, idx, idx, threads=threads)
+        assert list(zip(I.tolist(), U.tolist())) == expect
