@@ -37,7 +37,7 @@ Ring make_ring(const sccg_polys* P, int64_t k, bool* rejected) {
   r.n = P->offsets[k + 1] - P->offsets[k];
   r.x0 = r.y0 = INT32_MAX;
   r.x1 = r.y1 = INT32_MIN;
-  int64_t twice = 0;
+  uint64_t twice = 0;  // wrapping sum: twice the area can reach 2^63 in size
   for (int64_t i = 0; i < r.n; ++i) {
     const int64_t j = i + 1 == r.n ? 0 : i + 1;
     const int32_t x = r.xy[2 * i], y = r.xy[2 * i + 1];
@@ -45,7 +45,7 @@ Ring make_ring(const sccg_polys* P, int64_t k, bool* rejected) {
     r.y0 = std::min(r.y0, y);
     r.x1 = std::max(r.x1, x);
     r.y1 = std::max(r.y1, y);
-    twice += (int64_t)x * r.xy[2 * j + 1] - (int64_t)r.xy[2 * j] * y;
+    twice += (uint64_t)((int64_t)x * r.xy[2 * j + 1] - (int64_t)r.xy[2 * j] * y);
   }
   const bool bad = r.n > 0 && (r.x0 < -kMaxCoord || r.y0 < -kMaxCoord || r.x1 > kMaxCoord || r.y1 > kMaxCoord);
   *rejected = bad;
@@ -55,7 +55,7 @@ Ring make_ring(const sccg_polys* P, int64_t k, bool* rejected) {
     r.x1 = r.y1 = INT32_MIN;
     r.area = 0;
   } else {
-    r.area = (twice < 0 ? -twice : twice) / 2;
+    r.area = (int64_t)(((int64_t)twice < 0 ? 0 - twice : twice) / 2);
   }
   return r;
 }
@@ -92,7 +92,8 @@ void row_masks(const Ring& r, int32_t x0, int32_t y0, int32_t w, int32_t h, uint
     if (ax != bx || ax <= x0) continue;
     const int32_t lo = std::max(std::min(ay, by), y0), hi = std::min(std::max(ay, by), y0 + h);
     if (lo >= hi) continue;
-    const int32_t c = std::min(ax - x0, w);
+    // ax > x0; ax - x0 itself can reach 2^31
+    const int32_t c = ax >= x0 + w ? w : ax - x0;
     const uint64_t m = c >= 64 ? ~0ull : ((1ull << c) - 1);
     rows[lo - y0] ^= m;
     rows[hi - y0] ^= m;

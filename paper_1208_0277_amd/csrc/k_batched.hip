@@ -58,7 +58,7 @@
 namespace sccg {
 
 constexpr int kLeafSlots = 2 * kWave;  // per-wave leaf slots: one per column of p and of q
-constexpr int kBandCap = 256;           // per-wave band-edge list of one ring (p and q each)
+constexpr int kBandCap = 512;           // per-wave band-edge list of one ring (p and q each)
 constexpr int kLocalCap = 256;          // per-wave stack of boxes to process inline
 constexpr uint32_t kSpinLimit = 1u << 22;
 // per-wave LDS: leaf slots, band-edge lists, the inline box stack, the
@@ -106,6 +106,10 @@ __device__ __forceinline__ uint32_t cols_bits(int i0, int i1) { return (0xFFu >>
 __device__ __forceinline__ uint64_t row_range(int lo, int hi) {
   return (~0ull << lo) & (~0ull >> (64 - hi));
 }
+// x limited to [lo, hi]: a coordinate clamped to a box's sides before the
+// box origin is subtracted, since |x| <= 2^30 on both sides of a difference
+// could leave int32
+__device__ __forceinline__ int clamp_to(int x, int lo, int hi) { return min(max(x, lo), hi); }
 
 // ----------------------------------------------------------------- context
 struct Ctx {
@@ -312,7 +316,7 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
   m.x1 = wave_max_i32(x1);
   m.y1 = wave_max_i32(y1);
   const int32_t t = (int32_t)wave_sum_u32(twice);
-  if ((uint32_t)(m.x1 - m.x0) < 16384u && (uint32_t)(m.y1 - m.y0) < 16384u) {
+  if (side_u(m.x0, m.x1) < 16384u && side_u(m.y0, m.y1) < 16384u) {
     area = (int64_t)(t < 0 ? -(int64_t)t : (int64_t)t) / 2;
   } else {
     uint64_t tw = 0;
@@ -323,8 +327,10 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
       const int2 w = rs.succ();
       if (rs.valid()) tw += (uint64_t)((int64_t)rs.cur.x * w.y) - (uint64_t)((int64_t)w.x * rs.cur.y);
     } while (rs.next());
-    const int64_t t64 = (int64_t)wave_sum_u64(tw);
-    area = (t64 < 0 ? -t64 : t64) / 2;
+    // twice the area is at most 2^63 in size, so the magnitude of the wrapped
+    // sum is exact in unsigned form
+    const uint64_t t64 = wave_sum_u64(tw);
+    area = (int64_t)(((int64_t)t64 < 0 ? 0 - t64 : t64) / 2);
   }
   if (nv <= 0 || m.x0 < -kMaxCoord || m.y0 < -kMaxCoord || m.x1 > kMaxCoord || m.y1 > kMaxCoord) {
     m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};  // covers nothing
@@ -415,11 +421,11 @@ __device__ __forceinline__ uint64_t wave_prefix_xor(uint64_t x) {
 __device__ __forceinline__ bool leaf_edge(int2 v, int2 w, int tx0, int ty0, int th, int W, int& slot,
                                           uint64_t& rr) {
   if (v.x != w.x) return false;
-  const int lo = max(min(v.y, w.y) - ty0, 0);
-  const int hi = min(max(v.y, w.y) - ty0, th);
-  const int dx = v.x - tx0;
+  const int lo = clamp_to(min(v.y, w.y), ty0, ty0 + th) - ty0;
+  const int hi = clamp_to(max(v.y, w.y), ty0, ty0 + th) - ty0;
+  const int dx = min(v.x, tx0 + W) - tx0;
   if (!(lo < hi && dx > 0)) return false;
-  slot = W - min(dx, W);
+  slot = W - dx;
   rr = row_range(lo, hi);
   return true;
 }
@@ -572,11 +578,58 @@ __device__ __forceinline__ uint64_t leaf_count(Ctx& c, const PairInfo& pi, int t
   return pack_counts(n, nu, direct_union(a));
 }
 
-// Band rows.  When a split leaves several leaf tiles in one 64-row band,
-// each ring is read once into a compact list of its band edges (4 bytes per
-// edge: X relative to the row's leftmost tile, and the row span), and every
-// tile of the row scatters from that list instead of reading the ring again.
-// Record: dx (11 bits, capped at 2047), lo (7 bits), hi (7 bits).
+// Band rows.  When a split leaves several leaf tiles, each ring is read once
+// into compact lists of its band edges (4 bytes per edge: X relative to the
+// list's origin, and the span within the 64-row band), one list per band row,
+// and every tile of a row scatters from its row's list instead of reading
+// the ring again.  Record: dx (11 bits, capped at kBandMaxDx), lo (7 bits),
+// hi (7 bits).
+constexpr int kBandMaxDx = 2047;
+__device__ __forceinline__ uint32_t band_record(int dx, int lo, int hi) {
+  return (uint32_t)dx | ((uint32_t)lo << 11) | ((uint32_t)hi << 18);
+}
+
+// Stage the band edges of one ring for the band rows `rows` (bit j: rows
+// [by0 + 64 j, by0 + 64 j + 64) of a split at most 8 tiles high) in one pass
+// over the ring.  The k-th row of `rows` has list[k * cap, (k + 1) * cap),
+// X relative to bx0, and its count in bits [8 j, 8 j + 8) of `counts`
+// (cap <= 255).  Returns the rows whose edges did not fit.
+__device__ __forceinline__ uint32_t stage_rows(Ctx& c, const int2* xy, int64_t o, int64_t nv, uint32_t rows, int cap,
+                                               int bx0, int by0, int by1, uint32_t* list, uint64_t& counts) {
+  counts = 0;
+  uint32_t bad = 0;
+  if (uniform((int)nv) <= 0) return 0;
+  RingStream rs(xy, o, uniform((int)nv), c.lane);
+#pragma unroll 1
+  do {
+    rs.ahead();
+    const int2 v = rs.cur, w = rs.succ();
+    const int dx = min(v.x, bx0 + kBandMaxDx) - bx0;
+    const int ylo = clamp_to(min(v.y, w.y), by0, by1) - by0, yhi = clamp_to(max(v.y, w.y), by0, by1) - by0;
+    const bool edge = rs.valid() && v.x == w.x && dx > 0 && ylo < yhi;
+    // the band rows met by this chunk's edges (64 consecutive vertices
+    // usually meet one or two): only those rows are tested
+    const uint32_t met = wave_or_u32(edge ? (2u << ((yhi - 1) >> 6)) - (1u << (ylo >> 6)) : 0u);
+#pragma unroll 1
+    for (uint32_t live = rows & ~bad & met; live; live &= live - 1) {
+      const int j = __ffs((int)live) - 1;
+      const int lo = max(ylo - kTile * j, 0), hi = min(yhi - kTile * j, kTile);
+      const bool keep = edge && lo < hi;
+      const uint64_t b = ballot(keep);
+      const int nk = __popcll(b);
+      const int cj = (int)((counts >> (8 * j)) & 0xffu);
+      if (cj + nk > cap) {
+        bad |= 1u << j;
+        continue;
+      }
+      const int seg = __popc(rows & ((1u << j) - 1u));
+      if (keep) list[seg * cap + cj + lanes_below(b)] = band_record(dx, lo, hi);
+      counts += (uint64_t)nk << (8 * j);
+    }
+  } while (rs.next());
+  stat_add(c, 10, (unsigned long long)nv * __popc(rows));
+  return bad;
+}
 
 // Stage the band edges of one ring that lie right of xs; returns the count,
 // or -1 if they do not fit in kBandCap.
@@ -593,12 +646,12 @@ __device__ __forceinline__ int stage_band(Ctx& c, const int2* xy, int64_t o, int
     bool keep = false;
     uint32_t rec = 0;
     if (rs.valid() && v.x == w.x) {
-      const int lo = max(min(v.y, w.y) - ty0, 0);
-      const int hi = min(max(v.y, w.y) - ty0, th);
-      const int dx = v.x - xs;
+      const int lo = clamp_to(min(v.y, w.y), ty0, ty0 + th) - ty0;
+      const int hi = clamp_to(max(v.y, w.y), ty0, ty0 + th) - ty0;
+      const int dx = min(v.x, xs + kBandMaxDx) - xs;
       if (lo < hi && dx > 0) {
         keep = true;
-        rec = (uint32_t)min(dx, 2047) | ((uint32_t)lo << 11) | ((uint32_t)hi << 18);
+        rec = band_record(dx, lo, hi);
       }
     }
     const uint64_t b = ballot(keep);
@@ -638,15 +691,16 @@ __device__ __forceinline__ void scatter_band(Ctx& c, const uint32_t* list, int n
 
 // Count of one tile of a band row from the staged lists (n < 0: the polygon
 // is known to contain the tile).
-__device__ __forceinline__ uint64_t leaf_from_band(Ctx& c, int np, int nq, int off, int tw, int th) {
+__device__ __forceinline__ uint64_t leaf_from_band(Ctx& c, const uint32_t* lp, int np, const uint32_t* lq, int nq,
+                                                   int off, int tw, int th) {
   const int lane = c.lane;
   uint64_t* slots = c.slots;
   slots[lane] = fresh_zero<uint64_t>();
   slots[kWave + lane] = fresh_zero<uint64_t>();
   wave_sync_lds();
   uint64_t fp = 0, fq = 0;
-  if (np >= 0) scatter_band(c, c.band, np, off, slots, 0, fp);
-  if (nq >= 0) scatter_band(c, c.band + kBandCap, nq, off, slots, kWave, fq);
+  if (np >= 0) scatter_band(c, lp, np, off, slots, 0, fp);
+  if (nq >= 0) scatter_band(c, lq, nq, off, slots, kWave, fq);
   wave_sync_lds();
   const uint64_t all = row_range(0, th);
   const uint64_t mp = np < 0 ? all : wave_prefix_xor<false>(slots[lane]) ^ wave_xor64(fp);
@@ -662,41 +716,90 @@ __device__ __forceinline__ uint64_t leaf_from_band(Ctx& c, int np, int nq, int o
   return pack_counts(n, nu, direct_union(*c.a));
 }
 
+// The tiles of one band row from staged lists (n < 0: not staged, the ring is
+// known to contain every tile of the row); X of the lists relative to bx0.
+__device__ __forceinline__ void band_row_tiles(Ctx& c, const uint32_t* lp, int np, const uint32_t* lq, int nq,
+                                               uint32_t row, uint32_t kp_row, uint32_t kq_row, int bx0, int bx1,
+                                               int th, uint64_t& acc) {
+  for (uint32_t r = row; r; r &= r - 1) {
+    const int i = __ffs((int)r) - 1;
+    const int tx0 = bx0 + kTile * i, tw = min(kTile, bx1 - tx0);
+    const bool kp = (kp_row >> i) & 1u, kq = (kq_row >> i) & 1u;
+    acc += leaf_from_band(c, lp, kp ? -1 : np, lq, kq ? -1 : nq, tx0 - bx0, tw, th);
+  }
+}
+
 // The leaf tiles `cont` (bit 8j + i = tile (i, j) of side 64 from (bx0, by0))
-// of a split, processed by this wave a band row at a time.  kin_p / kin_q:
-// tiles known to lie inside p / q.
+// of a split.  kin_p / kin_q: tiles known to lie inside p / q.  A lone tile
+// is scattered straight from the rings.  Otherwise each ring is staged in one
+// pass for every band row with a tile not known inside it, a list per row;
+// rows whose lists do not fit are staged again one at a time with the whole
+// list, and failing that their tiles are scattered from the rings.
 __device__ __forceinline__ void leaf_rows(Ctx& c, const PairInfo& pi, int bx0, int by0, int bx1, int by1, int gy,
                                           uint64_t cont, uint64_t kin_p, uint64_t kin_q, uint64_t& acc) {
   const BatchArgs& a = *c.a;
+  if (__popcll(cont) == 1) {
+    const int t = __ffsll((long long)cont) - 1, i = t & 7, j = t >> 3;
+    const int tx0 = bx0 + kTile * i, ty0 = by0 + kTile * j;
+    acc += leaf_count(c, pi, tx0, ty0, min(kTile, bx1 - tx0), min(kTile, by1 - ty0), (kin_p >> t) & 1ull,
+                      (kin_q >> t) & 1ull);
+    return;
+  }
+  uint32_t rows = 0, sp = 0, sq = 0;
   for (int j = 0; j < gy; ++j) {
     const uint32_t row = (uint32_t)(cont >> (8 * j)) & 0xffu;
     if (!row) continue;
-    const int ty0 = by0 + kTile * j, th = min(kTile, by1 - ty0);
+    rows |= 1u << j;
+    if (((uint32_t)(kin_p >> (8 * j)) & row) != row) sp |= 1u << j;
+    if (((uint32_t)(kin_q >> (8 * j)) & row) != row) sq |= 1u << j;
+  }
+  const int cap_p = sp ? min(255, kBandCap / __popc(sp)) : 0;
+  const int cap_q = sq ? min(255, kBandCap / __popc(sq)) : 0;
+  uint64_t cnt_p = 0, cnt_q = 0;
+  const uint32_t bad_p = sp ? stage_rows(c, a.A.xy, pi.op, pi.np, sp, cap_p, bx0, by0, by1, c.band, cnt_p) : 0u;
+  const uint32_t bad_q =
+      sq ? stage_rows(c, a.B.xy, pi.oq, pi.nq, sq, cap_q, bx0, by0, by1, c.band + kBandCap, cnt_q) : 0u;
+  wave_sync_lds();
+  const uint32_t bad = bad_p | bad_q;
+  for (uint32_t r = rows & ~bad; r; r &= r - 1) {
+    const int j = __ffs((int)r) - 1;
+    const uint32_t row = (uint32_t)(cont >> (8 * j)) & 0xffu;
+    const int np = (sp >> j) & 1u ? (int)((cnt_p >> (8 * j)) & 0xffu) : -1;
+    const int nq = (sq >> j) & 1u ? (int)((cnt_q >> (8 * j)) & 0xffu) : -1;
+    const uint32_t* lp = c.band + __popc(sp & ((1u << j) - 1u)) * cap_p;
+    const uint32_t* lq = c.band + kBandCap + __popc(sq & ((1u << j) - 1u)) * cap_q;
+    band_row_tiles(c, lp, np, lq, nq, row, (uint32_t)(kin_p >> (8 * j)) & row, (uint32_t)(kin_q >> (8 * j)) & row,
+                   bx0, bx1, min(kTile, by1 - by0 - kTile * j), acc);
+  }
+  for (uint32_t r = bad; r; r &= r - 1) {
+    const int j = __ffs((int)r) - 1;
+    const uint32_t row = (uint32_t)(cont >> (8 * j)) & 0xffu;
     const uint32_t kp_row = (uint32_t)(kin_p >> (8 * j)) & row, kq_row = (uint32_t)(kin_q >> (8 * j)) & row;
-    const int ilo = __ffs((int)row) - 1;
-    const int xs = bx0 + kTile * ilo;
+    const int ty0 = by0 + kTile * j, th = min(kTile, by1 - ty0);
+    // both lists are restaged: the whole of each list is overwritten
+    wave_sync_lds();
     int np = -1, nq = -1;
-    bool staged = __popc(row) > 1;
-    if (staged && kp_row != row) {
-      np = stage_band(c, a.A.xy, pi.op, pi.np, xs, ty0, th, c.band);
+    bool staged = true;
+    if ((sp >> j) & 1u) {
+      np = stage_band(c, a.A.xy, pi.op, pi.np, bx0, ty0, th, c.band);
       staged = np >= 0;
     }
-    if (staged && kq_row != row) {
-      nq = stage_band(c, a.B.xy, pi.oq, pi.nq, xs, ty0, th, c.band + kBandCap);
+    if (staged && ((sq >> j) & 1u)) {
+      nq = stage_band(c, a.B.xy, pi.oq, pi.nq, bx0, ty0, th, c.band + kBandCap);
       staged = nq >= 0;
     }
     wave_sync_lds();
-    for (uint32_t r = row; r; r &= r - 1) {
-      const int i = __ffs((int)r) - 1;
-      const int tx0 = bx0 + kTile * i, tw = min(kTile, bx1 - tx0);
-      const bool kp = (kp_row >> i) & 1u, kq = (kq_row >> i) & 1u;
-      if (staged)
-        acc += leaf_from_band(c, kp ? -1 : np, kq ? -1 : nq, tx0 - xs, tw, th);
-      else
-        acc += leaf_count(c, pi, tx0, ty0, tw, th, kp, kq);
+    if (staged) {
+      band_row_tiles(c, c.band, np, c.band + kBandCap, nq, row, kp_row, kq_row, bx0, bx1, th, acc);
+    } else {
+      for (uint32_t t = row; t; t &= t - 1) {
+        const int i = __ffs((int)t) - 1;
+        const int tx0 = bx0 + kTile * i;
+        acc += leaf_count(c, pi, tx0, ty0, min(kTile, bx1 - tx0), th, (kp_row >> i) & 1u, (kq_row >> i) & 1u);
+      }
     }
-    wave_sync_lds();
   }
+  wave_sync_lds();
 }
 
 // One pass over the ring: hover mask H and first-pixel parity mask P of the
@@ -718,7 +821,9 @@ __device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int6
     if (!rs.valid()) {
       // past the end of the ring
     } else if (v.x == w.x) {
-      const int X = v.x, lo = min(v.y, w.y), hi = max(v.y, w.y);
+      // coordinates past the box's far sides are clamped to them (the tests
+      // below do not change), so that no difference leaves int32
+      const int X = min(v.x, bx1), lo = min(min(v.y, w.y), by1), hi = min(max(v.y, w.y), by1);
       const int dx = X - bx0;
       if (dx > 0 && hi > by0) {
         // hover: X strictly inside a column, span meeting the open rows
@@ -735,7 +840,7 @@ __device__ __forceinline__ void classify(Ctx& c, const int2* xy, int64_t o, int6
         if (ja <= jb) p ^= rows_bits(ja, jb) & spread(0xFFu >> (7 - ic));
       }
     } else {
-      const int Y = v.y, lo = min(v.x, w.x), hi = max(v.x, w.x);
+      const int Y = min(v.y, by1), lo = min(min(v.x, w.x), bx1), hi = min(max(v.x, w.x), bx1);
       const int dy = Y - by0;
       if (dy > 0 && Y < by1 && (dy & (S - 1)) != 0 && lo < bx1 && hi > bx0) {
         const int j = dy >> ls;
@@ -1154,7 +1259,8 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
                                     Held{use_pf, cur_vp[0], cur_vp[1]}, Held{use_pf, cur_vq[0], cur_vq[1]});
         in_regs = true;
         if (u.x0 >= -kMaxCoord && u.y0 >= -kMaxCoord && u.x1 <= kMaxCoord && u.y1 <= kMaxCoord &&
-            u.x1 - u.x0 <= kTile && u.y1 - u.y0 <= kTile && u.x0 < u.x1 && u.y0 < u.y1) {
+            u.x0 < u.x1 && u.y0 < u.y1 && side_u(u.x0, u.x1) <= (uint32_t)kTile &&
+            side_u(u.y0, u.y1) <= (uint32_t)kTile) {
           const int uw = u.x1 - u.x0, uh = u.y1 - u.y0;
           pi.box = u;
           I = uh > 32 ? leaf_small<true>(c, pi, rp, rq, uw, uh, true) : leaf_small<false>(c, pi, rp, rq, uw, uh, true);
@@ -1180,11 +1286,11 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
       if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[12], (unsigned long long)(pi.np + pi.nq));
       pi.area_sum = ap + aq;
       pi.box = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
-      const int bw = pi.box.x1 - pi.box.x0, bh = pi.box.y1 - pi.box.y0;
+      const int bw = (int)side_u(pi.box.x0, pi.box.x1), bh = (int)side_u(pi.box.y0, pi.box.y1);
       if (pi.box.x0 >= pi.box.x1 || pi.box.y0 >= pi.box.y1) {
         // empty pair box: nothing in common
         if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
-      } else if (bw > kMaxSide || bh > kMaxSide) {
+      } else if (side_u(pi.box.x0, pi.box.x1) > (uint32_t)kMaxSide || side_u(pi.box.y0, pi.box.y1) > (uint32_t)kMaxSide) {
         if (c.lane == 0) latch_error(a.err, kErrSide);
         if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
         pi.area_sum = 0;

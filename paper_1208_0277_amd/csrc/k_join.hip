@@ -34,7 +34,10 @@ __device__ __forceinline__ bool meta_empty(const Meta& m) { return m.x0 >= m.x1 
 
 // cell index of pixel coordinate v in a grid starting at o (floor division,
 // v >= o)
-__device__ __forceinline__ int cell_of(int v, int o, int cell) { return (v - o) / cell; }
+// cell index of v >= o; v - o can reach 2^31 with coordinates up to 2^30 in size
+__device__ __forceinline__ int cell_of(int v, int o, int cell) {
+  return (int)(((uint32_t)v - (uint32_t)o) / (uint32_t)cell);
+}
 
 }  // namespace
 

@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(WG) k_plain(PlainArgs a) {
       }
       continue;
     }
-    if (bx.x1 - bx.x0 > kMaxSide || bx.y1 - bx.y0 > kMaxSide) {
+    if (side_u(bx.x0, bx.x1) > (uint32_t)kMaxSide || side_u(bx.y0, bx.y1) > (uint32_t)kMaxSide) {
       if (tid == 0) {
         latch_error(a.err, kErrSide);
         a.inter[i] = 0;

@@ -9,7 +9,7 @@ namespace sccg {
 // One polygon's extent and doubled signed area, accumulated over one lane's
 // share of a ring.  The shoelace sum (Section 3.2) is taken
 // in wrapping 64-bit arithmetic: partial sums may overflow, the final value
-// (twice the area, below 2^63) is exact.
+// (twice the area, at most 2^63 in size) is exact modulo 2^64.
 struct MetaAcc {
   int32_t x0 = INT_MAX, y0 = INT_MAX, x1 = INT_MIN, y1 = INT_MIN;
   uint64_t twice = 0;
@@ -32,8 +32,9 @@ __device__ void write_meta(const MetaAcc& a, int64_t nv, int64_t k, Meta* meta, 
     return;
   }
   *reinterpret_cast<int4*>(meta + k) = make_int4(a.x0, a.y0, a.x1, a.y1);
-  int64_t t = (int64_t)a.twice;
-  area[k] = (t < 0 ? -t : t) / 2;
+  // twice the area is at most 2^63 in size: its magnitude is exact unsigned
+  const uint64_t t = (uint64_t)a.twice;
+  area[k] = (int64_t)(((int64_t)t < 0 ? 0 - t : t) / 2);
 }
 
 

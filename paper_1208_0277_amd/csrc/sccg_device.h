@@ -86,6 +86,10 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return s0 + (s1 << 22) + (s2 << 44);
 }
 
+// hi - lo of a box side (lo <= hi): with coordinates up to 2^30 in size the
+// difference can reach 2^31, which only the unsigned form holds
+__device__ __forceinline__ uint32_t side_u(int32_t lo, int32_t hi) { return (uint32_t)hi - (uint32_t)lo; }
+
 __device__ __forceinline__ void latch_error(uint32_t* err, uint32_t bit) {
   __hip_atomic_fetch_or(err, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

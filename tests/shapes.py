@@ -97,3 +97,52 @@ def transform(ring, rects, sx=1, sy=1, swap=False, dx=0, dy=0, k=1):
     r[:, 0] += dx
     r[:, 1] += dy
     return r.astype(np.int32), out_rects
+
+
+def comb_ring(n, height, base=10, x0=0):
+    """Ring (4n vertices) of a comb: base [x0, x0 + 2n - 1) x [0, base) with
+    n teeth [x0 + 2k, x0 + 2k + 1) x [base, height), one pixel wide and one
+    pixel apart, so every 64-row band above the base meets 2n vertical edges."""
+    pts = [(x0, 0), (x0 + 2 * n - 1, 0)]
+    for k in range(n - 1, -1, -1):
+        pts += [(x0 + 2 * k + 1, height), (x0 + 2 * k, height)]
+        if k > 0:
+            pts += [(x0 + 2 * k, base), (x0 + 2 * k - 1, base)]
+    return np.array(pts, dtype=np.int32)
+
+
+def comb_area(n, height, base=10):
+    return (2 * n - 1) * base + n * (height - base)
+
+
+def limit_cases():
+    """Pairs of rectangles (x0, y0, x1, y1) reaching |coordinate| = 2^30, the
+    largest accepted, where a coordinate minus a box side reaches 2^31.  In
+    every pair q lies inside p, so I = |q| and U = |p|.  The pair boxes cover
+    one leaf tile, a split into a few tiles, and a split that classifies
+    cells; the last pair's p has twice its area equal to 2^63."""
+    M = 1 << 30
+    return [
+        ((0, -M, 10, M), (0, -M, 10, -M + 5)),
+        ((-M, 0, M, 10), (-M, 0, -M + 10, 10)),
+        ((-M, 0, M, 10), (0, 0, 10, 10)),
+        ((0, -M, 100, M), (0, -M, 100, -M + 100)),
+        ((-M, 0, M, 100), (-M, 0, -M + 100, 100)),
+        ((0, -M, 600, M), (0, -M, 600, -M + 600)),
+        ((-M, -M, M, M), (M - 70, M - 70, M, M)),
+    ]
+
+
+def rect_ring(r):
+    x0, y0, x1, y1 = r
+    return band_ring([y0, y1], [x0], [x1])
+
+
+def comb_pairs(n, h):
+    """(p ring, q ring, I, U) of a comb against its box, the box against the
+    comb, the comb against itself shifted one pixel right (teeth interleave,
+    only the bases overlap) and the comb against itself."""
+    comb, shifted = comb_ring(n, h), comb_ring(n, h, x0=1)
+    box = rect_ring((0, 0, 2 * n - 1, h))
+    ca, ba, ia = comb_area(n, h), (2 * n - 1) * h, (2 * n - 2) * 10
+    return [(comb, box, ca, ba), (box, comb, ca, ba), (comb, shifted, ia, 2 * ca - ia), (comb, comb, ca, ca)]

@@ -10,7 +10,8 @@ import paper_1208_0277_amd as sccg
 import sccg_gen
 from sccg_gen import Polys, concat
 from tests.gpu_util import assert_exact, device_workload, run
-from tests.shapes import band_rects, band_ring, random_bands, rects_area, rects_inter, staircase, transform
+from tests.shapes import (band_rects, band_ring, comb_pairs, limit_cases, random_bands, rect_ring, rects_area,
+                          rects_inter, staircase, transform)
 
 pytestmark = pytest.mark.gpu
 
@@ -312,6 +313,59 @@ def test_wide_rings_exact_areas(ctx, mode):
     assert ctx.sync_code() == sccg.SCCG_OK
     got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
     assert got == expect
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_coordinates_at_the_limit(ctx, mode):
+    """Rectangles reaching |coordinate| = 2^30 paired with small ones at the
+    opposite extreme: a coordinate minus a box side reaches 2^31 in the leaf,
+    band-row and classification paths, a union box is 2^31 wide, and one ring
+    has twice its area equal to 2^63.  q lies inside p: I = |q|, U = |p|."""
+    cases = limit_cases()
+    A, B = concat([rect_ring(p) for p, _ in cases]), concat([rect_ring(q) for _, q in cases])
+    area = lambda r: (r[2] - r[0]) * (r[3] - r[1])
+    idx = np.arange(len(cases), dtype=np.int32)
+    I, U = ctx.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
+    assert ctx.sync_code() == sccg.SCCG_OK
+    got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
+    assert got == [(area(q), area(p)) for p, q in cases]
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_full_range_pair_box_is_rejected(mode):
+    """Two rings spanning [-2^30, 2^30] make a pair box 2^31 wide: beyond the
+    32767 limit, so the call reports SCCG_E_RANGE."""
+    M = 1 << 30
+    A = concat([rect_ring((-M, 0, M, 10))])
+    B = concat([rect_ring((-M, 5, M, 20))])
+    idx = np.zeros(1, np.int32)
+    c = sccg.Context(0)
+    try:
+        c.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
+        assert c.sync_code() == sccg.SCCG_E_RANGE
+    finally:
+        c.close()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("flags", [0, sccg.SCCG_F_NO_UNION_TILE])
+def test_comb_band_rows(mode, flags):
+    """Combs whose 64-row bands meet 300 and 640 vertical edges: band lists
+    that overflow their share of the staging list, are staged again one row at
+    a time, and (640 edges) fall back to scattering from the rings; with and
+    without cell classification.  Counts are closed forms."""
+    cases = comb_pairs(150, 300) + comb_pairs(320, 200)
+    A, B = concat([k[0] for k in cases]), concat([k[1] for k in cases])
+    idx = np.arange(len(cases), dtype=np.int32)
+    for mcc in (1, 26, 65):
+        c = sccg.Context(0, flags=flags, min_classify_cells=mcc)
+        try:
+            I, U = c.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
+            assert c.sync_code() == sccg.SCCG_OK
+            got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
+        finally:
+            c.close()
+        assert got == [(k[2], k[3]) for k in cases], f"min_classify_cells {mcc}"
 
 
 def _stair_bands(n_bands, x0, y0, width, step=1, h=1):

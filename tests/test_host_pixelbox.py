@@ -11,7 +11,8 @@ import oracle
 import paper_1208_0277_amd as sccg
 import sccg_gen
 from sccg_gen import concat
-from tests.shapes import band_rects, band_ring, random_bands, rects_area, rects_inter, staircase, transform
+from tests.shapes import (band_rects, band_ring, comb_pairs, limit_cases, random_bands, rect_ring, rects_area,
+                          rects_inter, staircase, transform)
 
 
 @pytest.fixture(scope="module")
@@ -119,3 +120,29 @@ def test_leaf_limit_boxes_closed_form(lib):
     for threads in (1, 3):
         I, U = _run(A, B, idx, idx, threads=threads)
         assert list(zip(I.tolist(), U.tolist())) == expect
+
+
+def test_comb_closed_forms_match_oracle():
+    cases = comb_pairs(12, 90)
+    A, B = concat([c[0] for c in cases]), concat([c[1] for c in cases])
+    idx = np.arange(len(cases), dtype=np.int32)
+    eI, eU = oracle.area_pairs(A, B, idx, idx)
+    assert list(zip(eI.tolist(), eU.tolist())) == [(c[2], c[3]) for c in cases]
+
+
+def test_combs_closed_form(lib):
+    """Combs whose 64-row bands meet 300 and 640 vertical edges each."""
+    cases = comb_pairs(150, 300) + comb_pairs(320, 200)
+    A, B = concat([c[0] for c in cases]), concat([c[1] for c in cases])
+    idx = np.arange(len(cases), dtype=np.int32)
+    I, U = _run(A, B, idx, idx)
+    assert list(zip(I.tolist(), U.tolist())) == [(c[2], c[3]) for c in cases]
+
+
+def test_coordinates_at_the_limit(lib):
+    cases = limit_cases()
+    A, B = concat([rect_ring(p) for p, _ in cases]), concat([rect_ring(q) for _, q in cases])
+    area = lambda r: (r[2] - r[0]) * (r[3] - r[1])
+    idx = np.arange(len(cases), dtype=np.int32)
+    I, U = _run(A, B, idx, idx)
+    assert list(zip(I.tolist(), U.tolist())) == [(area(q), area(p)) for p, q in cases]
