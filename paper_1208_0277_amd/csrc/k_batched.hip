@@ -29,7 +29,9 @@
 //     row mask into the LDS slot of the rightmost column it toggles (one
 //     atomic per edge), and a prefix XOR over the lanes turns the slots into
 //     every column's crossing parities.  A polygon known to contain a tile
-//     is not tested again (its mask is all ones).
+//     is not tested again (its mask is all ones).  When a split leaves
+//     several leaf tiles, each ring is read once into per-row lists of its
+//     band edges in LDS, and every tile scatters from its row's list.
 //   - The pair's MBRs and shoelace areas are reduced by the wave that takes
 //     the pair, from the same coalesced ring loads it needs anyway; only the
 //     pairs with many vertices ("heavy", claimed first: a largest-first
