@@ -527,6 +527,11 @@ def main(argv=None):
         # profiled kernel time, against the same peak
         roofline["valu_issue_frac_counters"] = prof["sq_insts_valu"] * 64 / (prof["kernel_ms"] / 1e3) / VALU_PEAK_OPS
         roofline["profile"] = f"profiles/{PROFILE_STEMS[args.workload]}.md"
+        # the further counter figures of the same summary, where it has them
+        for key in ("valu_busy_pct", "valu_utilization_pct", "valu_int32_share", "lds_bank_conflict_pct",
+                    "valu_insts_per_pixel_test"):
+            if key in prof:
+                roofline[key] = prof[key]
 
     cpu, exact_sample, n_sample = (None, None, 0)
     sets_info = {}
