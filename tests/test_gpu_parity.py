@@ -129,6 +129,26 @@ def test_config3_subset(ctx, wl3s, mode):
     assert_exact(gI, gU, eI, eU, f"heavy-tailed mix (60k pairs) mode {mode}")
 
 
+def test_config3_full_size():
+    """The whole 2,000,000-pair heavy-tailed mix in one persistent launch with
+    the parameters of the committed headline profile: every pair's counts
+    equal the oracle's (row-bucketed form, all host threads)."""
+    import json
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "profiles", "k_batch_run_heavy_tailed_2M.json")) as f:
+        params = json.load(f)["params"]
+    wl = sccg_gen.pairs(3, 2_000_000)
+    print(f"[gpu] generated {len(wl.pa)} pairs, params {params}", flush=True)
+    c = sccg.Context(0, **params)
+    try:
+        gI, gU = run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
+    finally:
+        c.close()
+    eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS, threads=min(os.cpu_count() or 1, 16))
+    assert_exact(gI, gU, eI, eU, "heavy-tailed mix, 2,000,000 pairs, headline parameters")
+
+
 PLAIN_TUNINGS = [
     dict(box_threshold=64), dict(box_threshold=512), dict(box_threshold=8192), dict(box_threshold=2),
     dict(wg_size=128), dict(wg_size=256), dict(wg_size=256, box_threshold=100000),
