@@ -149,6 +149,37 @@ def test_config3_full_size():
     assert_exact(gI, gU, eI, eU, "heavy-tailed mix, 2,000,000 pairs, headline parameters")
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_config2_full_size(ctx, mode):
+    """The whole 200,000-pair uniform workload (the plain kernel's baseline
+    set) in both modes: every pair equals the oracle."""
+    import os
+    wl = sccg_gen.pairs(2, 200_000)
+    gI, gU = run(ctx, device_workload(wl.A, wl.B, wl.pa, wl.pb), mode)
+    eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS, threads=min(os.cpu_count() or 1, 16))
+    assert_exact(gI, gU, eI, eU, f"uniform workload, 200,000 pairs, mode {mode}")
+
+
+def test_config4_full_size(ctx):
+    """Workload 4 at its full size (64 tiles of 8192 x 8192, the grid-join
+    candidates in one launch): every pair and every tile's sums, J and J'
+    equal the oracle."""
+    import os
+    import torch
+    wl = sccg_gen.sets(n_tiles=64, tile_side=8192, cell=64)
+    print(f"[gpu] generated {wl.n_pairs} pairs in {len(wl.set_off) - 1} tiles", flush=True)
+    I, U = ctx.area_pairs(*device_workload(wl.A, wl.B, wl.pa, wl.pb), mode=sccg.SCCG_BATCHED)
+    so = torch.from_numpy(wl.set_off).cuda()
+    si, su, nn, j, jp = ctx.jaccard_sets(so, I, U)
+    ctx.sync()
+    eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS, threads=min(os.cpu_count() or 1, 16))
+    assert_exact(I.cpu().numpy(), U.cpu().numpy(), eI, eU, "set workload, 64 tiles")
+    osi, osu, onn, oj, ojp = oracle.jaccard_sets(wl.set_off, eI, eU)
+    assert np.array_equal(si.cpu().numpy(), osi) and np.array_equal(su.cpu().numpy(), osu)
+    assert np.array_equal(nn.cpu().numpy(), onn)
+    assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(jp.cpu().numpy(), ojp)
+
+
 PLAIN_TUNINGS = [
     dict(box_threshold=64), dict(box_threshold=512), dict(box_threshold=8192), dict(box_threshold=2),
     dict(wg_size=128), dict(wg_size=256), dict(wg_size=256, box_threshold=100000),
