@@ -370,6 +370,23 @@ def fig8_bench(args):
     return 0
 
 
+def copy_probe(mib: int, reps: int) -> int:
+    """A device copy of a known byte count (each copy reads and writes `mib`
+    MiB), run under the profiler to scale its HBM byte counters: FETCH_SIZE
+    and WRITE_SIZE read for this copy, against the bytes it must move, give
+    the factors applied to the kernel's own counter readings."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copy probe: {reps} copies of {mib} MiB (each reads {mib} MiB and writes {mib} MiB)")
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +408,8 @@ def main(argv=None):
                     help='fixed batched parameters as JSON (e.g. \'{"min_queue_cells": 24}\'); skips the autotuner')
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a device copy of MIB MiB --steps times (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the pair path has no cross-GPU "
@@ -398,6 +417,8 @@ def main(argv=None):
               file=sys.stderr)
         return 2
 
+    if args.copy_probe:
+        return copy_probe(args.copy_probe, args.steps)
     if args.workload == 5:
         return serve_bench(args)
     if args.workload == 6:

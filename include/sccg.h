@@ -138,7 +138,9 @@ int sccg_set_params(sccg_ctx* ctx, const sccg_params* params);
 int sccg_get_params(const sccg_ctx* ctx, sccg_params* out);
 
 /* Pre-size the scratch so that later calls up to these sizes allocate
- * nothing (needed before capturing calls into a HIP graph). */
+ * nothing (needed before capturing calls into a HIP graph).  Growing the
+ * scratch frees the old buffers, so it also drops the context's captured
+ * batched graph, which is captured again on the next call. */
 int sccg_reserve(sccg_ctx* ctx, int64_t max_polys_a, int64_t max_polys_b, int64_t max_pairs);
 
 /* Per pair k: out_inter[k] = |A[pair_a[k]] ∩ B[pair_b[k]]| and
@@ -218,9 +220,15 @@ int sccg_relate_pairs(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, i
 int sccg_host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n_pairs, const int32_t* pair_a,
                          const int32_t* pair_b, int64_t* out_inter, int64_t* out_union, int n_threads);
 
-/* Check every ring of P: at least 4 vertices and every edge axis-aligned.
- * Writes the smallest bad polygon index, or -1, to *out_first_bad (device
- * int64).  Asynchronous; read the value after sccg_sync. */
+/* Check the input form the method assumes (Section 3.1 and Figure 3: a
+ * segmented object's boundary follows pixel sides, so a polygon has integer
+ * vertices and only horizontal and vertical edges): every ring of P has at
+ * least 4 vertices and every edge, the closing one included, is axis-aligned
+ * (a repeated vertex, i.e. an edge of length 0, passes).  Simplicity and the
+ * absence of holes are not checked.  Writes the smallest bad polygon index,
+ * or -1, to *out_first_bad (device int64, caller-owned).  Asynchronous on the
+ * context's stream; read the value after sccg_sync.  SCCG_E_ARG for a NULL
+ * context, polygon set or output. */
 int sccg_validate_polys(sccg_ctx* ctx, const sccg_polys* P, int64_t* out_first_bad);
 
 /* Wait for the context's stream; return SCCG_E_RANGE / SCCG_E_DEVICE if the
@@ -260,6 +268,11 @@ int sccg_get_timing(sccg_ctx* ctx, double* out_ms, int64_t* out_launches);
 
 /* Message of the last error on this context ("" if none). */
 const char* sccg_last_error(const sccg_ctx* ctx);
+
+/* Number of BATCHED sccg_area_pairs calls on this context that ran as a
+ * replay of its captured HIP graph (on a non-null stream, without
+ * SCCG_F_NO_GRAPH and with timing off); -1 for a NULL context. */
+int64_t sccg_graph_launches(const sccg_ctx* ctx);
 
 /* ------------------------------------------------------------ serving ---- */
 /* A server answers a stream of jobs, each one cross-comparison of two

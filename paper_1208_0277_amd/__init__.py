@@ -50,6 +50,7 @@ SCCG_J_INCLUDE_ZERO = 1
 EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
            "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
            "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version",
+           "sccg_graph_launches",
            "sccg_join_sets", "sccg_relate_pairs", "sccg_host_area_pairs", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
            "sccg_server_clock", "sccg_server_last_error", "sccg_server_destroy")
 
@@ -146,6 +147,7 @@ def load_library(path: str = LIB_PATH):
         "sccg_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "sccg_last_error": ([P], ctypes.c_char_p),
         "sccg_version": ([], ctypes.c_char_p),
+        "sccg_graph_launches": ([P], ctypes.c_int64),
         "sccg_join_sets": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, ctypes.c_int32,
                             i64, P, P, P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "sccg_relate_pairs": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P],
@@ -268,6 +270,10 @@ class Context:
         if n < 0:
             self._rc(n)
         return dict(zip(STAT_KEYS, (int(v) for v in out[:n])))
+
+    def graph_launches(self) -> int:
+        """BATCHED calls of this context that replayed its captured HIP graph."""
+        return int(self.lib.sccg_graph_launches(self.h))
 
     def set_timing(self, enable: bool):
         self._rc(self.lib.sccg_set_timing(self.h, 1 if enable else 0))

@@ -38,12 +38,14 @@ struct sccg_ctx {
   BatchState* st = nullptr;
   unsigned long long* queue = nullptr;
   int64_t queue_slots = 0;  // allocated n_queues * queue_cap
+  int32_t queue_nq = 0, queue_per = 0;  // the layout the queue slots were last cleared for
   unsigned long long* plain_stats = nullptr;
   int stats_on = 0;
   uint32_t last_mode = 0;
   // graph cache for the batched sequence
   hipGraphExec_t gexec = nullptr;
   std::string gkey;
+  int64_t graph_launches = 0;  // batched calls that ran as a replay of the captured graph
   // filter-stage scratch
   int4* j_bbox = nullptr;
   int4* j_grid = nullptr;
@@ -130,6 +132,14 @@ int resolve_params(sccg_ctx* c, const sccg_params* in, sccg_params* out) {
   return SCCG_OK;
 }
 
+// The captured graph holds the scratch pointers as kernel arguments: it is
+// dropped whenever scratch it may use is freed or reallocated.
+void drop_graph(sccg_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->gkey.clear();
+}
+
 template <typename T>
 int grow(sccg_ctx* c, T** ptr, int64_t n, const char* what) {
   if (*ptr) (void)hipFree(*ptr);
@@ -163,6 +173,7 @@ int ensure_polys(sccg_ctx* c, int which, int64_t n) {
 int ensure_pairs(sccg_ctx* c, int64_t n) {
   if (n <= c->cap_pairs) return SCCG_OK;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   int64_t want = n + n / 4 + 1024;
   int r;
   if ((r = grow(c, &c->cls, want, "pair classes")) || (r = grow(c, &c->rec, want, "pair records")) ||
@@ -188,17 +199,27 @@ int need(sccg_ctx* c, T** ptr, int64_t& cap, int64_t n, const char* what) {
 
 int ensure_queue(sccg_ctx* c) {
   const int64_t want = (int64_t)c->p.n_queues * c->p.queue_cap;
-  if (c->queue && c->queue_slots == want) return SCCG_OK;
+  // The reset kernel of a call clears the slots the previous call used,
+  // found from that call's head and tail counters in that call's layout, so
+  // the slots are cleared here whenever the layout changes.
+  if (c->queue && c->queue_slots == want && c->queue_nq == c->p.n_queues && c->queue_per == c->p.queue_cap)
+    return SCCG_OK;
   (void)hipStreamSynchronize(c->stream);
-  int r = grow(c, &c->queue, want, "task queue");
-  if (r) {
-    c->queue_slots = 0;
-    return r;
+  drop_graph(c);
+  if (!c->queue || c->queue_slots != want) {
+    int r = grow(c, &c->queue, want, "task queue");
+    if (r) {
+      c->queue_slots = 0;
+      return r;
+    }
+    c->queue_slots = want;
   }
-  c->queue_slots = want;
   // fresh slots must read as empty; the counters must not claim old slots
-  HIP_TRY(c, hipMemset(c->queue, 0, sizeof(unsigned long long) * (size_t)want));
-  HIP_TRY(c, hipMemset(c->st, 0, sizeof(BatchState)));
+  HIP_TRY(c, hipMemsetAsync(c->queue, 0, sizeof(unsigned long long) * (size_t)want, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->st, 0, sizeof(BatchState), c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->queue_nq = c->p.n_queues;
+  c->queue_per = c->p.queue_cap;
   return SCCG_OK;
 }
 
@@ -215,12 +236,6 @@ int timing_events(sccg_ctx* c, hipEvent_t* start, hipEvent_t* stop) {
   *stop = c->ev[c->ev_used * 2 + 1];
   c->ev_used += 1;
   return SCCG_OK;
-}
-
-void drop_graph(sccg_ctx* c) {
-  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-  c->gexec = nullptr;
-  c->gkey.clear();
 }
 
 int check_polys(sccg_ctx* c, const sccg_polys* P, const char* name) {
@@ -500,6 +515,7 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
     c->gkey = key;
   }
   HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
+  c->graph_launches += 1;
   return SCCG_OK;
 }
 
@@ -630,6 +646,8 @@ int sccg_validate_polys(sccg_ctx* c, const sccg_polys* P, int64_t* out_first_bad
   if (e != hipSuccess) return hip_fail(c, e, "validate");
   return SCCG_OK;
 }
+
+int64_t sccg_graph_launches(const sccg_ctx* c) { return c ? c->graph_launches : -1; }
 
 int sccg_sync(sccg_ctx* c) {
   if (!c) return SCCG_E_ARG;

@@ -9,7 +9,7 @@ import oracle
 import paper_1208_0277_amd as sccg
 import sccg_gen
 from sccg_gen import Polys, concat
-from tests.gpu_util import assert_exact, device_workload, run
+from tests.gpu_util import assert_exact, device_workload, graph_context, run, run_graph
 from tests.shapes import (band_rects, band_ring, comb_pairs, limit_cases, random_bands, rect_ring, rects_area,
                           rects_inter, staircase, transform)
 
@@ -131,8 +131,9 @@ def test_config3_subset(ctx, wl3s, mode):
 
 def test_config3_full_size():
     """The whole 2,000,000-pair heavy-tailed mix in one persistent launch with
-    the parameters of the committed headline profile: every pair's counts
-    equal the oracle's (row-bucketed form, all host threads)."""
+    the parameters of the committed headline profile, through the captured
+    HIP graph: every pair's counts equal the oracle's (row-bucketed form, all
+    host threads)."""
     import json
     import os
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -140,9 +141,9 @@ def test_config3_full_size():
         params = json.load(f)["params"]
     wl = sccg_gen.pairs(3, 2_000_000)
     print(f"[gpu] generated {len(wl.pa)} pairs, params {params}", flush=True)
-    c = sccg.Context(0, **params)
+    c = graph_context(**params)
     try:
-        gI, gU = run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
+        gI, gU = run_graph(c, device_workload(wl.A, wl.B, wl.pa, wl.pb))
     finally:
         c.close()
     eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS, threads=min(os.cpu_count() or 1, 16))
@@ -152,28 +153,45 @@ def test_config3_full_size():
 @pytest.mark.parametrize("mode", MODES)
 def test_config2_full_size(ctx, mode):
     """The whole 200,000-pair uniform workload (the plain kernel's baseline
-    set) in both modes: every pair equals the oracle."""
+    set) in both modes: every pair equals the oracle.  BATCHED runs through
+    the captured graph, PLAIN on the null stream."""
     import os
     wl = sccg_gen.pairs(2, 200_000)
-    gI, gU = run(ctx, device_workload(wl.A, wl.B, wl.pa, wl.pb), mode)
+    dwl = device_workload(wl.A, wl.B, wl.pa, wl.pb)
+    if mode == sccg.SCCG_BATCHED:
+        c = graph_context()
+        try:
+            gI, gU = run_graph(c, dwl)
+        finally:
+            c.close()
+    else:
+        gI, gU = run(ctx, dwl, mode)
     eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS, threads=min(os.cpu_count() or 1, 16))
     assert_exact(gI, gU, eI, eU, f"uniform workload, 200,000 pairs, mode {mode}")
 
 
-def test_config4_full_size(ctx):
+def test_config4_full_size():
     """Workload 4 at its full size (64 tiles of 8192 x 8192, the grid-join
-    candidates in one launch): every pair and every tile's sums, J and J'
-    equal the oracle."""
+    candidates in one launch through the captured graph): every pair and
+    every tile's sums, J and J' equal the oracle."""
     import os
     import torch
     wl = sccg_gen.sets(n_tiles=64, tile_side=8192, cell=64)
     print(f"[gpu] generated {wl.n_pairs} pairs in {len(wl.set_off) - 1} tiles", flush=True)
-    I, U = ctx.area_pairs(*device_workload(wl.A, wl.B, wl.pa, wl.pb), mode=sccg.SCCG_BATCHED)
+    dwl = device_workload(wl.A, wl.B, wl.pa, wl.pb)
     so = torch.from_numpy(wl.set_off).cuda()
-    si, su, nn, j, jp = ctx.jaccard_sets(so, I, U)
-    ctx.sync()
+    c = graph_context()
+    try:
+        gI, gU = run_graph(c, dwl)
+        I, U = torch.from_numpy(gI).cuda(), torch.from_numpy(gU).cuda()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(c.stream):
+            si, su, nn, j, jp = c.jaccard_sets(so, I, U)
+        c.sync()
+    finally:
+        c.close()
     eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS, threads=min(os.cpu_count() or 1, 16))
-    assert_exact(I.cpu().numpy(), U.cpu().numpy(), eI, eU, "set workload, 64 tiles")
+    assert_exact(gI, gU, eI, eU, "set workload, 64 tiles")
     osi, osu, onn, oj, ojp = oracle.jaccard_sets(wl.set_off, eI, eU)
     assert np.array_equal(si.cpu().numpy(), osi) and np.array_equal(su.cpu().numpy(), osu)
     assert np.array_equal(nn.cpu().numpy(), onn)
@@ -212,11 +230,49 @@ BATCH_TUNINGS = [
 
 @pytest.mark.parametrize("params", BATCH_TUNINGS, ids=[str(p) for p in BATCH_TUNINGS])
 def test_batched_tuning_invariance(wl3s, params):
+    """Every tuning of BATCHED mode gives the oracle's counts, through the
+    captured graph (eager launches with SCCG_F_NO_GRAPH)."""
     wl, eI, eU = wl3s
-    c = sccg.Context(0, **params)
-    gI, gU = run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
-    c.close()
+    c = graph_context(**params)
+    try:
+        graph = not (params.get("flags", 0) & sccg.SCCG_F_NO_GRAPH)
+        gI, gU = run_graph(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), expect_graph=graph)
+        if not graph:
+            assert c.graph_launches() == 0
+    finally:
+        c.close()
     assert_exact(gI, gU, eI, eU, f"batched {params}")
+
+
+def test_reserve_after_capture_recaptures(wl3s):
+    """Growing the scratch after a graph was captured frees the buffers the
+    graph's kernels point at: the next call must capture again and still
+    equal the oracle.  Changing the queue layout (same slot total, other
+    split between queues) must not leave stale task words behind."""
+    wl, eI, eU = wl3s
+    import torch
+    sel = np.arange(0, wl.n_pairs, 3)
+    dwl = device_workload(wl.A, wl.B, wl.pa[sel], wl.pb[sel])
+    # the same output tensors every time, so that only the scratch changes
+    out = (torch.empty(len(sel), dtype=torch.int64, device="cuda"),
+           torch.empty(len(sel), dtype=torch.int64, device="cuda"))
+    c = graph_context(heavy_verts=1, min_queue_cells=1, n_queues=2, queue_cap=4096)
+    try:
+        gI, gU = run_graph(c, dwl, out=out)
+        assert_exact(gI, gU, eI[sel], eU[sel], "first captured call")
+        c.reserve(wl.A.n, wl.B.n, 40 * len(sel))  # reallocates the pair scratch
+        gI, gU = run_graph(c, dwl, out=out)
+        assert_exact(gI, gU, eI[sel], eU[sel], "after reserve")
+        gI, gU = run_graph(c, dwl, out=out)
+        assert_exact(gI, gU, eI[sel], eU[sel], "replay after reserve")
+        c.set_params(heavy_verts=1, min_queue_cells=1, n_queues=4, queue_cap=2048)
+        gI, gU = run_graph(c, dwl, out=out)
+        assert_exact(gI, gU, eI[sel], eU[sel], "after a queue layout change")
+        c.set_params(heavy_verts=1, min_queue_cells=1, n_queues=2, queue_cap=4096)
+        gI, gU = run_graph(c, dwl, out=out)
+        assert_exact(gI, gU, eI[sel], eU[sel], "after the layout changed back")
+    finally:
+        c.close()
 
 
 @pytest.mark.parametrize("mode", MODES)
