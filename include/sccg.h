@@ -56,9 +56,10 @@ extern "C" {
 #define SCCG_E_STATE -7  /* call not allowed in the context's current state */
 
 /* ------------------------------------------------------------- modes ---- */
-/* PLAIN: Algorithm 1 as printed: one pair per workgroup, a shared box stack,
- * one sub-box per thread tested against every edge, one pixel per thread at
- * the leaves tested against every edge. */
+/* PLAIN: the direct GPU form of Section 3.3's method (the paper's Algorithm
+ * 1): one pair per workgroup, a stack of live sampling boxes in LDS, one
+ * sub-box per thread placed by Lemma 1 against every edge, one pixel per
+ * thread at the leaves tested against every edge. */
 #define SCCG_PLAIN 0u
 /* BATCHED: one persistent launch over all pairs with a device task queue
  * that spreads the hovering sampling boxes of large pairs over workgroups;

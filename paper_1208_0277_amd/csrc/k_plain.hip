@@ -1,246 +1,264 @@
-// PLAIN mode: Algorithm 1 of the paper as printed, on gfx950.
+// PLAIN mode: the PixelBox method of Section 3.3 in its direct GPU form, one
+// polygon pair per workgroup, one sampling sub-box or one pixel per thread.
 //
-// One polygon pair per workgroup (grid-stride over pairs, Algorithm 1's
-// outer loop).  The pair box is pushed on a shared stack of sampling boxes
-// with a "continue" flag; each popped box is either pixelized (BOXSIZE < T:
-// every thread tests its pixels against every edge of both polygons with the
-// crossing rule) or split into one sub-box per thread (SUBSAMPBOX), each
-// thread classifies its sub-box against both polygons (BOXPOSITION, Lemma 1),
-// adds the size of sub-boxes inside both, and pushes its sub-box with the
-// continue flag above the popped entry, which is marked dead instead of being
-// overwritten (Section 3.3).  Shared-memory vertex staging with a static cap,
-// a split (structure-of-arrays) stack and an unrolled edge loop are the
-// implementation optimizations of Section 3.3.
-//
-// Differences from the printed listing, none of which changes a count:
-//   - the per-thread partial sums are reduced on the device (wave shuffles)
-//     instead of being copied to the host;
-//   - a second barrier after reading the popped entry, so that no thread can
-//     still be reading it when thread 0 marks it dead (the listing relies on a
-//     warp being the whole block);
-//   - the polygon areas come from the per-polygon prepass.
+// A workgroup takes pairs in a grid-stride loop.  For its pair it keeps, in
+// LDS, a stack of the boxes still to be decided ("live" boxes), starting with
+// the pair box MBR(p) ∩ MBR(q):
+//   - a live box of fewer than T pixels is pixelized (Section 3.1): its pixels
+//     are dealt out to the threads row by row, and each pixel centre is tested
+//     against both rings with the even-odd crossing rule;
+//   - a larger live box is cut into a gx x gy grid of sub-boxes, one per
+//     thread.  Each thread places its sub-box against both polygons by Lemma 1
+//     (inside, outside or hovering), counts its pixels at once if it lies
+//     inside both, drops it if it lies outside either, and otherwise keeps it.
+//     The kept sub-boxes are compacted onto the stack with a workgroup-wide
+//     count of the keep flags, so the stack only ever holds live boxes.
+// The pixels counted by all threads are summed on the device; the union comes
+// from the polygon areas of the per-polygon prepass, |p ∪ q| = |p| + |q| −
+// |p ∩ q| (Section 3.2).  Both rings are staged in LDS when they fit
+// lds_vertex_cap (Section 3.3's use of shared memory), else read from global
+// memory.
 #include <limits.h>
 
 #include "sccg_device.h"
 
 namespace sccg {
 
-enum : int { kOut = 0, kIn = 1, kHover = 2 };
+namespace {
 
-// Stack depth bound: ceil-splitting a side of 32767 by g until it reaches 1.
-__host__ __device__ inline int plain_levels(int g) {
-  int levels = 0;
-  for (int s = kMaxSide; s > 1; s = (s + g - 1) / g) ++levels;
-  return levels + 1;
+enum Place : int { kOutside = 0, kInside = 1, kHovering = 2 };
+
+// Depth bound of the stack: the longest side (at most kMaxSide) shrinks to
+// ceil(side / g) per split, g = the smaller grid side.
+__host__ __device__ inline int plain_depth(int g) {
+  int d = 1;
+  for (int side = kMaxSide; side > 1; side = (side + g - 1) / g) ++d;
+  return d;
 }
 
-__host__ __device__ inline int plain_stack_cap(int wg, int gx, int gy) {
-  return plain_levels(gx < gy ? gx : gy) * (wg + 1) + 2;
+// A split keeps at most wg sub-boxes, and only the newest split's sub-boxes
+// are split further, so every level of the depth bound holds at most wg boxes.
+__host__ __device__ inline int plain_stack_boxes(int wg, int g_min) { return plain_depth(g_min) * wg + 1; }
+
+// Crossing parity of the pixel centre (px + 1/2, py + 1/2) against ring R
+// (Section 3.1): the number of vertical edges at X > px whose span
+// [min y, max y) holds py, taken mod 2.  Every edge is the pair
+// (previous vertex, vertex), the first one closing the ring.
+__device__ __forceinline__ unsigned crossing_parity(const int2* R, int n, int px, int py) {
+  unsigned odd = 0;
+  if (n <= 0) return 0;  // a ring without edges covers nothing
+  int2 prev = R[n - 1];
+#pragma unroll 4
+  for (int i = 0; i < n; ++i) {
+    const int2 cur = R[i];
+    const bool spans = (prev.y <= py) != (cur.y <= py);  // false for a horizontal edge
+    odd ^= (unsigned)(spans && cur.x > px);
+    prev = cur;
+  }
+  return odd;
 }
+
+// Lemma 1 (open-interior reading): the box [x0, x1) x [y0, y1) hovers R when
+// an edge of R meets the box's open interior; otherwise the box lies wholly
+// inside or wholly outside, and the crossing parity of its first pixel says
+// which (a box's geometric centre can fall on a grid line, a pixel centre
+// never does).
+__device__ __forceinline__ Place place_box(const int2* R, int n, int x0, int y0, int x1, int y1) {
+  bool meets = false;
+  unsigned odd = 0;
+  if (n <= 0) return kOutside;
+  int2 prev = R[n - 1];
+#pragma unroll 4
+  for (int i = 0; i < n; ++i) {
+    const int2 cur = R[i];
+    if (prev.x == cur.x) {
+      const int lo = min(prev.y, cur.y), hi = max(prev.y, cur.y);
+      meets |= x0 < cur.x && cur.x < x1 && lo < y1 && y0 < hi;
+      odd ^= (unsigned)(cur.x > x0 && lo <= y0 && y0 < hi);
+    } else {
+      const int lo = min(prev.x, cur.x), hi = max(prev.x, cur.x);
+      meets |= y0 < cur.y && cur.y < y1 && lo < x1 && x0 < hi;
+    }
+    prev = cur;
+  }
+  return meets ? kHovering : (odd ? kInside : kOutside);
+}
+
+// Live boxes, relative to the pair-box origin (sides <= 32767 fit int16).
+struct BoxStack {
+  int16_t* x0;
+  int16_t* y0;
+  int16_t* x1;
+  int16_t* y1;
+};
+
+}  // namespace
 
 int plain_lds_bytes(int wg_size, int lds_vertex_cap) {
-  // gx*gy == wg_size with min side >= 4 in every accepted configuration; size
-  // the stack for the worst (min side 4)
-  const int cap = plain_stack_cap(wg_size, 4, 4);
-  return lds_vertex_cap * 8 + cap * 9 + 64 + 16 * 8;
-}
-
-// Even-odd crossing count of the +x ray from the centre of pixel (px, py):
-// a vertical edge at X > px whose y-span [lo, hi) holds py.  Horizontal edges
-// never satisfy the span test.
-__device__ __forceinline__ int pixel_in_poly(const int2* R, int n, int px, int py) {
-  int par = 0;
-  int2 v = R[0];
-#pragma unroll 4
-  for (int i = 1; i < n; ++i) {
-    const int2 w = R[i];
-    par ^= ((v.y <= py) != (w.y <= py)) & (v.x > px);
-    v = w;
-  }
-  const int2 w = R[0];
-  par ^= ((v.y <= py) != (w.y <= py)) & (v.x > px);
-  return par;
-}
-
-// Lemma 1 with the open-interior reading: a box hovers iff some edge meets
-// its open interior (an edge crossing its sides or a vertex inside it);
-// otherwise all its pixels share the position of its first pixel.
-__device__ __forceinline__ int box_position(const int2* R, int n, int x0, int y0, int x1, int y1) {
-  bool hover = false;
-  int par = 0;
-  auto edge = [&](int2 v, int2 w) {
-    if (v.x == w.x) {
-      const int X = v.x, lo = min(v.y, w.y), hi = max(v.y, w.y);
-      hover |= (x0 < X) & (X < x1) & (lo < y1) & (hi > y0);
-      par ^= (X > x0) & (lo <= y0) & (y0 < hi);
-    } else {
-      const int Y = v.y, lo = min(v.x, w.x), hi = max(v.x, w.x);
-      hover |= (y0 < Y) & (Y < y1) & (lo < x1) & (hi > x0);
-    }
-  };
-  int2 v = R[0];
-#pragma unroll 4
-  for (int i = 1; i < n; ++i) {
-    const int2 w = R[i];
-    edge(v, w);
-    v = w;
-  }
-  edge(v, R[0]);
-  return hover ? kHover : (par ? kIn : kOut);
+  // every accepted grid has both sides >= 4: size the stack for that worst case
+  const int boxes = plain_stack_boxes(wg_size, 4);
+  return lds_vertex_cap * 8 + boxes * 8 + 16 * 8 + 16;
 }
 
 template <int WG>
 __global__ void __launch_bounds__(WG) k_plain(PlainArgs a) {
+  constexpr int kWaves = WG / kWave;
   extern __shared__ __align__(16) unsigned char smem[];
   const int cap_v = a.lds_vertex_cap;
-  const int scap = plain_stack_cap(WG, a.gx, a.gy);
-  int2* verts = reinterpret_cast<int2*>(smem);
-  int16_t* sx0 = reinterpret_cast<int16_t*>(smem + (size_t)cap_v * 8);
-  int16_t* sy0 = sx0 + scap;
-  int16_t* sx1 = sy0 + scap;
-  int16_t* sy1 = sx1 + scap;
-  uint8_t* sc = reinterpret_cast<uint8_t*>(sy1 + scap);
-  unsigned long long* wred = reinterpret_cast<unsigned long long*>(
-      smem + (((size_t)cap_v * 8 + (size_t)scap * 9 + 15) & ~(size_t)15));
+  const int gx = a.gx, gy = a.gy;
+  const int boxes = plain_stack_boxes(WG, min(gx, gy));
+  int2* staged = reinterpret_cast<int2*>(smem);
+  BoxStack st;
+  st.x0 = reinterpret_cast<int16_t*>(smem + (size_t)cap_v * 8);
+  st.y0 = st.x0 + boxes;
+  st.x1 = st.y0 + boxes;
+  st.y1 = st.x1 + boxes;
+  // per-wave keep counts (compaction) and partial sums (final reduction)
+  unsigned long long* wave_word =
+      reinterpret_cast<unsigned long long*>(smem + (((size_t)cap_v * 8 + (size_t)boxes * 8 + 15) & ~(size_t)15));
 
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
   const int T = a.box_threshold;
-  const int gx = a.gx, gy = a.gy;
-  const int si = tid % gx, sj = tid / gx;  // this thread's sub-box in the split grid
+  const int gi = tid % gx, gj = tid / gx;  // this thread's cell of a split grid
 
-  for (int64_t i = blockIdx.x; i < a.n_pairs; i += gridDim.x) {
-    const int64_t ia = a.pa[i], ib = a.pb[i];
+  for (int64_t k = blockIdx.x; k < a.n_pairs; k += gridDim.x) {
+    const int64_t ia = a.pa[k], ib = a.pb[k];
     if (ia < 0 || ia >= a.A.n || ib < 0 || ib >= a.B.n) {
       if (tid == 0) {
         latch_error(a.err, kErrIndex);
-        a.inter[i] = 0;
-        a.uni[i] = 0;
+        a.inter[k] = 0;
+        a.uni[k] = 0;
       }
       continue;
     }
-    const Meta mp = load_meta(a.metaA, ia), mq = load_meta(a.metaB, ib);
-    const int64_t ap = a.areaA[ia], aq = a.areaB[ib];
-    const Meta bx = pair_box(mp, mq);
-    if (bx.x0 >= bx.x1 || bx.y0 >= bx.y1) {
+    const Meta box = pair_box(load_meta(a.metaA, ia), load_meta(a.metaB, ib));
+    const int64_t area_sum = a.areaA[ia] + a.areaB[ib];
+    if (box.x0 >= box.x1 || box.y0 >= box.y1) {  // the MBRs do not overlap
       if (tid == 0) {
-        a.inter[i] = 0;
-        a.uni[i] = ap + aq;
+        a.inter[k] = 0;
+        a.uni[k] = area_sum;
       }
       continue;
     }
-    if (side_u(bx.x0, bx.x1) > (uint32_t)kMaxSide || side_u(bx.y0, bx.y1) > (uint32_t)kMaxSide) {
+    if (side_u(box.x0, box.x1) > (uint32_t)kMaxSide || side_u(box.y0, box.y1) > (uint32_t)kMaxSide) {
       if (tid == 0) {
         latch_error(a.err, kErrSide);
-        a.inter[i] = 0;
-        a.uni[i] = 0;
+        a.inter[k] = 0;
+        a.uni[k] = 0;
       }
       continue;
     }
     const int64_t op = a.A.off[ia], oq = a.B.off[ib];
     const int np = (int)(a.A.off[ia + 1] - op), nq = (int)(a.B.off[ib + 1] - oq);
-    const int2* P;
-    const int2* Q;
+    const int2* P = a.A.xy + op;
+    const int2* Q = a.B.xy + oq;
     if (np + nq <= cap_v) {
-      for (int k = tid; k < np; k += WG) verts[k] = a.A.xy[op + k];
-      for (int k = tid; k < nq; k += WG) verts[np + k] = a.B.xy[oq + k];
-      P = verts;
-      Q = verts + np;
-    } else {
-      P = a.A.xy + op;
-      Q = a.B.xy + oq;
+      for (int v = tid; v < np; v += WG) staged[v] = P[v];
+      for (int v = tid; v < nq; v += WG) staged[np + v] = Q[v];
+      P = staged;
+      Q = staged + np;
     }
-    // the stack holds boxes relative to the pair box origin
-    const int ox = bx.x0, oy = bx.y0;
+    const int ox = box.x0, oy = box.y0;
     if (tid == 0) {
-      sx0[0] = 0;
-      sy0[0] = 0;
-      sx1[0] = (int16_t)(bx.x1 - ox);
-      sy1[0] = (int16_t)(bx.y1 - oy);
-      sc[0] = 1;
+      st.x0[0] = 0;
+      st.y0[0] = 0;
+      st.x1[0] = (int16_t)(box.x1 - ox);
+      st.y1[0] = (int16_t)(box.y1 - oy);
     }
-    unsigned long long acc = 0, tests = 0, nleaf = 0, nsplit = 0, edge_tests = 0, box_tests = 0;
-    int top = 1;
-    bool overflow = false;
-    while (top > 0) {
-      top -= 1;
-      __syncthreads();
-      const int bx0 = sx0[top], by0 = sy0[top], bx1 = sx1[top], by1 = sy1[top];
-      const int c = sc[top];
-      __syncthreads();
-      if (c == 0) continue;
+    unsigned long long inside = 0;  // pixels of p ∩ q this thread counted
+    unsigned long long n_pix = 0, n_leaf = 0, n_split = 0, n_pix_edges = 0, n_box_edges = 0;
+    int live = 1;  // boxes on the stack (the same in every thread)
+    bool too_deep = false;
+    while (live > 0) {
+      __syncthreads();  // the last pushes (and the staged rings) are visible
+      const int bx0 = st.x0[live - 1], by0 = st.y0[live - 1], bx1 = st.x1[live - 1], by1 = st.y1[live - 1];
+      __syncthreads();  // every thread has the box before its slot is reused
+      live -= 1;
       const int w = bx1 - bx0, h = by1 - by0;
-      const int size = w * h;
-      if (size < T) {
-        // PIXELINPOLY over the box's pixels, WG at a time
-        const int stepy = WG / w, stepx = WG % w;
-        int jx = tid % w, jy = tid / w;
-        for (int j = tid; j < size; j += WG) {
-          const int px = ox + bx0 + jx, py = oy + by0 + jy;
-          const int in_p = pixel_in_poly(P, np, px, py);
-          const int in_q = pixel_in_poly(Q, nq, px, py);
-          acc += (unsigned)(in_p & in_q);
-          jx += stepx;
-          jy += stepy;
-          if (jx >= w) {
-            jx -= w;
-            jy += 1;
+      const int pixels = w * h;
+      if (pixels < T) {
+        // pixelize: thread t takes pixels t, t + WG, ... in row-major order
+        const int dy = WG / w, dx = WG % w;
+        int px = tid % w, py = tid / w;
+        for (int t = tid; t < pixels; t += WG) {
+          const int X = ox + bx0 + px, Y = oy + by0 + py;
+          inside += crossing_parity(P, np, X, Y) & crossing_parity(Q, nq, X, Y);
+          px += dx;
+          py += dy;
+          if (px >= w) {
+            px -= w;
+            py += 1;
           }
         }
-        tests += 2ull * (unsigned)size;
-        edge_tests += (unsigned long long)size * (unsigned)(np + nq);
-        nleaf += 1;
-      } else {
-        // SUBSAMPBOX: cut lines at x0 + floor(k*w/gx), y0 + floor(k*h/gy)
-        const int cx0 = bx0 + (si * w) / gx, cx1 = bx0 + ((si + 1) * w) / gx;
-        const int cy0 = by0 + (sj * h) / gy, cy1 = by0 + ((sj + 1) * h) / gy;
-        int cnext = 0;
-        if (cx0 < cx1 && cy0 < cy1) {
-          const int p1 = box_position(P, np, ox + cx0, oy + cy0, ox + cx1, oy + cy1);
-          const int p2 = box_position(Q, nq, ox + cx0, oy + cy0, ox + cx1, oy + cy1);
-          // BOXCONTINUE / BOXCONTRIBUTE
-          cnext = (p1 != kOut) & (p2 != kOut) & !((p1 == kIn) & (p2 == kIn));
-          const int t = (p1 == kIn) & (p2 == kIn);
-          acc += (unsigned long long)((1 - cnext) * t) * (unsigned)((cx1 - cx0) * (cy1 - cy0));
-          box_tests += (unsigned)(np + nq);
-        }
-        if (top + 1 + WG > scap) {
-          overflow = true;  // cannot happen for sides <= 32767; kept as a guard
-          break;
-        }
-        sx0[top + 1 + tid] = (int16_t)cx0;
-        sy0[top + 1 + tid] = (int16_t)cy0;
-        sx1[top + 1 + tid] = (int16_t)cx1;
-        sy1[top + 1 + tid] = (int16_t)cy1;
-        sc[top + 1 + tid] = (uint8_t)cnext;
-        if (tid == 0) sc[top] = 0;
-        top += 1 + WG;
-        nsplit += 1;
+        n_pix += 2ull * (unsigned)pixels;
+        n_pix_edges += (unsigned long long)pixels * (unsigned)(np + nq);
+        n_leaf += 1;
+        continue;
       }
-    }
-    // on-device reduction of the per-thread partial intersections
-    unsigned long long s = wave_sum_u64(acc);
-    if (WG > kWave) {
-      if ((tid & (kWave - 1)) == 0) wred[tid / kWave] = s;
+      // split: cell (gi, gj) spans [bx0 + floor(gi w / gx), bx0 + floor((gi + 1) w / gx)), likewise in y
+      const int cx0 = bx0 + gi * w / gx, cx1 = bx0 + (gi + 1) * w / gx;
+      const int cy0 = by0 + gj * h / gy, cy1 = by0 + (gj + 1) * h / gy;
+      bool keep = false;
+      if (cx0 < cx1 && cy0 < cy1) {
+        const Place in_p = place_box(P, np, ox + cx0, oy + cy0, ox + cx1, oy + cy1);
+        const Place in_q = place_box(Q, nq, ox + cx0, oy + cy0, ox + cx1, oy + cy1);
+        if (in_p == kInside && in_q == kInside)
+          inside += (unsigned long long)((cx1 - cx0) * (cy1 - cy0));
+        else
+          keep = in_p != kOutside && in_q != kOutside;
+        n_box_edges += (unsigned)(np + nq);
+      }
+      // compaction of the kept cells onto the stack, in thread order
+      const uint64_t kept = ballot(keep);
+      if (lane == 0) wave_word[wave] = (unsigned long long)__popcll(kept);
       __syncthreads();
-      if (tid == 0)
-        for (int k = 1; k < WG / kWave; ++k) s += wred[k];
+      int below = 0, total = 0;
+#pragma unroll
+      for (int v = 0; v < kWaves; ++v) {
+        const int c = (int)wave_word[v];
+        below += v < wave ? c : 0;
+        total += c;
+      }
+      if (live + total > boxes) {  // cannot happen for sides <= 32767; a guard
+        too_deep = true;
+        break;
+      }
+      if (keep) {
+        const int slot = live + below + lanes_below(kept);
+        st.x0[slot] = (int16_t)cx0;
+        st.y0[slot] = (int16_t)cy0;
+        st.x1[slot] = (int16_t)cx1;
+        st.y1[slot] = (int16_t)cy1;
+      }
+      live += total;
+      n_split += 1;
+    }
+    // sum the threads' pixels: DPP within each wave, then across waves
+    __syncthreads();
+    unsigned long long sum = wave_sum_u64(inside);
+    if (kWaves > 1) {
+      if (lane == 0) wave_word[wave] = sum;
+      __syncthreads();
+      sum = 0;
+#pragma unroll
+      for (int v = 0; v < kWaves; ++v) sum += wave_word[v];
     }
     if (a.stats) {
-      const unsigned long long bt = wave_sum_u64(box_tests);
-      if ((tid & (kWave - 1)) == 0) atomicAdd(&a.stats[9], bt);
+      const unsigned long long be = wave_sum_u64(n_box_edges);
+      if (lane == 0) atomicAdd(&a.stats[9], be);
     }
     if (tid == 0) {
-      if (overflow) latch_error(a.err, kErrWatchdog);
-      a.inter[i] = (int64_t)s;
-      a.uni[i] = ap + aq - (int64_t)s;
+      if (too_deep) latch_error(a.err, kErrWatchdog);
+      a.inter[k] = (int64_t)sum;
+      a.uni[k] = area_sum - (int64_t)sum;
       if (a.stats) {
-        atomicAdd(&a.stats[0], tests);
-        atomicAdd(&a.stats[1], nleaf);
-        atomicAdd(&a.stats[2], nsplit);
-        atomicAdd(&a.stats[8], edge_tests);
+        atomicAdd(&a.stats[0], n_pix);
+        atomicAdd(&a.stats[1], n_leaf);
+        atomicAdd(&a.stats[2], n_split);
+        atomicAdd(&a.stats[8], n_pix_edges);
       }
     }
-    __syncthreads();
   }
 }
 
