@@ -375,6 +375,16 @@ const char* sccg_server_last_error(sccg_server* srv);
  * Results not yet polled are dropped. */
 int sccg_server_destroy(sccg_server* srv);
 
+/* Diagnostic: the device's sustained integer VALU rate, the peak against
+ * which the persistent kernel's work is measured.  Runs a kernel in which
+ * every lane of 8 waves per SIMD on every compute unit issues independent
+ * 32-bit integer adds and XORs (32 per loop trip, `iters` trips, 1..2^24),
+ * once untimed and once timed with HIP events on the context's stream, and
+ * waits for it.  *out_lane_ops_per_s = lane-operations per second of the
+ * timed launch, *out_ms its duration.  The nominal figure is 256 CUs x 64
+ * lanes x 2.4 GHz = 39.3e12. */
+int sccg_valu_peak(sccg_ctx* ctx, int32_t iters, double* out_lane_ops_per_s, double* out_ms);
+
 /* Library version string. */
 const char* sccg_version(void);
 

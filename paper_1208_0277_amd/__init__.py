@@ -50,7 +50,7 @@ SCCG_J_INCLUDE_ZERO = 1
 EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
            "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
            "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version",
-           "sccg_graph_launches",
+           "sccg_graph_launches", "sccg_valu_peak",
            "sccg_join_sets", "sccg_relate_pairs", "sccg_host_area_pairs", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
            "sccg_server_clock", "sccg_server_last_error", "sccg_server_destroy")
 
@@ -148,6 +148,8 @@ def load_library(path: str = LIB_PATH):
         "sccg_last_error": ([P], ctypes.c_char_p),
         "sccg_version": ([], ctypes.c_char_p),
         "sccg_graph_launches": ([P], ctypes.c_int64),
+        "sccg_valu_peak": ([P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+                           ctypes.c_int),
         "sccg_join_sets": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, ctypes.c_int32,
                             i64, P, P, P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "sccg_relate_pairs": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P],
@@ -270,6 +272,12 @@ class Context:
         if n < 0:
             self._rc(n)
         return dict(zip(STAT_KEYS, (int(v) for v in out[:n])))
+
+    def valu_peak(self, iters: int = 20000):
+        """(sustained integer VALU lane-operations per second, kernel ms)."""
+        rate, ms = ctypes.c_double(), ctypes.c_double()
+        self._rc(self.lib.sccg_valu_peak(self.h, iters, ctypes.byref(rate), ctypes.byref(ms)))
+        return float(rate.value), float(ms.value)
 
     def graph_launches(self) -> int:
         """BATCHED calls of this context that replayed its captured HIP graph."""

@@ -649,6 +649,30 @@ int sccg_validate_polys(sccg_ctx* c, const sccg_polys* P, int64_t* out_first_bad
 
 int64_t sccg_graph_launches(const sccg_ctx* c) { return c ? c->graph_launches : -1; }
 
+int sccg_valu_peak(sccg_ctx* c, int32_t iters, double* out_lane_ops_per_s, double* out_ms) {
+  if (!c) return SCCG_E_ARG;
+  if (iters < 1 || iters > (1 << 24)) return fail(c, SCCG_E_ARG, "iters outside [1, 2^24]");
+  if (!out_lane_ops_per_s || !out_ms) return fail(c, SCCG_E_ARG, "NULL output");
+  HIP_TRY(c, hipSetDevice(c->device));
+  int r;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((r = timing_events(c, &t0, &t1))) return r;
+  c->ev_used -= 1;  // the pair is borrowed, not counted as a timed launch
+  const int grid = c->cu_count * 8;  // 8 waves per SIMD
+  hipError_t e;
+  // one untimed launch brings the clocks up, then the timed one
+  if ((e = launch_valu_peak(grid, iters, c->plain_stats, c->stream)) != hipSuccess) return hip_fail(c, e, "valu peak");
+  HIP_TRY(c, hipEventRecord(t0, c->stream));
+  if ((e = launch_valu_peak(grid, iters, c->plain_stats, c->stream)) != hipSuccess) return hip_fail(c, e, "valu peak");
+  HIP_TRY(c, hipEventRecord(t1, c->stream));
+  HIP_TRY(c, hipEventSynchronize(t1));
+  float ms = 0.f;
+  HIP_TRY(c, hipEventElapsedTime(&ms, t0, t1));
+  *out_ms = ms;
+  *out_lane_ops_per_s = (double)grid * 256.0 * (double)iters * 32.0 / ((double)ms * 1e-3);
+  return SCCG_OK;
+}
+
 int sccg_sync(sccg_ctx* c) {
   if (!c) return SCCG_E_ARG;
   HIP_TRY(c, hipSetDevice(c->device));

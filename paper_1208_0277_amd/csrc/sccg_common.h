@@ -159,6 +159,10 @@ hipError_t launch_relate(const Polys& A, const Polys& B, const Meta* metaA, cons
                          const int64_t* areaB, int64_t n_pairs, const int32_t* pa, const int32_t* pb,
                          const int64_t* inter, uint32_t* out, uint32_t* err, hipStream_t s);
 
+// Diagnostics: 32 integer VALU operations per lane and loop trip, `iters`
+// trips, grid workgroups of 256 lanes.
+hipError_t launch_valu_peak(int grid, int iters, unsigned long long* sink, hipStream_t s);
+
 // The device error word of a context (read and cleared by the server, which
 // owns its context and runs on the context's stream).
 uint32_t* ctx_error_word(sccg_ctx* c);
