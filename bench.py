@@ -61,8 +61,12 @@ WORKLOADS = {
 #   leaf_boxes:           one leaf tile: per ring a 64-bit prefix XOR over the
 #                         64 column lanes (6 steps x 2 words), then the AND and
 #                         popcount of both masks -> (2 x 12 + 2) x 64
+#   leaf_vertex_updates:  one ring vertex XORed into its column slot by the
+#                         union tile's vertex form (each vertical edge's two
+#                         end points together stand for one edge update) -> 1
 ALGO_OPS = {
     "leaf_edge_updates": 2,
+    "leaf_vertex_updates": 1,
     "leaf_staging_edges": 12,
     "classify_edge_visits": 24,
     "ring_scan_vertices": 10,
@@ -122,10 +126,11 @@ def kernel_source_hash() -> str:
 PROFILE_STEMS = {3: "k_batch_run_heavy_tailed_2M", 4: "k_batch_run_set_level_64_tiles"}
 
 
-def profile_summary(workload: int):
-    """The committed counter summary of the persistent kernel on this
-    workload (profiles/<stem>.json), or None when it is missing or was taken
-    on another version of the kernel source."""
+def profile_summary(workload: int, params: dict):
+    """The committed counter summary of the batched kernels on this workload
+    (profiles/<stem>.json), or None when it is missing, was taken on another
+    version of the kernel source, or with other tuning parameters than the
+    timed run's."""
     stem = PROFILE_STEMS.get(workload)
     if stem is None:
         return None
@@ -139,18 +144,48 @@ def profile_summary(workload: int):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
+    if {k: int(v) for k, v in (d.get("params") or {}).items()} != {k: int(v) for k, v in params.items()}:
+        return None
     return d
 
 
+def union_box_areas(wl, sel):
+    """Pixels of the bounding box of MBR(p) and MBR(q) for the pairs `sel`:
+    the pixel centres the oracle classifies, against both polygons."""
+    lo = np.full((len(sel), 2), np.iinfo(np.int64).max)
+    hi = np.full((len(sel), 2), np.iinfo(np.int64).min)
+    for P, idx in ((wl.A, wl.pa[sel]), (wl.B, wl.pb[sel])):
+        starts, ends = P.off[idx], P.off[idx + 1]
+        lens = ends - starts
+        keep = lens > 0
+        if not keep.any():
+            continue
+        s0, ln = starts[keep], lens[keep]
+        first = np.concatenate([[0], np.cumsum(ln)[:-1]])
+        pts = np.repeat(s0 - first, ln) + np.arange(int(ln.sum()))
+        for d in (0, 1):
+            v = P.xy[pts, d].astype(np.int64)
+            lo[keep, d] = np.minimum(lo[keep, d], np.minimum.reduceat(v, first))
+            hi[keep, d] = np.maximum(hi[keep, d], np.maximum.reduceat(v, first))
+    w, h = hi[:, 0] - lo[:, 0], hi[:, 1] - lo[:, 1]
+    return np.where((w > 0) & (h > 0), w * h, 0)
+
+
 def cpu_baseline(wl, I_gpu, U_gpu, seconds: float, seed: int):
-    """The oracle (row-bucketed form, all host cores) on a bounded random
-    sample of the same pairs; also checks the GPU counts of that sample."""
+    """The oracle (row-bucketed form, all host threads up to 16) on a bounded
+    random sample of the same pairs; also checks the GPU counts of that
+    sample.  Rates are wall-clock rates of the whole thread pool.  A
+    pixel-centre test is one pixel of the bounding box of both MBRs
+    classified against one polygon (the oracle classifies every such pixel
+    against both).  The pure form (every edge per pixel) is timed beside the
+    row-bucketed one on the 1,000-pair small workload."""
     import oracle
+    import sccg_gen
     threads = min(os.cpu_count() or 1, 16)
     rng = np.random.default_rng(seed)
     order = rng.permutation(wl.n_pairs)
-    done, t_total, pos, exact = 0, 0.0, 0, True
-    chunk = 2000
+    done, t_total, pos, exact, tests = 0, 0.0, 0, True, 0
+    chunk = 20000
     while t_total < seconds and pos < wl.n_pairs:
         sel = np.sort(order[pos:pos + chunk])
         pos += chunk
@@ -158,13 +193,21 @@ def cpu_baseline(wl, I_gpu, U_gpu, seconds: float, seed: int):
         eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa[sel], wl.pb[sel], form=oracle.ROWS, threads=threads)
         t_total += time.perf_counter() - t
         done += len(sel)
+        tests += 2 * int(union_box_areas(wl, sel).sum())
         if not (np.array_equal(eI, I_gpu[sel]) and np.array_equal(eU, U_gpu[sel])):
             exact = False
-    # one core on a fixed 1% subset (every 100th pair)
+    # one thread on a fixed 1% subset (every 100th pair)
     sub = np.arange(0, wl.n_pairs, 100)
     t = time.perf_counter()
     oracle.area_pairs(wl.A, wl.B, wl.pa[sub], wl.pb[sub], form=oracle.ROWS, threads=1)
     one = len(sub) / (time.perf_counter() - t)
+    # both forms on the small workload (the pure form is the plain definition)
+    small = sccg_gen.pairs(1)
+    forms = {}
+    for name, form in (("pure", oracle.PURE), ("rows", oracle.ROWS)):
+        t = time.perf_counter()
+        oracle.area_pairs(small.A, small.B, small.pa, small.pb, form=form, threads=threads)
+        forms[name] = small.n_pairs / (time.perf_counter() - t)
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -173,15 +216,18 @@ def cpu_baseline(wl, I_gpu, U_gpu, seconds: float, seed: int):
         pass
     return {"value": done / t_total, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} pairs drawn uniformly (seed {seed}) from the same workload, row-bucketed "
-                      f"oracle form, {t_total:.1f} s of CPU time",
-            "one_core_pairs_per_s": one, "one_core_sample": f"every 100th pair ({len(sub)} pairs)",
+                      f"oracle form, {t_total:.2f} s wall time on {threads} threads",
+            "pixel_tests_per_s": tests / t_total, "wall_s": t_total,
+            "one_core_pairs_per_s": one, "one_core_sample": f"every 100th pair ({len(sub)} pairs), 1 thread",
+            "small_workload_pairs_per_s": forms,
             "nproc": os.cpu_count(), "cpu_model": model}, exact, done
 
 
-def serve_bench(args):
+def run_serving(rates, jobs, cpu_threads=0, cpu_max_pairs=0):
     """Continuous-batching server under Poisson arrivals; latency is submit
     to results on the host (the server's clock).  Every job is checked
-    against the oracle's counts of the corpus."""
+    against the oracle's counts of the corpus.  Returns (per-rate records,
+    all bit-exact, corpus pairs)."""
     import math
     import threading
 
@@ -191,7 +237,6 @@ def serve_bench(args):
     import paper_1208_0277_amd as sccg
     import sccg_gen
 
-    rates = [float(r) for r in args.rates.split(",")]
     corpus_n = 500_000
     t0 = time.perf_counter()
     wl = sccg_gen.pairs(2, corpus_n, seed=sccg_gen.BASE_SEED + 5)
@@ -203,7 +248,7 @@ def serve_bench(args):
     log(f"corpus: {corpus_n} pairs, {len(wl.A.xy) + len(wl.B.xy)} vertices (pinned), oracle counts in "
         f"{time.perf_counter() - t0:.1f} s")
     local = np.arange(5 * 10 ** 5, dtype=np.int32)
-    srv = sccg.Server(0, cpu_threads=args.cpu_threads, cpu_max_pairs=args.cpu_max_pairs)
+    srv = sccg.Server(0, cpu_threads=cpu_threads, cpu_max_pairs=cpu_max_pairs)
     rng = np.random.default_rng(sccg_gen.BASE_SEED + 5)
     out_rates, all_exact = [], True
     try:
@@ -212,7 +257,7 @@ def serve_bench(args):
         if not srv.poll(1, timeout=60.0):
             raise RuntimeError("warm-up job did not finish")
         for lam in rates:
-            n_jobs = args.jobs
+            n_jobs = jobs
             sizes = np.exp(rng.uniform(math.log(1e3), math.log(5e5), n_jobs)).astype(np.int64)
             starts = rng.integers(0, corpus_n - sizes + 1)
             arrive = np.cumsum(rng.exponential(1.0 / lam, n_jobs))  # rate inf: all at once
@@ -280,6 +325,12 @@ def serve_bench(args):
             out_rates.append(rec)
     finally:
         srv.close()
+    return out_rates, bool(all_exact), corpus_n
+
+
+def serve_bench(args):
+    rates = [float(r) for r in args.rates.split(",")]
+    out_rates, all_exact, corpus_n = run_serving(rates, args.jobs, args.cpu_threads, args.cpu_max_pairs)
     top = out_rates[-1]
     out = {
         "metric": METRIC, "value": top["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
@@ -295,11 +346,11 @@ def serve_bench(args):
     return 0
 
 
-def fig8_bench(args):
+def run_fig8(steps, warmup, autotuned=True):
     """Section 5.2's comparison (Figure 8) on a synthetic stand-in for its
     15,724-pair set: the same pairs with every coordinate multiplied by k.
     Every variant must give identical counts, and counts at k must be k^2
-    times those at 1."""
+    times those at 1.  Returns (rows of ms per call, all exact, pairs)."""
     import torch
 
     import paper_1208_0277_amd as sccg
@@ -332,19 +383,19 @@ def fig8_bench(args):
             ctx = sccg.Context(0, stream=stream, **fixed)
             with torch.cuda.stream(stream):
                 tuned = {}
-                if not args.no_autotune:
+                if autotuned:
                     tuned = autotune.tune(ctx, dA, dB, pa, pb, I, U, mode=mode, workload_key=f"fig8/{name}/{k}",
                                           steps=2, use_cache=False, log=lambda m: None)
                     ctx.set_params(**{**tuned, **fixed})
-                for _ in range(args.warmup):
+                for _ in range(warmup):
                     ctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=mode)
                 ctx.sync()
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                for _ in range(args.steps):
+                for _ in range(steps):
                     ctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=mode)
                 torch.cuda.synchronize()
-                ms = (time.perf_counter() - t) * 1e3 / args.steps
+                ms = (time.perf_counter() - t) * 1e3 / steps
                 ctx.sync()
             got = (I.cpu().numpy(), U.cpu().numpy())
             ctx.close()
@@ -357,12 +408,17 @@ def fig8_bench(args):
             ref1 = ref
         exact &= bool(np.array_equal(ref[0], k * k * ref1[0]) and np.array_equal(ref[1], k * k * ref1[1]))
         rows.append(rec)
+    return rows, bool(exact), base.n_pairs
+
+
+def fig8_bench(args):
+    rows, exact, n_pairs = run_fig8(args.steps, args.warmup, not args.no_autotune)
     top = rows[-1]["PixelBox_ms"]
     out = {
-        "metric": METRIC, "value": base.n_pairs / (top / 1e3), "unit": "pairs/s", "n_gpus": 1,
+        "metric": METRIC, "value": n_pairs / (top / 1e3), "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": top, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": WORKLOADS[6], "n_pairs": base.n_pairs, "value_at": "PixelBox, k = 5",
+        "config": {"workload": WORKLOADS[6], "n_pairs": n_pairs, "value_at": "PixelBox, k = 5",
                    "parallelism": "none (1 GPU)"},
         "figure8": rows, "bit_exact_across_variants_and_k2": bool(exact), "roofline": None, "cpu_baseline": None,
     }
@@ -408,6 +464,9 @@ def main(argv=None):
                     help='fixed batched parameters as JSON (e.g. \'{"min_queue_cells": 24}\'); skips the autotuner')
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="headline run: skip the serving summary")
+    ap.add_argument("--serve-jobs", type=int, default=240, help="headline run: jobs of the serving summary")
+    ap.add_argument("--no-fig8", action="store_true", help="headline run: skip the Figure 8 summary")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a device copy of MIB MiB --steps times (counter calibration)")
     args = ap.parse_args(argv)
@@ -533,16 +592,26 @@ def main(argv=None):
             log(f"plain: {p_ms:.1f} ms/step; batched/plain = {plain['batched_vs_plain']:.1f}x")
             pctx.close()
 
-    # roofline of the persistent kernel
+    # roofline of the batched kernels (the sweep and the persistent kernel,
+    # timed together with HIP events on their stream)
     algo_ops = sum(ALGO_OPS[k] * st.get(k, 0) for k in ALGO_OPS)
     achieved = algo_ops / (k_avg_ms / 1e3)
     algo_bytes = 8 * wl.n_pairs + 32 * wl.n_pairs + 8 * (len(wl.A.xy) + len(wl.B.xy)) + 16 * wl.n_pairs
-    prof = profile_summary(args.workload)
+    prof = profile_summary(args.workload, tuned)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_OPS, "traffic": prof["bytes_per_launch"] if prof else None,
-                "kernel": "k_batch_run", "kernel_ms": k_avg_ms, "algorithmic_ops_per_launch": algo_ops,
-                "algorithmic_bytes_per_launch": algo_bytes,
+                "kernel": "k_batch_sweep + k_batch_run", "kernel_ms": k_avg_ms,
+                "algorithmic_ops_per_launch": algo_ops, "algorithmic_bytes_per_launch": algo_bytes,
                 "hbm_frac_algorithmic": (algo_bytes / (k_avg_ms / 1e3)) / HBM_PEAK}
+    # the sustained integer VALU rate of this device (every lane of every
+    # compute unit issuing independent adds and XORs)
+    try:
+        sustained, _ = ctx.valu_peak()
+        roofline["peak_sustained"] = sustained / 1e12
+        roofline["frac_sustained"] = achieved / sustained
+        log(f"valu peak: {sustained / 1e12:.1f} T lane-ops/s sustained (nominal {VALU_PEAK_OPS / 1e12:.1f})")
+    except Exception as e:  # reported, not fatal
+        log(f"valu peak probe failed: {e}")
     if prof and prof.get("sq_insts_valu"):
         # counter view: every issued VALU instruction at 64 lanes, over the
         # profiled kernel time, against the same peak
@@ -550,7 +619,7 @@ def main(argv=None):
         roofline["profile"] = f"profiles/{PROFILE_STEMS[args.workload]}.md"
         # the further counter figures of the same summary, where it has them
         for key in ("valu_busy_pct", "valu_utilization_pct", "valu_int32_share", "lds_bank_conflict_pct",
-                    "valu_insts_per_pixel_test"):
+                    "valu_insts_per_pixel_test", "kernels_ms"):
             if key in prof:
                 roofline[key] = prof[key]
 
@@ -598,6 +667,23 @@ def main(argv=None):
                           "J_min": float(np.min(gsets[3])), "J_max": float(np.max(gsets[3])),
                           "Jprime_mean": float(np.mean(gsets[4]))})
 
+    # the serving loop and the Figure 8 comparison, summarized beside the
+    # headline (after its timed region)
+    extras = {}
+    if args.workload == 3 and not args.no_serving:
+        recs, sexact, corpus_n = run_serving([80.0], args.serve_jobs)
+        r = recs[0]
+        extras["serving"] = {"workload": WORKLOADS[5].replace("5, 20 and 80 jobs/s, 600 jobs per rate",
+                                                               f"80 jobs/s, {args.serve_jobs} jobs"),
+                             "rate_jobs_per_s": 80.0, "jobs": r["jobs"], "measured_jobs": r["measured_jobs"],
+                             "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "pairs_per_s": r["pairs_per_s"],
+                             "offered_pairs_per_s": r["offered_pairs_per_s"], "launches": r["launches"],
+                             "max_jobs_per_launch": r["max_jobs_per_launch"], "bit_exact": sexact}
+    if args.workload == 3 and not args.no_fig8:
+        rows, fexact, n8 = run_fig8(steps=5, warmup=1)
+        extras["figure8"] = {"workload": WORKLOADS[6], "pairs": n8, "ms_per_call": rows,
+                             "bit_exact_across_variants_and_k2": fexact}
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -624,6 +710,7 @@ def main(argv=None):
         "stats": st,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **extras,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

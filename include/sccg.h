@@ -61,15 +61,19 @@ extern "C" {
  * sub-box per thread placed by Lemma 1 against every edge, one pixel per
  * thread at the leaves tested against every edge. */
 #define SCCG_PLAIN 0u
-/* BATCHED: one persistent launch over all pairs with a device task queue
- * that spreads the hovering sampling boxes of large pairs over workgroups;
- * edge-parallel box classification and bit-sliced 64x64-pixel leaves, in
- * which every band edge XORs its row mask into one column slot and a prefix
- * XOR over the columns gives the crossing parities. */
+/* BATCHED: a sweep over all pairs, then one persistent launch over the
+ * pairs whose box is larger than a leaf tile, with a device task queue that
+ * spreads the hovering sampling boxes of large pairs over workgroups.
+ * Leaves are bit-sliced 64x64-pixel tiles: a prefix XOR over the columns of
+ * per-column row masks gives the crossing parities.  The sweep counts a
+ * pair whose MBR union fits one tile directly there (every ring vertex with
+ * one vertical edge XORs the rows at or above it into the column left of
+ * it); the persistent kernel classifies boxes edge-parallel and XORs each
+ * band edge's row mask into one column slot. */
 #define SCCG_BATCHED 1u
 
 /* sccg_params.flags (ablation switches; none changes any count) */
-#define SCCG_F_NO_LPT 0x1u          /* batched: no heavy-first ordering (and no box sharing)  */
+#define SCCG_F_NO_LPT 0x1u          /* batched: no heavy-first ordering (heavy pairs are swept) */
 #define SCCG_F_NO_KNOWN_INSIDE 0x2u /* batched: re-test a polygon already known to contain a box */
 #define SCCG_F_NO_SPLIT_QUEUE 0x4u  /* batched: a large pair's boxes stay with the wave that split it */
 #define SCCG_F_NO_GRAPH 0x8u        /* batched: launch the kernels directly, no HIP graph      */
@@ -251,15 +255,17 @@ int sccg_sync(sccg_ctx* ctx);
  *       PLAIN, sub-boxes x ring edges tested
  *   [10] ring edges read while staging leaf tiles (BATCHED)
  *   [11] covered pixels: sum of the non-empty pair-box areas (BATCHED)
- *   [12] vertices reduced for MBRs and areas inside the persistent kernel (BATCHED)
+ *   [12] vertices reduced for MBRs and areas by the sweep (BATCHED)
  *   [13] vertices reduced for union boxes only, of pairs counted on one leaf tile (BATCHED)
+ *   [14] leaf vertex updates: vertices XORed into a leaf slot by the union
+ *        tile's vertex form of the crossing test (BATCHED)
  * Writes min(n, 16) values to out; returns that count (or an error < 0). */
 int sccg_set_stats(sccg_ctx* ctx, int enable);
 int sccg_get_stats(sccg_ctx* ctx, int64_t* out, int n);
 
-/* Time the main kernel of every sccg_area_pairs call (the plain kernel, or
- * the persistent kernel of BATCHED mode) with HIP events recorded on the
- * context's stream around that one launch.  While timing is on, BATCHED mode
+/* Time the main kernels of every sccg_area_pairs call (the plain kernel, or
+ * BATCHED mode's sweep and persistent kernel, back to back) with HIP events
+ * recorded on the context's stream around them.  While timing is on, BATCHED mode
  * launches its kernels directly instead of through the HIP graph.
  * sccg_get_timing waits for the stream, returns the summed milliseconds and
  * the number of timed launches since the last sccg_get_timing (or since

@@ -60,7 +60,7 @@ SERVER_STAT_KEYS = ("jobs_submitted", "jobs_done", "launches", "pairs_done", "pe
 
 STAT_KEYS = ("leaf_pixel_tests", "leaf_boxes", "split_boxes", "queued_boxes", "kept_boxes", "small_pairs",
              "large_pairs", "empty_pairs", "leaf_edge_updates", "classify_edge_visits", "leaf_staging_edges",
-             "covered_pixels", "ring_scan_vertices", "union_tile_vertices")
+             "covered_pixels", "ring_scan_vertices", "union_tile_vertices", "leaf_vertex_updates")
 
 
 class SccgError(RuntimeError):

@@ -50,6 +50,7 @@
 //     yet written) is on a producer that writes right after reserving; it is
 //     bounded anyway and latches SCCG_E_DEVICE if the bound is hit.
 #include <limits.h>
+#include <stddef.h>
 
 #include <algorithm>
 
@@ -63,11 +64,9 @@ constexpr int kLeafSlots = 2 * kWave;  // per-wave leaf slots: one per column of
 constexpr int kBandCap = 512;           // per-wave band-edge list of one ring (p and q each)
 constexpr int kLocalCap = 256;          // per-wave stack of boxes to process inline
 constexpr uint32_t kSpinLimit = 1u << 22;
-// per-wave LDS: leaf slots, band-edge lists, the inline box stack, the
-// metadata of one chunk
-using ChunkMeta = PairRec;
-constexpr int kLdsPerWave =
-    kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8 + kWave * (int)sizeof(ChunkMeta) + kWave * 16;
+// per-wave LDS of the persistent kernel: leaf slots, band-edge lists, the
+// inline box stack
+constexpr int kLdsPerWave = kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8;
 constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
 constexpr int kSetupPerThread = 16;         // most pairs per thread of the setup pass
 
@@ -120,8 +119,6 @@ struct Ctx {
   uint64_t* slots;  // per-wave leaf slots, kLeafSlots entries
   uint32_t* band;   // per-wave band-edge lists: p at [0, kBandCap), q at [kBandCap, 2 kBandCap)
   uint64_t* local;  // per-wave inline stack, kLocalCap entries
-  ChunkMeta* meta;  // per-wave metadata of the pairs of one chunk
-  int64_t* res;     // per-wave (I, U) of the chunk's sweep pairs, written out when the chunk is done
   int lsp;          // inline stack depth (wave-uniform)
   int home;         // preferred queue
   int xcd;          // first claim stream (the workgroup's XCD under round-robin dispatch)
@@ -343,26 +340,6 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
 __device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv, int lane, Meta& m, int64_t& area) {
   RingRegs r;
   ring_extent(xy, o, nv, lane, r, m, area);
-}
-
-// Union box of two rings of at most 128 vertices each, both non-empty, from
-// their first two chunks (loaded here into rp and rq, which the leaf reuses):
-// four wave reductions over both rings at once.  Lanes past the end of a ring
-// stand at p's first vertex.
-__device__ __forceinline__ Meta union_extent(const int2* xa, int64_t oa, int np, const int2* xb, int64_t ob, int nq,
-                                             int lane, RingRegs& rp, RingRegs& rq, const Held& pre_p,
-                                             const Held& pre_q) {
-  int2 fp, fq;
-  load_ring2(xa, oa, np, lane, rp, fp, pre_p);
-  load_ring2(xb, ob, nq, lane, rq, fq, pre_q);
-  const int2 p0 = lane < np ? rp.v0 : fp, p1 = lane + kWave < np ? rp.v1 : fp;
-  const int2 q0 = lane < nq ? rq.v0 : fp, q1 = lane + kWave < nq ? rq.v1 : fp;
-  Meta u;
-  u.x0 = wave_min_i32(min(min(p0.x, p1.x), min(q0.x, q1.x)));
-  u.y0 = wave_min_i32(min(min(p0.y, p1.y), min(q0.y, q1.y)));
-  u.x1 = wave_max_i32(max(max(p0.x, p1.x), max(q0.x, q1.x)));
-  u.y1 = wave_max_i32(max(max(p0.y, p1.y), max(q0.y, q1.y)));
-  return u;
 }
 
 __device__ __forceinline__ bool coords_bad(const Meta& m, int64_t nv) {
@@ -1101,6 +1078,507 @@ __device__ __forceinline__ PairInfo heavy_info(const BatchArgs& a, int64_t hidx)
 #define SCCG_RUN_ATTR
 #endif
 
+// -------------------------------------------------------------------- sweep
+// First pass of a batched call: every pair the setup pass did not list as
+// heavy, one pair at a time per wave, a chunk of consecutive pairs per claim.
+// A pair whose two rings have at most kSweepRing vertices each is loaded
+// into registers, both rings as one stream of positions (p's vertices, then
+// q's); when the union of its MBRs fits one leaf tile it is counted there
+// at once (below Section 3.4's pixelization threshold, I and U directly).
+// Every other pair gets its MBRs and areas from its rings and is appended,
+// with its pair box, to the persistent kernel's list.
+constexpr int kSweepRing = 2 * kWave;                 // longest ring held in registers
+constexpr int kSweepWaves = 4;                        // waves per workgroup of the sweep
+// Occupancy target of the sweep (waves per SIMD), a build-time tuning knob.
+#ifndef SCCG_SWEEP_WAVES_PER_EU
+#define SCCG_SWEEP_WAVES_PER_EU 8
+#endif
+
+// the lanes named by a wave-uniform mask (the mask is the lane condition)
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// lanes [0, n) of a chunk, for any n
+__device__ __forceinline__ uint64_t lanes_lt(int n) {
+  return n <= 0 ? 0ull : (n >= kWave ? ~0ull : (1ull << n) - 1ull);
+}
+
+// Lane L < 32 gets lane L + 32's value (v_permlane32_swap).
+__device__ __forceinline__ uint32_t upper_half(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_permlane32_swap((int)v, (int)v, false, false)[1];
+}
+__device__ __forceinline__ uint64_t upper_half(uint64_t v) {
+  return ((uint64_t)upper_half((uint32_t)(v >> 32)) << 32) | upper_half((uint32_t)v);
+}
+
+// The value of the next lane (DPP wave shift left by one; lane 63 reads 0).
+__device__ __forceinline__ int next_lane_x(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xf, 0xf, false); }
+
+// A sweep pair in registers: each ring in up to two 64-vertex chunks, lane L
+// of chunk c holding vertex 64 c + L (lanes past the end hold the ring's last
+// vertex again: neutral for extents).
+constexpr int kRingChunks = kSweepRing / kWave;
+struct PairRegs {
+  int2 p[kRingChunks], q[kRingChunks];
+};
+
+__device__ __forceinline__ void ring_load(const int2* R, int nr, int lane, int2 (&d)[kRingChunks]) {
+#pragma unroll
+  for (int c = 0; c < kRingChunks; ++c)
+    if (c * kWave < nr) d[c] = R[min(c * kWave + lane, nr - 1)];
+}
+
+__device__ __forceinline__ void ring_move(int2 (&d)[kRingChunks], const int2 (&s)[kRingChunks], int nr) {
+#pragma unroll
+  for (int c = 0; c < kRingChunks; ++c)
+    if (c * kWave < nr) d[c] = s[c];
+}
+
+// lanes [0, k) for 0 <= k <= 63, and lanes [0, m) for 1 <= m <= 64
+__device__ __forceinline__ uint64_t lanes_below_k(int k) { return (1ull << k) - 1ull; }
+__device__ __forceinline__ uint64_t lanes_upto_m(int m) { return ~0ull >> (kWave - m); }
+
+// Scatter of one ring of a union tile (see union_counts): every vertex whose
+// two edges are not both vertical or both horizontal XORs the rows at or
+// above it into the slot of the rightmost column left of it.  `base`: the
+// ring's first slot.  Returns the vertices scattered.
+template <typename M, int W, int R>
+__device__ __forceinline__ uint32_t ring_scatter(M* slots, const int2 (&d)[kRingChunks], int nr, int x0, int y0,
+                                                 int lane, int base) {
+  if (nr <= 0) return 0;
+  const bool two = nr > kWave;
+  const int le = (nr - 1) & (kWave - 1);  // lane of the last vertex, in the last chunk
+  // b: the vertex's edge to its successor is vertical.  The successor is the
+  // next lane, the next chunk's first lane, and after the last vertex the
+  // first: that edge's bit is set from the two end points.
+  const int x_first = __builtin_amdgcn_readlane(d[0].x, 0);
+  const int x_last = __builtin_amdgcn_readlane(two ? d[1].x : d[0].x, le);
+  const uint64_t last = x_last == x_first ? 1ull : 0ull;
+  uint64_t b0, b1 = 0;
+  if (two) {
+    const int x64 = __builtin_amdgcn_readlane(d[1].x, 0);
+    b0 = ballot(d[0].x == __builtin_amdgcn_update_dpp(x64, d[0].x, 0x130, 0xf, 0xf, false));
+    b1 = (ballot(d[1].x == next_lane_x(d[1].x)) & lanes_below_k(le)) | (last << le);
+  } else {
+    b0 = (ballot(d[0].x == next_lane_x(d[0].x)) & lanes_below_k(le)) | (last << le);
+  }
+  // the vertex's two edges differ: b differs from the previous lane's (the
+  // ring's last edge before its first vertex)
+  const uint64_t c0 = (b0 ^ ((b0 << 1) | last)) & (two ? ~0ull : lanes_upto_m(nr));
+  uint32_t kept = 0;
+  {
+    const int dx = d[0].x - x0, ty = d[0].y - y0;
+    const uint64_t keep = c0 & ballot(dx > 0) & ballot(ty < R);
+    M* sp = slots + (base + W - dx);
+    if (lane_in(keep)) slot_xor(sp, 0, (M)(~(M)0 << ty));
+    kept += (uint32_t)__popcll(keep);
+  }
+  if (two) {
+    const uint64_t c1 = (b1 ^ ((b1 << 1) | (b0 >> 63))) & lanes_upto_m(nr - kWave);
+    const int dx = d[1].x - x0, ty = d[1].y - y0;
+    const uint64_t keep = c1 & ballot(dx > 0) & ballot(ty < R);
+    M* sp = slots + (base + W - dx);
+    if (lane_in(keep)) slot_xor(sp, 0, (M)(~(M)0 << ty));
+    kept += (uint32_t)__popcll(keep);
+  }
+  return kept;
+}
+
+// Counts of a pair whose MBR union [x0, x0 + W) x [y0, y0 + R) fits one leaf
+// tile, from its rings in registers, packed as I | U << 16.
+//
+// Pixel (x, y) is inside a ring iff an odd number of its vertical edges lie
+// right of x with a span holding row y (Section 3.1).  A vertical edge from
+// (X, ya) to (X, yb) holds row y iff exactly one of ya, yb is <= y, so its
+// term is the XOR of one term per end: "rows >= y_end, in the columns left of
+// X".  Summed over a ring, a vertex contributes its term once for each
+// vertical edge it bounds: once at a corner, twice (no effect) between two
+// vertical edges, never between two horizontal ones.  So every vertex whose
+// two edges are not both vertical or both horizontal XORs the mask of rows
+// >= y_v into the slot of the rightmost column left of x_v, and the prefix
+// XOR over the columns (lanes, in reverse order as in the other leaves)
+// gives every column's crossing parities.  Every vertex lies in the tile:
+// rows and columns past the union box come out outside, and nothing needs
+// clipping.  kHalves: W = 32, p's columns in lanes 0-31 and q's in lanes
+// 32-63, one scan; else W = 64 and one scan per ring.  M: 32- or 64-bit rows.
+template <bool kHalves, typename M>
+__device__ __forceinline__ uint32_t union_counts(Ctx& c, const PairRegs& r, int np, int nq, int x0, int y0) {
+  constexpr int W = kHalves ? 32 : kWave;
+  constexpr int R = (int)sizeof(M) * 8;
+  const int lane = c.lane;
+  M* slots = reinterpret_cast<M*>(c.slots);
+  slots[lane] = (M)0;
+  if (!kHalves) slots[kWave + lane] = (M)0;
+  wave_sync_lds();
+  uint32_t kept = ring_scatter<M, W, R>(slots, r.p, np, x0, y0, lane, 0);
+  kept += ring_scatter<M, W, R>(slots, r.q, nq, x0, y0, lane, W);
+  wave_sync_lds();
+  uint32_t t;
+  if (kHalves) {
+    const M m = wave_prefix_xor<true>(slots[lane]);
+    const M o = upper_half(m);
+    const uint32_t ni = lane < 32 ? (uint32_t)__popcll((uint64_t)(m & o)) : 0u;
+    const uint32_t nu = lane < 32 ? (uint32_t)__popcll((uint64_t)(m | o)) : 0u;
+    t = wave_sum_u32(ni | (nu << 16));
+  } else {
+    const M mp = wave_prefix_xor<false>(slots[lane]);
+    const M mq = wave_prefix_xor<false>(slots[kWave + lane]);
+    t = wave_sum_u32((uint32_t)__popcll((uint64_t)(mp & mq)) | ((uint32_t)__popcll((uint64_t)(mp | mq)) << 16));
+  }
+  wave_sync_lds();
+  stat_add(c, 14, (unsigned long long)kept);
+  return t;
+}
+
+// Scan and count of a union tile's 64-bit slots (see union_counts), packed as
+// I | U << 16.  kHalves: W = 32, p's columns in slots 0-31 and q's in 32-63;
+// else p's in 0-63 and q's in 64-127.  kRows64: rows 32-63 are in use
+// (else those bits are all zero: rows past the union box come out outside).
+template <bool kHalves, bool kRows64>
+__device__ __forceinline__ uint32_t union_tile_count(const uint64_t* slots, int lane) {
+  using M = typename std::conditional<kRows64, uint64_t, uint32_t>::type;
+  auto slot = [&](int k) -> M {
+    if (kRows64) return (M)slots[k];
+    return (M)reinterpret_cast<const uint32_t*>(slots)[2 * k];  // low word: rows 0-31
+  };
+  uint32_t ni, nu;
+  if (kHalves) {
+    const M m = wave_prefix_xor<true>(slot(lane));
+    const M o = upper_half(m);
+    ni = lane < 32 ? (uint32_t)__popcll((uint64_t)(m & o)) : 0u;
+    nu = lane < 32 ? (uint32_t)__popcll((uint64_t)(m | o)) : 0u;
+  } else {
+    const M mp = wave_prefix_xor<false>(slot(lane));
+    const M mq = wave_prefix_xor<false>(slot(kWave + lane));
+    ni = (uint32_t)__popcll((uint64_t)(mp & mq));
+    nu = (uint32_t)__popcll((uint64_t)(mp | mq));
+  }
+  return wave_sum_u32(ni | (nu << 16));
+}
+
+// One ring of at most 64 vertices (lane L: vertex L; lanes past the end hold
+// the last vertex again) scattered into a union tile's 64-bit slots from
+// `base` on (see union_counts).  Returns the vertices scattered.
+__device__ __forceinline__ uint32_t scatter_small_ring(uint64_t* slots, int2 v, int nr, int x0, int y0, int W, int base,
+                                                       int lane) {
+  if (nr <= 0) return 0;
+  const int le = nr - 1;
+  const uint64_t close = __builtin_amdgcn_readlane(v.x, le) == __builtin_amdgcn_readlane(v.x, 0) ? 1ull : 0ull;
+  // b: the vertex's edge to its successor is vertical (the last vertex's
+  // successor is the first)
+  const uint64_t b = (ballot(v.x == next_lane_x(v.x)) & lanes_below_k(le)) | (close << le);
+  // the vertex's two edges differ
+  const uint64_t cm = (b ^ ((b << 1) | close)) & lanes_upto_m(nr);
+  const int dx = v.x - x0, ty = v.y - y0;
+  const uint64_t keep = cm & ballot(dx > 0) & ballot(ty < kWave);
+  uint64_t* sp = slots + (base + W - dx);
+  if (lane_in(keep)) slot_xor(sp, 0, ~0ull << ty);
+  return (uint32_t)__popcll(keep);
+}
+
+// A pair whose rings have at most 64 vertices each, one chunk per ring in
+// registers: when the union of its MBRs fits one leaf tile (and every
+// coordinate is in range), its counts packed as I | U << 16 in t, and true.
+__device__ __forceinline__ bool union_small(Ctx& c, int2 vp, int np, int2 vq, int nq, uint32_t& t) {
+  const int lane = c.lane;
+  const int2 a = np > 0 ? vp : vq, b = nq > 0 ? vq : vp;  // an empty ring takes the other's vertices
+  const int x0 = wave_min_i32(min(a.x, b.x)), y0 = wave_min_i32(min(a.y, b.y));
+  const int x1 = wave_max_i32(max(a.x, b.x)), y1 = wave_max_i32(max(a.y, b.y));
+  if (!(x0 >= -kMaxCoord && y0 >= -kMaxCoord && x1 <= kMaxCoord && y1 <= kMaxCoord &&
+        side_u(x0, x1) <= (uint32_t)kTile && side_u(y0, y1) <= (uint32_t)kTile))
+    return false;
+  const int uw = x1 - x0, uh = y1 - y0;
+  const int W = uw <= 32 ? 32 : kWave;
+  uint64_t* slots = c.slots;
+  slots[lane] = fresh_zero<uint64_t>();
+  slots[kWave + lane] = fresh_zero<uint64_t>();
+  wave_sync_lds();
+  uint32_t kept = scatter_small_ring(slots, vp, np, x0, y0, W, 0, lane);
+  kept += scatter_small_ring(slots, vq, nq, x0, y0, W, W, lane);
+  wave_sync_lds();
+  if (W == 32)
+    t = uh <= 32 ? union_tile_count<true, false>(slots, lane) : union_tile_count<true, true>(slots, lane);
+  else
+    t = uh <= 32 ? union_tile_count<false, false>(slots, lane) : union_tile_count<false, true>(slots, lane);
+  wave_sync_lds();
+  if (c.a->stats_on) {
+    const int n = np + nq;
+    stat_add(c, 14, (unsigned long long)kept);
+    stat_add(c, 5, 1ull);
+    stat_add(c, 11, (unsigned long long)uw * uh);
+    stat_add(c, 13, (unsigned long long)n);
+    stat_add(c, 1, 1ull);
+    stat_add(c, 0, 2ull * (unsigned long long)uw * uh);
+    stat_add(c, 10, (unsigned long long)n);
+  }
+  return true;
+}
+
+// A pair held in registers: when the union of its MBRs fits one leaf tile
+// (and every coordinate is in range), its counts packed as I | U << 16 in t,
+// and true.
+__device__ __forceinline__ bool union_pair(Ctx& c, const PairRegs& r, int np, int nq, uint32_t& t) {
+  const int2 f = np > 0 ? r.p[0] : r.q[0];  // lanes of an empty ring take this vertex
+  int mnx = f.x, mny = f.y, mxx = f.x, mxy = f.y;
+  auto add = [&](int2 v) {
+    mnx = min(mnx, v.x);
+    mny = min(mny, v.y);
+    mxx = max(mxx, v.x);
+    mxy = max(mxy, v.y);
+  };
+  if (np > kWave) add(r.p[1]);
+  if (nq > 0) add(r.q[0]);
+  if (nq > kWave) add(r.q[1]);
+  const int x0 = wave_min_i32(mnx), y0 = wave_min_i32(mny);
+  const int x1 = wave_max_i32(mxx), y1 = wave_max_i32(mxy);
+  if (!(x0 >= -kMaxCoord && y0 >= -kMaxCoord && x1 <= kMaxCoord && y1 <= kMaxCoord &&
+        side_u(x0, x1) <= (uint32_t)kTile && side_u(y0, y1) <= (uint32_t)kTile))
+    return false;
+  const int uw = x1 - x0, uh = y1 - y0;
+  if (uw <= 32)
+    t = uh <= 32 ? union_counts<true, uint32_t>(c, r, np, nq, x0, y0)
+                 : union_counts<true, uint64_t>(c, r, np, nq, x0, y0);
+  else
+    t = uh <= 32 ? union_counts<false, uint32_t>(c, r, np, nq, x0, y0)
+                 : union_counts<false, uint64_t>(c, r, np, nq, x0, y0);
+  if (c.a->stats_on) {
+    const int n = np + nq;
+    stat_add(c, 5, 1ull);
+    stat_add(c, 11, (unsigned long long)uw * uh);
+    stat_add(c, 13, (unsigned long long)n);
+    stat_add(c, 1, 1ull);
+    stat_add(c, 0, 2ull * (unsigned long long)uw * uh);
+    stat_add(c, 10, (unsigned long long)n);
+  }
+  return true;
+}
+// Extent and |shoelace|/2 of a ring held in registers (Section 3.2's area
+// formula; one or two chunks, lanes past the end holding the last vertex
+// again).  Twice the signed area is summed modulo 2^64 and its magnitude
+// taken unsigned, which is exact while it stays within 2^63.  A ring with a
+// coordinate beyond 2^30 comes back empty, with area 0 and `bad` set.
+__device__ __forceinline__ void ring_meta_regs(const int2 (&d)[kRingChunks], int nr, int lane, Meta& m, int64_t& area,
+                                               bool& bad) {
+  m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+  area = 0;
+  bad = false;
+  if (nr <= 0) return;
+  const bool two = nr > kWave;
+  int mnx = d[0].x, mny = d[0].y, mxx = mnx, mxy = mny;
+  if (two) {
+    mnx = min(mnx, d[1].x);
+    mny = min(mny, d[1].y);
+    mxx = max(mxx, d[1].x);
+    mxy = max(mxy, d[1].y);
+  }
+  const Meta e{wave_min_i32(mnx), wave_min_i32(mny), wave_max_i32(mxx), wave_max_i32(mxy)};
+  if (e.x0 < -kMaxCoord || e.y0 < -kMaxCoord || e.x1 > kMaxCoord || e.y1 > kMaxCoord) {
+    bad = true;
+    return;
+  }
+  m = e;
+  // each vertex's successor: the next lane, the next chunk's first lane, and
+  // the first vertex after the last
+  const int le = (nr - 1) & (kWave - 1);
+  const int2 f = lane_value(d[0], 0);
+  uint64_t tw = 0;
+#pragma unroll
+  for (int c = 0; c < kRingChunks; ++c) {
+    if (c == 0 || two) {
+      const bool last_chunk = c == kRingChunks - 1 || !two;
+      const int2 nx = last_chunk ? f : lane_value(d[c + 1 < kRingChunks ? c + 1 : c], 0);
+      int sx = __builtin_amdgcn_update_dpp(nx.x, d[c].x, 0x130, 0xf, 0xf, false);
+      int sy = __builtin_amdgcn_update_dpp(nx.y, d[c].y, 0x130, 0xf, 0xf, false);
+      if (last_chunk && lane == le) {
+        sx = f.x;
+        sy = f.y;
+      }
+      if (!last_chunk || lane <= le)
+        tw += (uint64_t)((int64_t)d[c].x * sy) - (uint64_t)((int64_t)sx * d[c].y);
+    }
+  }
+  const uint64_t t = wave_sum_u64(tw);
+  area = (int64_t)(((int64_t)t < 0 ? 0 - t : t) / 2);
+}
+
+// A sweep pair held in registers that the union tile does not take: MBRs and
+// areas, then the pair box (the union box when the union is counted
+// directly).  Returns the pair's class: done (an empty box, or a box side
+// out of range: I and U are final), or small / large (the pair is to be
+// listed for the persistent kernel with `box`, I = 0 and U = |p| + |q|, or 0
+// when the union is counted directly, as the values its boxes add to).
+__device__ __forceinline__ uint8_t sweep_meta(Ctx& c, const PairRegs& r, int np, int nq, int64_t& I, int64_t& U,
+                                              Meta& box) {
+  const BatchArgs& a = *c.a;
+  Meta mp, mq;
+  int64_t ap, aq;
+  bool bp, bq;
+  ring_meta_regs(r.p, np, c.lane, mp, ap, bp);
+  ring_meta_regs(r.q, nq, c.lane, mq, aq, bq);
+  if (c.lane == 0 && (bp || bq)) latch_error(a.err, kErrCoord);
+  stat_add(c, 12, (unsigned long long)(np + nq));
+  const bool direct = direct_union(a);
+  box = direct ? union_box(mp, mq) : pair_box(mp, mq);
+  I = 0;
+  U = direct ? 0 : ap + aq;
+  if (box.x0 >= box.x1 || box.y0 >= box.y1) {
+    stat_add(c, 7, 1ull);  // empty pair box: nothing in common
+    return kClsDone;
+  }
+  const uint32_t bw = side_u(box.x0, box.x1), bh = side_u(box.y0, box.y1);
+  if (bw > (uint32_t)kMaxSide || bh > (uint32_t)kMaxSide) {
+    if (c.lane == 0) latch_error(a.err, kErrSide);
+    stat_add(c, 7, 1ull);
+    U = 0;
+    return kClsDone;
+  }
+  const bool small = bw <= (uint32_t)kTile && bh <= (uint32_t)kTile;
+  stat_add(c, small ? 5 : 6, 1ull);
+  stat_add(c, 11, (unsigned long long)bw * bh);
+  return small ? kClsSmall : kClsLarge;
+}
+
+// A sweep pair as the setup pass recorded it (wave-uniform), taken from the
+// chunk's records held one per lane.
+struct SweepRec {
+  int64_t op, oq;
+  int np, nq, cls;
+};
+struct ChunkRecs {
+  int op_lo, op_hi, oq_lo, oq_hi, np, nq, cls;
+};
+__device__ __forceinline__ SweepRec sweep_rec(const ChunkRecs& cr, int j) {
+  SweepRec s;
+  s.op = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(cr.op_hi, j) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane(cr.op_lo, j));
+  s.oq = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(cr.oq_hi, j) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane(cr.oq_lo, j));
+  s.np = __builtin_amdgcn_readlane(cr.np, j);
+  s.nq = __builtin_amdgcn_readlane(cr.nq, j);
+  s.cls = __builtin_amdgcn_readlane(cr.cls, j);
+  return s;
+}
+// a sweep pair (both rings of at most kSweepRing vertices) with vertices
+__device__ __forceinline__ bool in_regs(const SweepRec& s) { return s.cls == kClsSweep && s.np + s.nq > 0; }
+
+// Pair i = i0 + j of the chunk.  A pair counted on its union tile leaves
+// I | U << 16 in lane j of `packed` (written out with the chunk); any other
+// pair writes its counts (or, when it is listed for the persistent kernel,
+// the values its boxes add to) itself.
+__device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairRegs& r, int64_t i, int j,
+                                          bool union_ok, uint32_t& packed, uint64_t& wmask) {
+  if (s.cls != kClsSweep) return;  // listed by the setup pass, or a bad index
+  const BatchArgs& a = *c.a;
+  const int lane = c.lane;
+  uint32_t t;
+  if (s.np + s.nq > 0 && union_ok &&
+      (s.np <= kWave && s.nq <= kWave ? union_small(c, r.p[0], s.np, r.q[0], s.nq, t)
+                                      : union_pair(c, r, s.np, s.nq, t))) {
+    if (lane == j) packed = t;
+    wmask |= 1ull << j;
+    return;
+  }
+  int64_t I = 0, U = 0;
+  Meta box{0, 0, 0, 0};
+  uint8_t cls = kClsDone;
+  if (s.np + s.nq > 0)
+    cls = sweep_meta(c, r, s.np, s.nq, I, U, box);
+  else
+    stat_add(c, 7, 1ull);  // two empty rings
+  if (lane == 0) {
+    a.inter[i] = I;
+    a.uni[i] = U;
+    if (cls != kClsDone) {
+      const unsigned long long k = atomicAdd(&a.st->l_count.v, 1ull);
+      a.l_list[k] = (int32_t)i;
+      *reinterpret_cast<int4*>(a.hbox + k) = make_int4(box.x0, box.y0, box.x1, box.y1);
+      a.cls[i] = cls;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_waves_per_eu(SCCG_SWEEP_WAVES_PER_EU))) k_batch_sweep(BatchArgs args) {
+  __shared__ __align__(16) uint64_t sweep_slots[kSweepWaves * kLeafSlots];
+  Ctx c;
+  c.a = &args;
+  c.lane = lane_id();
+  c.slots = sweep_slots + (threadIdx.x / kWave) * kLeafSlots;
+  c.band = nullptr;
+  c.local = nullptr;
+  c.lsp = 0;
+  c.home = 0;
+  c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
+  const BatchArgs& a = args;
+  const int lane = c.lane;
+  const unsigned long long n_chunks = ((unsigned long long)a.n_pairs + a.chunk - 1) / a.chunk;
+  const bool union_ok = direct_union(a) || !(a.flags & SCCG_F_NO_UNION_TILE);
+  uint32_t s_empty = 0;  // claim streams found exhausted (wave-uniform)
+  for (;;) {
+    int64_t i0 = -1;
+    while (s_empty != 0xffu) {
+      const int st = next_stream(s_empty, c.xcd);
+      unsigned long long k = 0;
+      if (lane == 0) k = atomicAdd(&a.st->s_next[st].v, 1ull);
+      k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
+      const unsigned long long g = k * kStreams + st;
+      if (g >= n_chunks) {
+        s_empty = uniform_u(s_empty | (1u << st));
+        continue;
+      }
+      i0 = uniform64((int64_t)g * a.chunk);
+      break;
+    }
+    if (i0 < 0) break;
+    const int cnt = uniform((int)min((int64_t)a.chunk, a.n_pairs - i0));
+    // the chunk's records, one per lane (one coalesced load)
+    ChunkRecs cr{0, 0, 0, 0, 0, 0, kClsDone};
+    if (lane < cnt) {
+      const int4 h = *reinterpret_cast<const int4*>(a.rec + i0 + lane);
+      const int4 t = *(reinterpret_cast<const int4*>(a.rec + i0 + lane) + 1);
+      cr = ChunkRecs{h.x, h.y, h.z, h.w, t.x, t.y, t.z};
+    }
+    // lane j: I | U << 16 of pair i0 + j when it is counted on its union tile
+    uint32_t packed = 0;
+    uint64_t wmask = 0;
+    // the pair in hand (sc, rc) and the next one (sn, rn), whose loads are in
+    // flight while the pair in hand is processed
+    PairRegs rc, rn;
+    SweepRec sc = sweep_rec(cr, 0);
+    if (in_regs(sc)) {
+      ring_load(a.A.xy + sc.op, sc.np, lane, rc.p);
+      ring_load(a.B.xy + sc.oq, sc.nq, lane, rc.q);
+    }
+#pragma unroll 1
+    for (int j = 0; j < cnt; ++j) {
+      SweepRec sn{0, 0, 0, 0, kClsDone};
+      bool gn = false;
+      if (j + 1 < cnt) {
+        sn = sweep_rec(cr, j + 1);
+        gn = in_regs(sn);
+        if (gn) {
+          ring_load(a.A.xy + sn.op, sn.np, lane, rn.p);
+          ring_load(a.B.xy + sn.oq, sn.nq, lane, rn.q);
+        }
+      }
+      sweep_one(c, sc, rc, i0 + j, j, union_ok, packed, wmask);
+      sc = sn;
+      if (gn) {
+        ring_move(rc.p, rn.p, sn.np);
+        ring_move(rc.q, rn.q, sn.nq);
+      }
+    }
+    // the chunk's union-tile counts go out in one coalesced store per array
+    if (lane_in(wmask)) {
+      a.inter[i0 + lane] = (int64_t)(packed & 0xffffu);
+      a.uni[i0 + lane] = (int64_t)(packed >> 16);
+    }
+  }
+}
+
+// ----------------------------------------------------------- persistent run
+// Second pass: the listed pairs (heavy pairs from the setup pass, claimed
+// first, then the sweep's pairs whose box is larger than a leaf tile), each
+// with its box from the prepass or the sweep.  Waves claim, in this order:
+// boxes from their queue, listed pairs, boxes from any queue.
 __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wave = threadIdx.x / kWave;
@@ -1111,226 +1589,54 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   c.slots = reinterpret_cast<uint64_t*>(lds);
   c.band = reinterpret_cast<uint32_t*>(lds + kLeafSlots * 8);
   c.local = reinterpret_cast<uint64_t*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4);
-  c.meta = reinterpret_cast<ChunkMeta*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8);
-  c.res = reinterpret_cast<int64_t*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8 +
-                                     kWave * sizeof(ChunkMeta));
   c.lsp = 0;
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
   const BatchArgs& a = args;
-  const unsigned long long n_heavy = a.st->l_count.v;
-  // Boxes reach a queue only from splits of heavy pairs with at least
-  // min_cells_to_queue continuing cells (at most 64): otherwise no wave ever
-  // needs to look at the queues.
-  const bool queues_used = n_heavy > 0 && !(a.flags & SCCG_F_NO_SPLIT_QUEUE) && a.min_cells_to_queue <= kWave;
-  const unsigned long long n_chunks = ((unsigned long long)a.n_pairs + a.chunk - 1) / a.chunk;
-  uint32_t l_empty = 0, s_empty = 0;  // streams this wave found exhausted (wave-uniform)
-  int64_t ch_i0 = 0;                  // the sweep chunk in hand: pairs ch_i0 + [ch_j, ch_cnt)
-  int ch_cnt = 0, ch_j = 0;
-  int pf_j = -1;  // chunk index whose first 128 vertices per ring are in pf_vp, pf_vq
-  int2 pf_vp[2] = {make_int2(0, 0), make_int2(0, 0)}, pf_vq[2] = {make_int2(0, 0), make_int2(0, 0)};
-  int2 cur_vp[2] = {pf_vp[0], pf_vp[1]}, cur_vq[2] = {pf_vq[0], pf_vq[1]};
+  const unsigned long long n_list = a.st->l_count.v;
+  // Boxes reach a queue only from splits with at least min_cells_to_queue
+  // continuing cells (at most 64): otherwise no wave ever needs to look at
+  // the queues.
+  const bool queues_used = n_list > 0 && !(a.flags & SCCG_F_NO_SPLIT_QUEUE) && a.min_cells_to_queue <= kWave;
+  uint32_t l_empty = 0;  // streams of the list this wave found exhausted (wave-uniform)
   for (;;) {
-    // ------------------------------------------------ pick one piece of work
     PairInfo pi;
-    bool use_pf = false;  // cur_vp / cur_vq hold the pair's first 128 vertices per ring
-    uint64_t task = 0;    // large-path task word, 0 = go through the small-pair path first
-    bool shared = false;  // outputs are shared with other waves: add atomically
+    uint64_t task = 0;  // 0: a box that fits one leaf tile
     uint64_t w;
     bool have = false;
-    // the home queue first, but not between the pairs of a sweep chunk
-    if (queues_used && (ch_j >= ch_cnt || l_empty != 0xffu) && queue_claim(c, false, &w)) {
+    if (queues_used && queue_claim(c, false, &w)) {
       pi = heavy_info(a, task_decode(w).hidx);
       task = w;
-      shared = have = true;
+      have = true;
     }
-    // heavy pairs first: a largest-first order over the pairs with most vertices
     while (!have && l_empty != 0xffu) {
       const int st = next_stream(l_empty, c.xcd);
       unsigned long long k = 0;
       if (c.lane == 0) k = atomicAdd(&a.st->l_next[st].v, 1ull);
       k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
       const unsigned long long e = k * kStreams + st;
-      if (e >= n_heavy) {
+      if (e >= n_list) {
         l_empty = uniform_u(l_empty | (1u << st));
         continue;
       }
       pi = heavy_info(a, (int64_t)e);
       const uint8_t cls = a.cls[pi.pair];
       if (cls == kClsDone) continue;  // settled by the prepass
-      shared = have = true;
-      if (cls == kClsLarge) {
-        task = root_task(pi);
-        if (a.stats_on && c.lane == 0) {
-          atomicAdd(&a.st->stats[6], 1ull);
-          atomicAdd(&a.st->stats[11], (unsigned long long)(pi.box.x1 - pi.box.x0) * (pi.box.y1 - pi.box.y0));
-        }
-      }
-    }
-    // then the sweep over the other pairs, a chunk at a time
-    while (!have) {
-      if (ch_j >= ch_cnt) {
-        // the chunk in hand is done: its sweep pairs' counts go out in one
-        // coalesced store per array
-        if (ch_cnt > 0) {
-          wave_sync_lds();
-          if (c.lane < ch_cnt && c.meta[c.lane].cls == kClsSweep) {
-            a.inter[ch_i0 + c.lane] = c.res[2 * c.lane];
-            a.uni[ch_i0 + c.lane] = c.res[2 * c.lane + 1];
-          }
-          ch_cnt = ch_j = 0;
-          wave_sync_lds();
-        }
-        bool got = false;
-        while (!got && s_empty != 0xffu) {
-          const int st = next_stream(s_empty, c.xcd);
-          unsigned long long k = 0;
-          if (c.lane == 0) k = atomicAdd(&a.st->s_next[st].v, 1ull);
-          k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
-          const unsigned long long g = k * kStreams + st;
-          if (g >= n_chunks) {
-            s_empty = uniform_u(s_empty | (1u << st));
-            continue;
-          }
-          got = true;
-          pf_j = -1;
-          ch_i0 = uniform64((int64_t)g * a.chunk);
-          ch_cnt = uniform((int)min((int64_t)a.chunk, a.n_pairs - ch_i0));
-          ch_j = 0;
-          // one lane per pair of the chunk copies its setup record
-          wave_sync_lds();
-          if (c.lane < ch_cnt) c.meta[c.lane] = a.rec[ch_i0 + c.lane];
-          wave_sync_lds();
-        }
-        if (!got) break;
-      }
-      const ChunkMeta m = c.meta[ch_j];
-      const int j = ch_j;
-      ch_j = uniform(ch_j + 1);
-      if (uniform(m.cls) != kClsSweep) continue;
-      pi.pair = ch_i0 + j;
-      pi.hidx = -1;
-      pi.op = uniform64(m.op);
-      pi.np = uniform(m.np);
-      pi.oq = uniform64(m.oq);
-      pi.nq = uniform(m.nq);
       have = true;
-      // the first 128 vertices of both rings of this pair may already be in
-      // registers; start those of the next pair of the chunk
-      use_pf = uniform(pf_j) == j;
-      if (use_pf) {
-        cur_vp[0] = pf_vp[0];
-        cur_vp[1] = pf_vp[1];
-        cur_vq[0] = pf_vq[0];
-        cur_vq[1] = pf_vq[1];
-      }
-      pf_j = -1;
-      if (ch_j < ch_cnt) {
-        const ChunkMeta m2 = c.meta[ch_j];
-        if (uniform(m2.cls) == kClsSweep) {
-          const int64_t op2 = uniform64(m2.op), oq2 = uniform64(m2.oq);
-          const int np2 = uniform(m2.np), nq2 = uniform(m2.nq);
-          pf_vp[0] = c.lane < np2 ? a.A.xy[op2 + c.lane] : make_int2(0, 0);
-          pf_vq[0] = c.lane < nq2 ? a.B.xy[oq2 + c.lane] : make_int2(0, 0);
-          pf_vp[1] = c.lane + kWave < np2 ? a.A.xy[op2 + kWave + c.lane] : make_int2(0, 0);
-          pf_vq[1] = c.lane + kWave < nq2 ? a.B.xy[oq2 + kWave + c.lane] : make_int2(0, 0);
-          pf_j = ch_j;
-        }
-      }
+      if (cls == kClsLarge) task = root_task(pi);
     }
     // nothing of its own left: help with every queue, then stop
     if (!have) {
       if (!queues_used || !queue_claim(c, true, &w)) break;
       pi = heavy_info(a, task_decode(w).hidx);
       task = w;
-      shared = have = true;
     }
-
-    // ------------------------------------------------------ small-pair path
-    int64_t I = 0;
-    bool union_tile = false;  // I holds direct counts: intersection low, union high
-    bool in_regs = false;     // rp, rq hold the first two chunks of both rings
-    RingRegs rp, rq;
-    if (task == 0) {
-      const int np = uniform((int)pi.np), nq = uniform((int)pi.nq);
-      const bool try_union = !shared && !direct_union(a) && !(a.flags & SCCG_F_NO_UNION_TILE) && np > 0 &&
-                             nq > 0 && np <= 2 * kWave && nq <= 2 * kWave;
-      if (try_union) {
-        // both polygons inside one leaf tile: count I and U there directly
-        const Meta u = union_extent(a.A.xy, pi.op, np, a.B.xy, pi.oq, nq, c.lane, rp, rq,
-                                    Held{use_pf, cur_vp[0], cur_vp[1]}, Held{use_pf, cur_vq[0], cur_vq[1]});
-        in_regs = true;
-        if (u.x0 >= -kMaxCoord && u.y0 >= -kMaxCoord && u.x1 <= kMaxCoord && u.y1 <= kMaxCoord &&
-            u.x0 < u.x1 && u.y0 < u.y1 && side_u(u.x0, u.x1) <= (uint32_t)kTile &&
-            side_u(u.y0, u.y1) <= (uint32_t)kTile) {
-          const int uw = u.x1 - u.x0, uh = u.y1 - u.y0;
-          pi.box = u;
-          I = uh > 32 ? leaf_small<true>(c, pi, rp, rq, uw, uh, true) : leaf_small<false>(c, pi, rp, rq, uw, uh, true);
-          union_tile = true;
-          if (a.stats_on && c.lane == 0) {
-            atomicAdd(&a.st->stats[5], 1ull);
-            atomicAdd(&a.st->stats[11], (unsigned long long)uw * uh);
-            atomicAdd(&a.st->stats[13], (unsigned long long)(np + nq));
-          }
-        }
-      }
-    }
-    if (task == 0 && !union_tile) {
-      // MBRs and areas from the pair's own rings, then the pair box (the
-      // first 128 vertices of each ring may already be in registers)
-      Meta mp, mq;
-      int64_t ap, aq;
-      const Held hp{in_regs || use_pf, in_regs ? rp.v0 : cur_vp[0], in_regs ? rp.v1 : cur_vp[1]};
-      const Held hq{in_regs || use_pf, in_regs ? rq.v0 : cur_vq[0], in_regs ? rq.v1 : cur_vq[1]};
-      ring_extent(a.A.xy, pi.op, pi.np, c.lane, rp, mp, ap, hp);
-      ring_extent(a.B.xy, pi.oq, pi.nq, c.lane, rq, mq, aq, hq);
-      if (c.lane == 0 && (coords_bad(mp, pi.np) || coords_bad(mq, pi.nq))) latch_error(a.err, kErrCoord);
-      if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[12], (unsigned long long)(pi.np + pi.nq));
-      pi.area_sum = ap + aq;
-      pi.box = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
-      const int bw = (int)side_u(pi.box.x0, pi.box.x1), bh = (int)side_u(pi.box.y0, pi.box.y1);
-      if (pi.box.x0 >= pi.box.x1 || pi.box.y0 >= pi.box.y1) {
-        // empty pair box: nothing in common
-        if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
-      } else if (side_u(pi.box.x0, pi.box.x1) > (uint32_t)kMaxSide || side_u(pi.box.y0, pi.box.y1) > (uint32_t)kMaxSide) {
-        if (c.lane == 0) latch_error(a.err, kErrSide);
-        if (a.stats_on && c.lane == 0) atomicAdd(&a.st->stats[7], 1ull);
-        pi.area_sum = 0;
-      } else if (bw <= kTile && bh <= kTile) {
-        I = bh > 32 ? leaf_small<true>(c, pi, rp, rq, bw, bh, direct_union(a))
-                    : leaf_small<false>(c, pi, rp, rq, bw, bh, direct_union(a));
-        if (a.stats_on && c.lane == 0) {
-          atomicAdd(&a.st->stats[5], 1ull);
-          atomicAdd(&a.st->stats[11], (unsigned long long)bw * bh);
-        }
-      } else {
-        task = root_task(pi);
-        if (a.stats_on && c.lane == 0) {
-          atomicAdd(&a.st->stats[6], 1ull);
-          atomicAdd(&a.st->stats[11], (unsigned long long)bw * bh);
-        }
-      }
-    }
-    // --------------------------------------------------------- large path
-    if (task != 0) {
-      // the next pair's prefetched vertices are dropped: the large path
-      // needs the registers more than the next pair needs the head start
-      pf_j = -1;
-      pf_vp[0] = pf_vp[1] = pf_vq[0] = pf_vq[1] = make_int2(0, 0);
-      cur_vp[0] = cur_vp[1] = cur_vq[0] = cur_vq[1] = make_int2(0, 0);
-      I = (int64_t)run_large(c, pi, task);
-    }
-    if (c.lane == 0) {
-      if (shared) {
-        add_counts(a, pi.pair, (uint64_t)I);
-      } else {
-        // a sweep pair of the chunk in hand
-        const int j = (int)(pi.pair - ch_i0);
-        const bool packed = direct_union(a) || union_tile;
-        c.res[2 * j] = packed ? (I & 0xffffffffll) : I;
-        c.res[2 * j + 1] = packed ? ((I >> 32) & 0xffffffffll) : pi.area_sum - I;
-      }
-    }
+    uint64_t I;
+    if (task == 0)
+      I = leaf_count(c, pi, pi.box.x0, pi.box.y0, pi.box.x1 - pi.box.x0, pi.box.y1 - pi.box.y0, false, false);
+    else
+      I = run_large(c, pi, task);
+    if (c.lane == 0) add_counts(a, pi.pair, I);
   }
 }
 
@@ -1379,7 +1685,10 @@ __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a, int per) {
       r.np = (int32_t)(a.A.off[ia + 1] - r.op);
       r.oq = a.B.off[ib];
       r.nq = (int32_t)(a.B.off[ib + 1] - r.oq);
-      if (!(a.flags & SCCG_F_NO_LPT) && (int64_t)r.np + r.nq >= a.heavy_verts) {
+      // the sweep holds rings of at most kSweepRing vertices in registers:
+      // longer ones are listed, as are (largest first) the heaviest pairs
+      if (r.np > kSweepRing || r.nq > kSweepRing ||
+          (!(a.flags & SCCG_F_NO_LPT) && (int64_t)r.np + r.nq >= a.heavy_verts)) {
         hmask |= 1u << t;
         cls = kClsHeavy;
       }
@@ -1436,6 +1745,10 @@ __global__ void __launch_bounds__(256) k_batch_heavy_meta(BatchArgs a) {
       a.uni[i] = 0;
     } else {
       cls = (w <= kTile && h <= kTile) ? kClsSmall : kClsLarge;
+      if (a.stats_on) {
+        atomicAdd(&a.st->stats[cls == kClsSmall ? 5 : 6], 1ull);
+        atomicAdd(&a.st->stats[11], (unsigned long long)(w * h));
+      }
     }
     a.cls[i] = cls;
   }
@@ -1472,8 +1785,15 @@ int batch_occupancy(int waves_per_wg) {
   return n > 0 ? n : 1;
 }
 
-hipError_t launch_batch_run(const BatchArgs& a, int grid, int waves_per_wg, hipStream_t s) {
+int batch_sweep_occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep, kSweepWaves * kWave, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
+hipError_t launch_batch_run(const BatchArgs& a, int sweep_grid, int grid, int waves_per_wg, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_sweep, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
   const size_t lds = (size_t)waves_per_wg * batch_lds_bytes_per_wave();
   hipLaunchKernelGGL(k_batch_run, dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
   if (a.stats_on)

@@ -391,7 +391,7 @@ __global__ void k_zero_stats(unsigned long long* s) {
   if ((int)threadIdx.x < kNumStats) s[threadIdx.x] = 0;
 }
 
-static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int grid) {
+static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int grid) {
   hipError_t e;
   if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
   if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
@@ -401,7 +401,7 @@ static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int grid) {
     if (r) return r;
     HIP_TRY(c, hipEventRecord(t0, c->stream));
   }
-  if ((e = launch_batch_run(ba, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
+  if ((e = launch_batch_run(ba, sweep_grid, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
     return hip_fail(c, e, "batch run");
   if (c->timing_on) HIP_TRY(c, hipEventRecord(t1, c->stream));
   return SCCG_OK;
@@ -486,8 +486,9 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   ba.stats_on = c->stats_on;
   int grid = c->p.grid;
   if (grid == 0) grid = c->cu_count * batch_occupancy(c->p.waves_per_wg);
+  const int sweep_grid = c->cu_count * batch_sweep_occupancy();
   const bool use_graph = c->stream != nullptr && !(c->p.flags & SCCG_F_NO_GRAPH) && !c->timing_on;
-  if (!use_graph) return launch_batched(c, ba, grid);
+  if (!use_graph) return launch_batched(c, ba, sweep_grid, grid);
   // the graph is keyed on every launch argument
   char key[512];
   snprintf(key, sizeof(key), "%lld/%p/%p|%lld/%p/%p|%lld/%p/%p/%p/%p|%d/%d/%d/%d/%d/%d/%u/%d/%d",
@@ -499,7 +500,7 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
     drop_graph(c);
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    r = launch_batched(c, ba, grid);
+    r = launch_batched(c, ba, sweep_grid, grid);
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (r) {
       if (g) (void)hipGraphDestroy(g);

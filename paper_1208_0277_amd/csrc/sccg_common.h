@@ -23,7 +23,8 @@ enum : uint32_t {
 };
 
 // Pair classes of the batched path: done in a prepass, swept in index
-// order, or heavy (claimed first); heavy pairs are then marked by their box.
+// order, or heavy (listed for the persistent kernel, claimed first); listed
+// pairs are then marked by their box (small: one leaf tile; large: split).
 enum : uint8_t { kClsDone = 0, kClsSweep = 1, kClsHeavy = 2, kClsSmall = 3, kClsLarge = 4 };
 
 struct Polys {
@@ -94,7 +95,7 @@ struct BatchState {
 
 // Per-pair record written by the batched setup pass: ring offsets and
 // vertex counts of both polygons and the pair's class, so that the sweep
-// fetches a chunk of pairs with one coalesced 32-byte load per pair.
+// reads one 32-byte record per pair (through the scalar cache).
 struct PairRec {
   int64_t op, oq;
   int32_t np, nq;
@@ -126,9 +127,11 @@ struct BatchArgs {
 };
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s);
-hipError_t launch_batch_run(const BatchArgs& a, int grid, int waves_per_wg, hipStream_t s);
+// The sweep (sweep_grid workgroups) then the persistent kernel (grid).
+hipError_t launch_batch_run(const BatchArgs& a, int sweep_grid, int grid, int waves_per_wg, hipStream_t s);
 int batch_lds_bytes_per_wave();
 int batch_occupancy(int waves_per_wg);
+int batch_sweep_occupancy();
 
 // Set-level Jaccard.
 hipError_t launch_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter, const int64_t* uni,

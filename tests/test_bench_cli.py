@@ -21,16 +21,20 @@ def test_code_only_ignores_comments_and_layout():
     assert "// kept" in bench._code_only(a)
 
 
-def test_profile_summary_needs_the_same_kernel_source(monkeypatch):
+def test_profile_summary_needs_the_same_kernel_source_and_params(monkeypatch):
     stem = bench.PROFILE_STEMS[3]
     path = os.path.join(ROOT, "profiles", stem + ".json")
     with open(path) as f:
-        committed = json.load(f)["kernel_source_hash"]
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: committed)
-    d = bench.profile_summary(3)
-    assert d is not None and d["kernel"] == "k_batch_run" and d["bytes_per_launch"] > 0
+        committed = json.load(f)
+    params = committed["params"]
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: committed["kernel_source_hash"])
+    d = bench.profile_summary(3, params)
+    assert d is not None and d["bytes_per_launch"] > 0
+    # other tuning parameters than the timed run's: not used
+    other = dict(params, queue_chunk=int(params["queue_chunk"]) + 1)
+    assert bench.profile_summary(3, other) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.profile_summary(3) is None
+    assert bench.profile_summary(3, params) is None
 
 
 def test_algorithmic_weights_name_work_counters():

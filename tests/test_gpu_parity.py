@@ -324,6 +324,52 @@ def test_degenerate_rings(ctx, mode):
     assert gU.tolist() == [25, 25, 25, 50, 50, 50]
 
 
+def _redundant(ring, rng, n_extra):
+    """The same polygon with n_extra redundant vertices: edge midpoints
+    (collinear points on vertical or horizontal runs) and repeated vertices."""
+    r = [tuple(v) for v in ring]
+    for _ in range(n_extra):
+        k = int(rng.integers(0, len(r)))
+        a, b = r[k], r[(k + 1) % len(r)]
+        if rng.random() < 0.5 and abs(a[0] - b[0]) + abs(a[1] - b[1]) >= 2:
+            r.insert(k + 1, ((a[0] + b[0]) // 2, (a[1] + b[1]) // 2))
+        else:
+            r.insert(k + 1, a)
+    return np.array(r, np.int32)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_redundant_vertices(ctx, mode):
+    """Rings with collinear and repeated vertices (every vertex is then not a
+    corner), sized so that the extra vertices fall at 64-vertex chunk
+    boundaries of the sweep's registers (63, 64, 65, 127, 128, 129 vertices
+    and more): counts equal the oracle's and those of the clean rings."""
+    wl = sccg_gen.pairs(3, 3000)
+    rng = np.random.default_rng(17)
+    ra, rb, pa_clean, pb_clean = [], [], [], []
+    for i in range(wl.n_pairs):
+        a, b = wl.A.ring(wl.pa[i]), wl.B.ring(wl.pb[i])
+        if len(a) > 200 or len(b) > 200:
+            continue
+        ta = int(rng.choice([len(a) + 1, 63, 64, 65, 127, 128, 129, len(a) + 40]))
+        tb = int(rng.choice([len(b) + 1, 63, 64, 65, 127, 128, 129, len(b) + 40]))
+        ra.append(_redundant(a, rng, max(1, ta - len(a))))
+        rb.append(_redundant(b, rng, max(1, tb - len(b))))
+        pa_clean.append(wl.pa[i])
+        pb_clean.append(wl.pb[i])
+    A, B = concat(ra), concat(rb)
+    idx = np.arange(len(ra), dtype=np.int32)
+    eI, eU = oracle.area_pairs(A, B, idx, idx, form=oracle.ROWS)
+    cI, cU = oracle.area_pairs(wl.A, wl.B, np.array(pa_clean, np.int32), np.array(pb_clean, np.int32),
+                               form=oracle.ROWS)
+    assert np.array_equal(eI, cI) and np.array_equal(eU, cU)
+    if mode == sccg.SCCG_PLAIN:
+        idx = idx[:300]
+        eI, eU = eI[:300], eU[:300]
+    gI, gU = run(ctx, device_workload(A, B, idx, idx), mode)
+    assert_exact(gI, gU, eI, eU, f"redundant vertices mode {mode}")
+
+
 def _comb(width, height, base, tooth, gap):
     """A comb: `base` full rows, then teeth `tooth` px wide every
     tooth + gap px up to `height`: many vertical edges in every 64-row band."""
