@@ -61,12 +61,13 @@
 namespace sccg {
 
 constexpr int kLeafSlots = 2 * kWave;  // per-wave leaf slots: one per column of p and of q
-constexpr int kBandCap = 512;           // per-wave band-edge list of one ring (p and q each)
 constexpr int kLocalCap = 256;          // per-wave stack of boxes to process inline
 constexpr uint32_t kSpinLimit = 1u << 22;
-// per-wave LDS of the persistent kernel: leaf slots, band-edge lists, the
-// inline box stack
-constexpr int kLdsPerWave = kLeafSlots * 8 + 2 * kBandCap * 4 + kLocalCap * 8;
+// per-wave LDS of the persistent kernel: the slots of one band row of each
+// ring (a single tile's leaf slots are the first of them), the inline box
+// stack
+constexpr int kRowSlotsPerWave = 2 * kMaxGrid * kWave;
+constexpr int kLdsPerWave = kRowSlotsPerWave * 8 + kLocalCap * 8;
 constexpr unsigned long long kSkip = 1ull;  // slot abandoned by an overshooting consumer
 constexpr int kSetupPerThread = 16;         // most pairs per thread of the setup pass
 
@@ -116,8 +117,7 @@ __device__ __forceinline__ int clamp_to(int x, int lo, int hi) { return min(max(
 struct Ctx {
   const BatchArgs* a;
   int lane;
-  uint64_t* slots;  // per-wave leaf slots, kLeafSlots entries
-  uint32_t* band;   // per-wave band-edge lists: p at [0, kBandCap), q at [kBandCap, 2 kBandCap)
+  uint64_t* slots;  // per-wave leaf slots (kLeafSlots; in the persistent kernel, two band rows' worth)
   uint64_t* local;  // per-wave inline stack, kLocalCap entries
   int lsp;          // inline stack depth (wave-uniform)
   int home;         // preferred queue
@@ -557,163 +557,45 @@ __device__ __forceinline__ uint64_t leaf_count(Ctx& c, const PairInfo& pi, int t
   return pack_counts(n, nu, direct_union(a));
 }
 
-// Band rows.  When a split leaves several leaf tiles, each ring is read once
-// into compact lists of its band edges (4 bytes per edge: X relative to the
-// list's origin, and the span within the 64-row band), one list per band row,
-// and every tile of a row scatters from its row's list instead of reading
-// the ring again.  Record: dx (11 bits, capped at kBandMaxDx), lo (7 bits),
-// hi (7 bits).
-constexpr int kBandMaxDx = 2047;
-__device__ __forceinline__ uint32_t band_record(int dx, int lo, int hi) {
-  return (uint32_t)dx | ((uint32_t)lo << 11) | ((uint32_t)hi << 18);
-}
+// Row-wide leaves.  When a split leaves several leaf tiles, each band row of
+// it (up to kMaxGrid tiles) is pixelized at once: one slot array per ring
+// holds every column of the row, position Wpad - 1 - (column - bx0) for
+// Wpad = 64 x (tiles per row), so that a vertical edge at X toggles the
+// positions from Wpad - min(X - bx0, Wpad) up, with one atomic whatever its
+// distance.  Each ring is streamed once per band row (from L2: its pair's
+// rings were read moments before).  Inside each tile's block of 64 positions
+// a prefix XOR over the lanes gives the tile's columns their crossing
+// parities for the edges that end inside it; the blocks of the tiles to its
+// right add the XOR of all their slots, carried from block to block.
+constexpr int kRowSlots = kMaxGrid * kWave;  // slots of one ring's band row
 
-// Stage the band edges of one ring for the band rows `rows` (bit j: rows
-// [by0 + 64 j, by0 + 64 j + 64) of a split at most 8 tiles high) in one pass
-// over the ring.  The k-th row of `rows` has list[k * cap, (k + 1) * cap),
-// X relative to bx0, and its count in bits [8 j, 8 j + 8) of `counts`
-// (cap <= 255).  Returns the rows whose edges did not fit.
-__device__ __forceinline__ uint32_t stage_rows(Ctx& c, const int2* xy, int64_t o, int64_t nv, uint32_t rows, int cap,
-                                               int bx0, int by0, int by1, uint32_t* list, uint64_t& counts) {
-  counts = 0;
-  uint32_t bad = 0;
-  if (uniform((int)nv) <= 0) return 0;
-  RingStream rs(xy, o, uniform((int)nv), c.lane);
-#pragma unroll 1
-  do {
-    rs.ahead();
-    const int2 v = rs.cur, w = rs.succ();
-    const int dx = min(v.x, bx0 + kBandMaxDx) - bx0;
-    const int ylo = clamp_to(min(v.y, w.y), by0, by1) - by0, yhi = clamp_to(max(v.y, w.y), by0, by1) - by0;
-    const bool edge = rs.valid() && v.x == w.x && dx > 0 && ylo < yhi;
-    // the band rows met by this chunk's edges (64 consecutive vertices
-    // usually meet one or two): only those rows are tested
-    const uint32_t met = wave_or_u32(edge ? (2u << ((yhi - 1) >> 6)) - (1u << (ylo >> 6)) : 0u);
-#pragma unroll 1
-    for (uint32_t live = rows & ~bad & met; live; live &= live - 1) {
-      const int j = __ffs((int)live) - 1;
-      const int lo = max(ylo - kTile * j, 0), hi = min(yhi - kTile * j, kTile);
-      const bool keep = edge && lo < hi;
-      const uint64_t b = ballot(keep);
-      const int nk = __popcll(b);
-      const int cj = (int)((counts >> (8 * j)) & 0xffu);
-      if (cj + nk > cap) {
-        bad |= 1u << j;
-        continue;
-      }
-      const int seg = __popc(rows & ((1u << j) - 1u));
-      if (keep) list[seg * cap + cj + lanes_below(b)] = band_record(dx, lo, hi);
-      counts += (uint64_t)nk << (8 * j);
-    }
-  } while (rs.next());
-  stat_add(c, 10, (unsigned long long)nv * __popc(rows));
-  return bad;
-}
-
-// Stage the band edges of one ring that lie right of xs; returns the count,
-// or -1 if they do not fit in kBandCap.
-__device__ __forceinline__ int stage_band(Ctx& c, const int2* xy, int64_t o, int64_t nv, int xs, int ty0, int th,
-                                          uint32_t* list) {
-  const int lane = c.lane;
-  int cnt = 0;
-  if (uniform((int)nv) <= 0) return 0;
-  RingStream rs(xy, o, uniform((int)nv), lane);
-#pragma unroll 1
-  do {
-    rs.ahead();
-    const int2 v = rs.cur, w = rs.succ();
-    bool keep = false;
-    uint32_t rec = 0;
-    if (rs.valid() && v.x == w.x) {
-      const int lo = clamp_to(min(v.y, w.y), ty0, ty0 + th) - ty0;
-      const int hi = clamp_to(max(v.y, w.y), ty0, ty0 + th) - ty0;
-      const int dx = min(v.x, xs + kBandMaxDx) - xs;
-      if (lo < hi && dx > 0) {
-        keep = true;
-        rec = band_record(dx, lo, hi);
-      }
-    }
-    const uint64_t b = ballot(keep);
-    const int nk = __popcll(b);
-    if (cnt + nk > kBandCap) return -1;
-    if (keep) list[cnt + lanes_below(b)] = rec;
-    cnt += nk;
-  } while (rs.next());
-  stat_add(c, 10, (unsigned long long)nv);
-  return cnt;
-}
-
-// Scatter a staged band list into slots[base ..) for the tile whose left
-// side is `off` pixels right of the list's origin; edges right of the tile
-// go to *full.
-__device__ __forceinline__ void scatter_band(Ctx& c, const uint32_t* list, int n, int off, uint64_t* slots, int base,
-                                             uint64_t& full) {
-  const int lane = c.lane;
+// Scatter the vertical edges of one ring that meet rows [ry0, ry0 + th) into
+// a row's slots (wpad positions from bx0).
+__device__ __forceinline__ void scatter_row(Ctx& c, const int2* xy, int64_t o, int64_t nv, int bx0, int wpad, int ry0,
+                                            int th, uint64_t* slots) {
+  const int n = uniform((int)nv);
+  if (n <= 0) return;
   uint32_t kept = 0;
+  RingStream rs(xy, o, n, c.lane);
 #pragma unroll 1
-  for (int k0 = 0; k0 < n; k0 += kWave) {
-    const int k = k0 + lane;
-    const uint32_t rec = k < n ? list[k] : 0u;
-    const int rel = (int)(rec & 0x7ffu) - off;
-    const bool keep = k < n && rel > 0;
-    if (keep) {
-      const uint64_t rr = row_range((int)((rec >> 11) & 0x7fu), (int)((rec >> 18) & 0x7fu));
-      if (rel >= kWave)
-        full ^= rr;
-      else
-        slot_xor(slots, base + kWave - rel, rr);
-    }
+  do {
+    rs.ahead();
+    const int2 w = rs.succ();
+    int slot = 0;
+    uint64_t rr = 0;
+    const bool keep = rs.valid() && leaf_edge(rs.cur, w, bx0, ry0, th, wpad, slot, rr);
+    if (keep) slot_xor(slots, slot, rr);
     if (c.a->stats_on) kept += (uint32_t)__popcll(ballot(keep));
-  }
-  stat_add(c, 8, (unsigned long long)kept);
-}
-
-// Count of one tile of a band row from the staged lists (n < 0: the polygon
-// is known to contain the tile).
-__device__ __forceinline__ uint64_t leaf_from_band(Ctx& c, const uint32_t* lp, int np, const uint32_t* lq, int nq,
-                                                   int off, int tw, int th) {
-  const int lane = c.lane;
-  uint64_t* slots = c.slots;
-  slots[lane] = fresh_zero<uint64_t>();
-  slots[kWave + lane] = fresh_zero<uint64_t>();
-  wave_sync_lds();
-  uint64_t fp = 0, fq = 0;
-  if (np >= 0) scatter_band(c, lp, np, off, slots, 0, fp);
-  if (nq >= 0) scatter_band(c, lq, nq, off, slots, kWave, fq);
-  wave_sync_lds();
-  const uint64_t all = row_range(0, th);
-  const uint64_t mp = np < 0 ? all : wave_prefix_xor<false>(slots[lane]) ^ wave_xor64(fp);
-  const uint64_t mq = nq < 0 ? all : wave_prefix_xor<false>(slots[kWave + lane]) ^ wave_xor64(fq);
-  wave_sync_lds();
-  const bool in_tile = kWave - 1 - lane < tw;
-  const uint32_t n = in_tile ? (uint32_t)__popcll(mp & mq) : 0u;
-  const uint32_t nu = in_tile ? (uint32_t)__popcll(mp | mq) : 0u;
+  } while (rs.next());
   if (c.a->stats_on) {
-    stat_add(c, 1, 1ull);
-    stat_add(c, 0, (unsigned long long)tw * th * ((np < 0 ? 0 : 1) + (nq < 0 ? 0 : 1)));
-  }
-  return pack_counts(n, nu, direct_union(*c.a));
-}
-
-// The tiles of one band row from staged lists (n < 0: not staged, the ring is
-// known to contain every tile of the row); X of the lists relative to bx0.
-__device__ __forceinline__ void band_row_tiles(Ctx& c, const uint32_t* lp, int np, const uint32_t* lq, int nq,
-                                               uint32_t row, uint32_t kp_row, uint32_t kq_row, int bx0, int bx1,
-                                               int th, uint64_t& acc) {
-  for (uint32_t r = row; r; r &= r - 1) {
-    const int i = __ffs((int)r) - 1;
-    const int tx0 = bx0 + kTile * i, tw = min(kTile, bx1 - tx0);
-    const bool kp = (kp_row >> i) & 1u, kq = (kq_row >> i) & 1u;
-    acc += leaf_from_band(c, lp, kp ? -1 : np, lq, kq ? -1 : nq, tx0 - bx0, tw, th);
+    stat_add(c, 8, (unsigned long long)kept);
+    stat_add(c, 10, (unsigned long long)n);
   }
 }
 
 // The leaf tiles `cont` (bit 8j + i = tile (i, j) of side 64 from (bx0, by0))
 // of a split.  kin_p / kin_q: tiles known to lie inside p / q.  A lone tile
-// is scattered straight from the rings.  Otherwise each ring is staged in one
-// pass for every band row with a tile not known inside it, a list per row;
-// rows whose lists do not fit are staged again one at a time with the whole
-// list, and failing that their tiles are scattered from the rings.
+// is scattered straight from the rings; otherwise a band row at a time.
 __device__ __forceinline__ void leaf_rows(Ctx& c, const PairInfo& pi, int bx0, int by0, int bx1, int by1, int gy,
                                           uint64_t cont, uint64_t kin_p, uint64_t kin_q, uint64_t& acc) {
   const BatchArgs& a = *c.a;
@@ -724,61 +606,60 @@ __device__ __forceinline__ void leaf_rows(Ctx& c, const PairInfo& pi, int bx0, i
                       (kin_q >> t) & 1ull);
     return;
   }
-  uint32_t rows = 0, sp = 0, sq = 0;
+  const int lane = c.lane;
+  const bool direct = direct_union(a);
+  const int gx = uniform((bx1 - bx0 + kTile - 1) / kTile);
+  const int wpad = gx * kTile;
+  uint64_t* sp = c.slots;
+  uint64_t* sq = c.slots + kRowSlots;
+  uint32_t ni = 0, nu = 0;  // this lane's pixels counted, over every tile
+  unsigned long long n_leaf = 0, n_tests = 0;
+#pragma unroll 1
   for (int j = 0; j < gy; ++j) {
     const uint32_t row = (uint32_t)(cont >> (8 * j)) & 0xffu;
     if (!row) continue;
-    rows |= 1u << j;
-    if (((uint32_t)(kin_p >> (8 * j)) & row) != row) sp |= 1u << j;
-    if (((uint32_t)(kin_q >> (8 * j)) & row) != row) sq |= 1u << j;
-  }
-  const int cap_p = sp ? min(255, kBandCap / __popc(sp)) : 0;
-  const int cap_q = sq ? min(255, kBandCap / __popc(sq)) : 0;
-  uint64_t cnt_p = 0, cnt_q = 0;
-  const uint32_t bad_p = sp ? stage_rows(c, a.A.xy, pi.op, pi.np, sp, cap_p, bx0, by0, by1, c.band, cnt_p) : 0u;
-  const uint32_t bad_q =
-      sq ? stage_rows(c, a.B.xy, pi.oq, pi.nq, sq, cap_q, bx0, by0, by1, c.band + kBandCap, cnt_q) : 0u;
-  wave_sync_lds();
-  const uint32_t bad = bad_p | bad_q;
-  for (uint32_t r = rows & ~bad; r; r &= r - 1) {
-    const int j = __ffs((int)r) - 1;
-    const uint32_t row = (uint32_t)(cont >> (8 * j)) & 0xffu;
-    const int np = (sp >> j) & 1u ? (int)((cnt_p >> (8 * j)) & 0xffu) : -1;
-    const int nq = (sq >> j) & 1u ? (int)((cnt_q >> (8 * j)) & 0xffu) : -1;
-    const uint32_t* lp = c.band + __popc(sp & ((1u << j) - 1u)) * cap_p;
-    const uint32_t* lq = c.band + kBandCap + __popc(sq & ((1u << j) - 1u)) * cap_q;
-    band_row_tiles(c, lp, np, lq, nq, row, (uint32_t)(kin_p >> (8 * j)) & row, (uint32_t)(kin_q >> (8 * j)) & row,
-                   bx0, bx1, min(kTile, by1 - by0 - kTile * j), acc);
-  }
-  for (uint32_t r = bad; r; r &= r - 1) {
-    const int j = __ffs((int)r) - 1;
-    const uint32_t row = (uint32_t)(cont >> (8 * j)) & 0xffu;
     const uint32_t kp_row = (uint32_t)(kin_p >> (8 * j)) & row, kq_row = (uint32_t)(kin_q >> (8 * j)) & row;
-    const int ty0 = by0 + kTile * j, th = min(kTile, by1 - ty0);
-    // both lists are restaged: the whole of each list is overwritten
-    wave_sync_lds();
-    int np = -1, nq = -1;
-    bool staged = true;
-    if ((sp >> j) & 1u) {
-      np = stage_band(c, a.A.xy, pi.op, pi.np, bx0, ty0, th, c.band);
-      staged = np >= 0;
-    }
-    if (staged && ((sq >> j) & 1u)) {
-      nq = stage_band(c, a.B.xy, pi.oq, pi.nq, bx0, ty0, th, c.band + kBandCap);
-      staged = nq >= 0;
+    const bool need_p = kp_row != row, need_q = kq_row != row;
+    const int ry0 = by0 + kTile * j, th = min(kTile, by1 - ry0);
+    const uint64_t full = row_range(0, th);
+#pragma unroll 1
+    for (int b = 0; b < gx; ++b) {
+      sp[b * kWave + lane] = fresh_zero<uint64_t>();
+      sq[b * kWave + lane] = fresh_zero<uint64_t>();
     }
     wave_sync_lds();
-    if (staged) {
-      band_row_tiles(c, c.band, np, c.band + kBandCap, nq, row, kp_row, kq_row, bx0, bx1, th, acc);
-    } else {
-      for (uint32_t t = row; t; t &= t - 1) {
-        const int i = __ffs((int)t) - 1;
-        const int tx0 = bx0 + kTile * i;
-        acc += leaf_count(c, pi, tx0, ty0, min(kTile, bx1 - tx0), th, (kp_row >> i) & 1u, (kq_row >> i) & 1u);
+    if (need_p) scatter_row(c, a.A.xy, pi.op, pi.np, bx0, wpad, ry0, th, sp);
+    if (need_q) scatter_row(c, a.B.xy, pi.oq, pi.nq, bx0, wpad, ry0, th, sq);
+    wave_sync_lds();
+    // tiles right to left: block b = gx - 1 - i holds tile i
+    uint64_t carry_p = 0, carry_q = 0;
+#pragma unroll 1
+    for (int i = gx - 1; i >= 0; --i) {
+      const int b = gx - 1 - i;
+      const uint64_t xp = wave_prefix_xor<false>(sp[b * kWave + lane]);
+      const uint64_t xq = wave_prefix_xor<false>(sq[b * kWave + lane]);
+      if ((row >> i) & 1u) {
+        const int tw = min(kTile, bx1 - (bx0 + kTile * i));
+        const uint64_t mp = ((kp_row >> i) & 1u) ? full : (xp ^ carry_p);
+        const uint64_t mq = ((kq_row >> i) & 1u) ? full : (xq ^ carry_q);
+        if (kWave - 1 - lane < tw) {
+          ni += (uint32_t)__popcll(mp & mq);
+          nu += (uint32_t)__popcll(mp | mq);
+        }
+        n_leaf += 1;
+        n_tests += (unsigned long long)tw * th * ((((kp_row >> i) & 1u) ? 0 : 1) + (((kq_row >> i) & 1u) ? 0 : 1));
       }
+      carry_p ^= (uint64_t)readlane64((int64_t)xp, kWave - 1);
+      carry_q ^= (uint64_t)readlane64((int64_t)xq, kWave - 1);
     }
+    wave_sync_lds();
   }
-  wave_sync_lds();
+  const uint64_t si = wave_sum_u32(ni);
+  acc += direct ? (si | ((uint64_t)wave_sum_u32(nu) << 32)) : si;
+  if (a.stats_on) {
+    stat_add(c, 1, n_leaf);
+    stat_add(c, 0, n_tests);
+  }
 }
 
 // One pass over the ring: hover mask H and first-pixel parity mask P of the
@@ -1502,7 +1383,6 @@ __global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_wave
   c.a = &args;
   c.lane = lane_id();
   c.slots = sweep_slots + (threadIdx.x / kWave) * kLeafSlots;
-  c.band = nullptr;
   c.local = nullptr;
   c.lsp = 0;
   c.home = 0;
@@ -1587,8 +1467,7 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   c.lane = lane_id();
   unsigned char* lds = smem + (size_t)wave * kLdsPerWave;
   c.slots = reinterpret_cast<uint64_t*>(lds);
-  c.band = reinterpret_cast<uint32_t*>(lds + kLeafSlots * 8);
-  c.local = reinterpret_cast<uint64_t*>(lds + kLeafSlots * 8 + 2 * kBandCap * 4);
+  c.local = reinterpret_cast<uint64_t*>(lds + kRowSlotsPerWave * 8);
   c.lsp = 0;
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
