@@ -255,7 +255,8 @@ int sccg_sync(sccg_ctx* ctx);
  *       PLAIN, sub-boxes x ring edges tested
  *   [10] ring edges read while staging leaf tiles (BATCHED)
  *   [11] covered pixels: sum of the non-empty pair-box areas (BATCHED)
- *   [12] vertices reduced for MBRs and areas by the sweep (BATCHED)
+ *   [12] vertices reduced for MBRs and areas: by the prepass of listed pairs
+ *        and by the medium sweep (BATCHED)
  *   [13] vertices reduced for union boxes only, of pairs counted on one leaf tile (BATCHED)
  *   [14] leaf vertex updates: vertices XORed into a leaf slot by the union
  *        tile's vertex form of the crossing test (BATCHED)
@@ -263,9 +264,10 @@ int sccg_sync(sccg_ctx* ctx);
 int sccg_set_stats(sccg_ctx* ctx, int enable);
 int sccg_get_stats(sccg_ctx* ctx, int64_t* out, int n);
 
-/* Time the main kernels of every sccg_area_pairs call (the plain kernel, or
- * BATCHED mode's sweep and persistent kernel, back to back) with HIP events
- * recorded on the context's stream around them.  While timing is on, BATCHED mode
+/* Time the kernels of every sccg_area_pairs call (the plain kernel, or every
+ * launch of BATCHED mode, from the reset of its state to the persistent
+ * kernel, back to back) with HIP events recorded on the context's stream
+ * around them.  While timing is on, BATCHED mode
  * launches its kernels directly instead of through the HIP graph.
  * sccg_get_timing waits for the stream, returns the summed milliseconds and
  * the number of timed launches since the last sccg_get_timing (or since

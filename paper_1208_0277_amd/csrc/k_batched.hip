@@ -933,19 +933,29 @@ __device__ __forceinline__ uint64_t root_task(const PairInfo& pi) {
   return task_word(pi.hidx < 0 ? 0 : pi.hidx, cl, 0, 0, false, false);
 }
 
-__device__ __forceinline__ PairInfo heavy_info(const BatchArgs& a, int64_t hidx) {
+// A listed pair (its box from the prepass or the sweep).  Its index also
+// names it in the task words of its boxes.
+__device__ __forceinline__ PairInfo heavy_info(const BatchArgs& a, int64_t pair) {
   PairInfo pi;
-  pi.hidx = hidx;
-  pi.pair = a.l_list[hidx];
-  const int64_t ia = a.pa[pi.pair], ib = a.pb[pi.pair];
+  pi.hidx = pair;
+  pi.pair = pair;
+  const int64_t ia = a.pa[pair], ib = a.pb[pair];
   pi.op = a.A.off[ia];
   pi.np = a.A.off[ia + 1] - pi.op;
   pi.oq = a.B.off[ib];
   pi.nq = a.B.off[ib + 1] - pi.oq;
-  pi.box = load_meta(a.hbox, hidx);
+  pi.box = load_meta(a.hbox, pair);
   pi.area_sum = 0;
   make_uniform(pi);
   return pi;
+}
+
+// The list bucket of a pair with n vertices (largest first; one bucket when
+// the order is switched off).
+__device__ __forceinline__ int lpt_bucket(const BatchArgs& a, int64_t n) {
+  if (a.flags & SCCG_F_NO_LPT) return 0;
+  const int64_t h = a.heavy_verts;
+  return n >= 4 * h ? 3 : n >= 2 * h ? 2 : n >= h ? 1 : 0;
 }
 
 // Occupancy target of the persistent kernel (waves per SIMD); 0 leaves the
@@ -968,8 +978,10 @@ __device__ __forceinline__ PairInfo heavy_info(const BatchArgs& a, int64_t hidx)
 // at once (below Section 3.4's pixelization threshold, I and U directly).
 // Every other pair gets its MBRs and areas from its rings and is appended,
 // with its pair box, to the persistent kernel's list.
-constexpr int kSweepRing = 2 * kWave;                 // longest ring held in registers
+constexpr int kSweepRing = 2 * kWave;                 // longest ring of the union sweep
+constexpr int kMediumRing = 4 * kWave;                // longest ring of the medium sweep
 constexpr int kSweepWaves = 4;                        // waves per workgroup of the sweep
+constexpr int kSweepRowTiles = 4;                     // widest box (in leaf tiles) the sweep pixelizes
 // Occupancy target of the sweep (waves per SIMD), a build-time tuning knob.
 #ifndef SCCG_SWEEP_WAVES_PER_EU
 #define SCCG_SWEEP_WAVES_PER_EU 8
@@ -994,23 +1006,35 @@ __device__ __forceinline__ uint64_t upper_half(uint64_t v) {
 // The value of the next lane (DPP wave shift left by one; lane 63 reads 0).
 __device__ __forceinline__ int next_lane_x(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xf, 0xf, false); }
 
-// A sweep pair in registers: each ring in up to two 64-vertex chunks, lane L
+// A sweep pair in registers: each ring in up to N 64-vertex chunks, lane L
 // of chunk c holding vertex 64 c + L (lanes past the end hold the ring's last
 // vertex again: neutral for extents).
-constexpr int kRingChunks = kSweepRing / kWave;
+constexpr int kUnionChunks = kSweepRing / kWave;    // chunks per ring in the union sweep
+constexpr int kMediumChunks = kMediumRing / kWave;  // chunks per ring in the medium sweep
+template <int N>
 struct PairRegs {
-  int2 p[kRingChunks], q[kRingChunks];
+  int2 p[N], q[N];
 };
 
-__device__ __forceinline__ void ring_load(const int2* R, int nr, int lane, int2 (&d)[kRingChunks]) {
+// Chunks [c0, c1) of a ring of nr vertices.
+template <int N>
+__device__ __forceinline__ void ring_load(const int2* R, int nr, int lane, int2 (&d)[N], int c0 = 0, int c1 = N) {
 #pragma unroll
-  for (int c = 0; c < kRingChunks; ++c)
-    if (c * kWave < nr) d[c] = R[min(c * kWave + lane, nr - 1)];
+  for (int c = 0; c < N; ++c)
+    if (c >= c0 && c < c1 && c * kWave < nr) d[c] = R[min(c * kWave + lane, nr - 1)];
 }
 
-__device__ __forceinline__ void ring_move(int2 (&d)[kRingChunks], const int2 (&s)[kRingChunks], int nr) {
+// The next pair's rings are loaded ahead up to this many chunks each; the
+// rest of a longer ring is loaded when its pair comes up.
+constexpr int kAheadChunks = 2;
+struct AheadRegs {
+  int2 p[kAheadChunks], q[kAheadChunks];
+};
+
+template <int N>
+__device__ __forceinline__ void ring_move(int2 (&d)[N], const int2 (&s)[kAheadChunks], int nr) {
 #pragma unroll
-  for (int c = 0; c < kRingChunks; ++c)
+  for (int c = 0; c < kAheadChunks; ++c)
     if (c * kWave < nr) d[c] = s[c];
 }
 
@@ -1018,48 +1042,57 @@ __device__ __forceinline__ void ring_move(int2 (&d)[kRingChunks], const int2 (&s
 __device__ __forceinline__ uint64_t lanes_below_k(int k) { return (1ull << k) - 1ull; }
 __device__ __forceinline__ uint64_t lanes_upto_m(int m) { return ~0ull >> (kWave - m); }
 
-// Scatter of one ring of a union tile (see union_counts): every vertex whose
-// two edges are not both vertical or both horizontal XORs the rows at or
-// above it into the slot of the rightmost column left of it.  `base`: the
-// ring's first slot.  Returns the vertices scattered.
-template <typename M, int W, int R>
-__device__ __forceinline__ uint32_t ring_scatter(M* slots, const int2 (&d)[kRingChunks], int nr, int x0, int y0,
+// The corners of a ring held in registers: the vertices whose two edges are
+// not both vertical or both horizontal (bit L of word c: vertex 64 c + L).
+// A vertex's edge to its successor is vertical iff both have the same x;
+// the successor is the next lane, the next chunk's first lane, and after
+// the last vertex the first.
+template <int N>
+__device__ __forceinline__ void ring_corners(const int2 (&d)[N], int nr, uint64_t (&cm)[N]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) cm[c] = 0;
+  if (nr <= 0) return;
+  const int nc = (nr + kWave - 1) / kWave;
+  const int le = (nr - 1) & (kWave - 1);  // lane of the last vertex, in the last chunk
+  const int xl_lane = nc == 1 ? d[0].x : nc == 2 ? d[1].x : nc == 3 ? d[2].x : d[N - 1].x;
+  const uint64_t last = __builtin_amdgcn_readlane(xl_lane, le) == __builtin_amdgcn_readlane(d[0].x, 0) ? 1ull : 0ull;
+  uint64_t carry = last;  // the edge before vertex 0 is the ring's last
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    if (c < nc) {
+      int xs;
+      if (c + 1 < N && c + 1 < nc)
+        xs = __builtin_amdgcn_update_dpp(__builtin_amdgcn_readlane(d[c + 1 < N ? c + 1 : c].x, 0), d[c].x,
+                                         0x130, 0xf, 0xf, false);
+      else
+        xs = next_lane_x(d[c].x);
+      uint64_t b = ballot(d[c].x == xs);
+      if (c == nc - 1) b = (b & lanes_below_k(le)) | (last << le);
+      cm[c] = (b ^ ((b << 1) | carry)) & (c == nc - 1 ? lanes_upto_m(nr - c * kWave) : ~0ull);
+      carry = b >> 63;
+    }
+  }
+}
+
+// Scatter of one ring of a union tile (see union_counts): every corner XORs
+// the rows at or above it into the slot of the rightmost column left of it.
+// `base`: the ring's first slot.  Returns the vertices scattered.
+template <typename M, int W, int R, int N>
+__device__ __forceinline__ uint32_t ring_scatter(M* slots, const int2 (&d)[N], int nr, int x0, int y0,
                                                  int lane, int base) {
   if (nr <= 0) return 0;
-  const bool two = nr > kWave;
-  const int le = (nr - 1) & (kWave - 1);  // lane of the last vertex, in the last chunk
-  // b: the vertex's edge to its successor is vertical.  The successor is the
-  // next lane, the next chunk's first lane, and after the last vertex the
-  // first: that edge's bit is set from the two end points.
-  const int x_first = __builtin_amdgcn_readlane(d[0].x, 0);
-  const int x_last = __builtin_amdgcn_readlane(two ? d[1].x : d[0].x, le);
-  const uint64_t last = x_last == x_first ? 1ull : 0ull;
-  uint64_t b0, b1 = 0;
-  if (two) {
-    const int x64 = __builtin_amdgcn_readlane(d[1].x, 0);
-    b0 = ballot(d[0].x == __builtin_amdgcn_update_dpp(x64, d[0].x, 0x130, 0xf, 0xf, false));
-    b1 = (ballot(d[1].x == next_lane_x(d[1].x)) & lanes_below_k(le)) | (last << le);
-  } else {
-    b0 = (ballot(d[0].x == next_lane_x(d[0].x)) & lanes_below_k(le)) | (last << le);
-  }
-  // the vertex's two edges differ: b differs from the previous lane's (the
-  // ring's last edge before its first vertex)
-  const uint64_t c0 = (b0 ^ ((b0 << 1) | last)) & (two ? ~0ull : lanes_upto_m(nr));
+  uint64_t cm[N];
+  ring_corners(d, nr, cm);
   uint32_t kept = 0;
-  {
-    const int dx = d[0].x - x0, ty = d[0].y - y0;
-    const uint64_t keep = c0 & ballot(dx > 0) & ballot(ty < R);
-    M* sp = slots + (base + W - dx);
-    if (lane_in(keep)) slot_xor(sp, 0, (M)(~(M)0 << ty));
-    kept += (uint32_t)__popcll(keep);
-  }
-  if (two) {
-    const uint64_t c1 = (b1 ^ ((b1 << 1) | (b0 >> 63))) & lanes_upto_m(nr - kWave);
-    const int dx = d[1].x - x0, ty = d[1].y - y0;
-    const uint64_t keep = c1 & ballot(dx > 0) & ballot(ty < R);
-    M* sp = slots + (base + W - dx);
-    if (lane_in(keep)) slot_xor(sp, 0, (M)(~(M)0 << ty));
-    kept += (uint32_t)__popcll(keep);
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    if (c * kWave < nr) {
+      const int dx = d[c].x - x0, ty = d[c].y - y0;
+      const uint64_t keep = cm[c] & ballot(dx > 0) & ballot(ty < R);
+      M* sp = slots + (base + W - dx);
+      if (lane_in(keep)) slot_xor(sp, 0, (M)(~(M)0 << ty));
+      kept += (uint32_t)__popcll(keep);
+    }
   }
   return kept;
 }
@@ -1081,8 +1114,8 @@ __device__ __forceinline__ uint32_t ring_scatter(M* slots, const int2 (&d)[kRing
 // rows and columns past the union box come out outside, and nothing needs
 // clipping.  kHalves: W = 32, p's columns in lanes 0-31 and q's in lanes
 // 32-63, one scan; else W = 64 and one scan per ring.  M: 32- or 64-bit rows.
-template <bool kHalves, typename M>
-__device__ __forceinline__ uint32_t union_counts(Ctx& c, const PairRegs& r, int np, int nq, int x0, int y0) {
+template <bool kHalves, typename M, int N>
+__device__ __forceinline__ uint32_t union_counts(Ctx& c, const PairRegs<N>& r, int np, int nq, int x0, int y0) {
   constexpr int W = kHalves ? 32 : kWave;
   constexpr int R = (int)sizeof(M) * 8;
   const int lane = c.lane;
@@ -1090,8 +1123,8 @@ __device__ __forceinline__ uint32_t union_counts(Ctx& c, const PairRegs& r, int 
   slots[lane] = (M)0;
   if (!kHalves) slots[kWave + lane] = (M)0;
   wave_sync_lds();
-  uint32_t kept = ring_scatter<M, W, R>(slots, r.p, np, x0, y0, lane, 0);
-  kept += ring_scatter<M, W, R>(slots, r.q, nq, x0, y0, lane, W);
+  uint32_t kept = ring_scatter<M, W, R, N>(slots, r.p, np, x0, y0, lane, 0);
+  kept += ring_scatter<M, W, R, N>(slots, r.q, nq, x0, y0, lane, W);
   wave_sync_lds();
   uint32_t t;
   if (kHalves) {
@@ -1197,7 +1230,8 @@ __device__ __forceinline__ bool union_small(Ctx& c, int2 vp, int np, int2 vq, in
 // A pair held in registers: when the union of its MBRs fits one leaf tile
 // (and every coordinate is in range), its counts packed as I | U << 16 in t,
 // and true.
-__device__ __forceinline__ bool union_pair(Ctx& c, const PairRegs& r, int np, int nq, uint32_t& t) {
+template <int N>
+__device__ __forceinline__ bool union_pair(Ctx& c, const PairRegs<N>& r, int np, int nq, uint32_t& t) {
   const int2 f = np > 0 ? r.p[0] : r.q[0];  // lanes of an empty ring take this vertex
   int mnx = f.x, mny = f.y, mxx = f.x, mxy = f.y;
   auto add = [&](int2 v) {
@@ -1206,9 +1240,11 @@ __device__ __forceinline__ bool union_pair(Ctx& c, const PairRegs& r, int np, in
     mxx = max(mxx, v.x);
     mxy = max(mxy, v.y);
   };
-  if (np > kWave) add(r.p[1]);
-  if (nq > 0) add(r.q[0]);
-  if (nq > kWave) add(r.q[1]);
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    if (c > 0 && c * kWave < np) add(r.p[c]);
+    if (c * kWave < nq) add(r.q[c]);
+  }
   const int x0 = wave_min_i32(mnx), y0 = wave_min_i32(mny);
   const int x1 = wave_max_i32(mxx), y1 = wave_max_i32(mxy);
   if (!(x0 >= -kMaxCoord && y0 >= -kMaxCoord && x1 <= kMaxCoord && y1 <= kMaxCoord &&
@@ -1216,11 +1252,11 @@ __device__ __forceinline__ bool union_pair(Ctx& c, const PairRegs& r, int np, in
     return false;
   const int uw = x1 - x0, uh = y1 - y0;
   if (uw <= 32)
-    t = uh <= 32 ? union_counts<true, uint32_t>(c, r, np, nq, x0, y0)
-                 : union_counts<true, uint64_t>(c, r, np, nq, x0, y0);
+    t = uh <= 32 ? union_counts<true, uint32_t, N>(c, r, np, nq, x0, y0)
+                 : union_counts<true, uint64_t, N>(c, r, np, nq, x0, y0);
   else
-    t = uh <= 32 ? union_counts<false, uint32_t>(c, r, np, nq, x0, y0)
-                 : union_counts<false, uint64_t>(c, r, np, nq, x0, y0);
+    t = uh <= 32 ? union_counts<false, uint32_t, N>(c, r, np, nq, x0, y0)
+                 : union_counts<false, uint64_t, N>(c, r, np, nq, x0, y0);
   if (c.a->stats_on) {
     const int n = np + nq;
     stat_add(c, 5, 1ull);
@@ -1237,19 +1273,23 @@ __device__ __forceinline__ bool union_pair(Ctx& c, const PairRegs& r, int np, in
 // again).  Twice the signed area is summed modulo 2^64 and its magnitude
 // taken unsigned, which is exact while it stays within 2^63.  A ring with a
 // coordinate beyond 2^30 comes back empty, with area 0 and `bad` set.
-__device__ __forceinline__ void ring_meta_regs(const int2 (&d)[kRingChunks], int nr, int lane, Meta& m, int64_t& area,
+template <int N>
+__device__ __forceinline__ void ring_meta_regs(const int2 (&d)[N], int nr, int lane, Meta& m, int64_t& area,
                                                bool& bad) {
   m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};
   area = 0;
   bad = false;
   if (nr <= 0) return;
-  const bool two = nr > kWave;
+  const int nc = (nr + kWave - 1) / kWave;
   int mnx = d[0].x, mny = d[0].y, mxx = mnx, mxy = mny;
-  if (two) {
-    mnx = min(mnx, d[1].x);
-    mny = min(mny, d[1].y);
-    mxx = max(mxx, d[1].x);
-    mxy = max(mxy, d[1].y);
+#pragma unroll
+  for (int c = 1; c < N; ++c) {
+    if (c < nc) {
+      mnx = min(mnx, d[c].x);
+      mny = min(mny, d[c].y);
+      mxx = max(mxx, d[c].x);
+      mxy = max(mxy, d[c].y);
+    }
   }
   const Meta e{wave_min_i32(mnx), wave_min_i32(mny), wave_max_i32(mxx), wave_max_i32(mxy)};
   if (e.x0 < -kMaxCoord || e.y0 < -kMaxCoord || e.x1 > kMaxCoord || e.y1 > kMaxCoord) {
@@ -1263,10 +1303,10 @@ __device__ __forceinline__ void ring_meta_regs(const int2 (&d)[kRingChunks], int
   const int2 f = lane_value(d[0], 0);
   uint64_t tw = 0;
 #pragma unroll
-  for (int c = 0; c < kRingChunks; ++c) {
-    if (c == 0 || two) {
-      const bool last_chunk = c == kRingChunks - 1 || !two;
-      const int2 nx = last_chunk ? f : lane_value(d[c + 1 < kRingChunks ? c + 1 : c], 0);
+  for (int c = 0; c < N; ++c) {
+    if (c < nc) {
+      const bool last_chunk = c == nc - 1;
+      const int2 nx = last_chunk ? f : lane_value(d[c + 1 < N ? c + 1 : c], 0);
       int sx = __builtin_amdgcn_update_dpp(nx.x, d[c].x, 0x130, 0xf, 0xf, false);
       int sy = __builtin_amdgcn_update_dpp(nx.y, d[c].y, 0x130, 0xf, 0xf, false);
       if (last_chunk && lane == le) {
@@ -1281,13 +1321,91 @@ __device__ __forceinline__ void ring_meta_regs(const int2 (&d)[kRingChunks], int
   area = (int64_t)(((int64_t)t < 0 ? 0 - t : t) / 2);
 }
 
+// Count of a pair box [bx0, bx1) x [by0, by1) at most kSweepRowTiles leaf
+// tiles wide, from the rings in registers: the vertex form of the crossing
+// test (see union_counts) with the box clipping it.  A corner left of the
+// box toggles none of its columns and one right of it all of them; a corner
+// below a band row of the box sets all of the band's rows and one above it
+// none.  Each band row is laid out as in leaf_rows: the columns of both
+// rings in one slot array each, tiles scanned right to left with the XOR of
+// the tiles to their right carried.
+template <int N>
+__device__ __forceinline__ uint64_t sweep_rows(Ctx& c, const PairRegs<N>& r, int np, int nq, const Meta& box) {
+  const int lane = c.lane;
+  const int bw = box.x1 - box.x0, bh = box.y1 - box.y0;
+  const int gx = (bw + kTile - 1) / kTile, gy = (bh + kTile - 1) / kTile;
+  const int wpad = gx * kTile;
+  // per vertex: its slot position when it is a corner right of the box's
+  // left side, else -1
+  int posp[N], posq[N];
+  {
+    uint64_t cm[N];
+    ring_corners(r.p, np, cm);
+#pragma unroll
+    for (int ch = 0; ch < N; ++ch) {
+      const int dx = min(r.p[ch].x, box.x0 + wpad) - box.x0;
+      posp[ch] = lane_in(cm[ch]) && dx > 0 ? wpad - dx : -1;
+    }
+    ring_corners(r.q, nq, cm);
+#pragma unroll
+    for (int ch = 0; ch < N; ++ch) {
+      const int dx = min(r.q[ch].x, box.x0 + wpad) - box.x0;
+      posq[ch] = lane_in(cm[ch]) && dx > 0 ? kSweepRowTiles * kWave + wpad - dx : -1;
+    }
+  }
+  uint64_t* slots = c.slots;
+  uint32_t ni = 0;
+#pragma unroll 1
+  for (int j = 0; j < gy; ++j) {
+    const int ry0 = box.y0 + kTile * j, th = min(kTile, box.y1 - ry0);
+    const uint64_t full = row_range(0, th);
+#pragma unroll 1
+    for (int b = 0; b < gx; ++b) {
+      slots[b * kWave + lane] = fresh_zero<uint64_t>();
+      slots[kSweepRowTiles * kWave + b * kWave + lane] = fresh_zero<uint64_t>();
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int ch = 0; ch < N; ++ch) {
+      if (ch * kWave < np) {
+        const int ty = min(r.p[ch].y, ry0 + kTile) - ry0;
+        if (posp[ch] >= 0 && ty < kTile) slot_xor(slots, posp[ch], ty <= 0 ? ~0ull : ~0ull << ty);
+      }
+      if (ch * kWave < nq) {
+        const int ty = min(r.q[ch].y, ry0 + kTile) - ry0;
+        if (posq[ch] >= 0 && ty < kTile) slot_xor(slots, posq[ch], ty <= 0 ? ~0ull : ~0ull << ty);
+      }
+    }
+    wave_sync_lds();
+    uint64_t carry_p = 0, carry_q = 0;
+#pragma unroll 1
+    for (int i = gx - 1; i >= 0; --i) {
+      const int b = gx - 1 - i;
+      const uint64_t xp = wave_prefix_xor<false>(slots[b * kWave + lane]);
+      const uint64_t xq = wave_prefix_xor<false>(slots[kSweepRowTiles * kWave + b * kWave + lane]);
+      const int tw = min(kTile, bw - kTile * i);
+      if (kWave - 1 - lane < tw) ni += (uint32_t)__popcll((xp ^ carry_p) & (xq ^ carry_q) & full);
+      carry_p ^= (uint64_t)readlane64((int64_t)xp, kWave - 1);
+      carry_q ^= (uint64_t)readlane64((int64_t)xq, kWave - 1);
+    }
+    wave_sync_lds();
+  }
+  if (c.a->stats_on) {
+    stat_add(c, 1, (unsigned long long)gx * gy);
+    stat_add(c, 0, 2ull * (unsigned long long)bw * bh);
+    stat_add(c, 10, (unsigned long long)(np + nq) * gy);
+  }
+  return wave_sum_u32(ni);
+}
+
 // A sweep pair held in registers that the union tile does not take: MBRs and
 // areas, then the pair box (the union box when the union is counted
 // directly).  Returns the pair's class: done (an empty box, or a box side
 // out of range: I and U are final), or small / large (the pair is to be
 // listed for the persistent kernel with `box`, I = 0 and U = |p| + |q|, or 0
 // when the union is counted directly, as the values its boxes add to).
-__device__ __forceinline__ uint8_t sweep_meta(Ctx& c, const PairRegs& r, int np, int nq, int64_t& I, int64_t& U,
+template <int N>
+__device__ __forceinline__ uint8_t sweep_meta(Ctx& c, const PairRegs<N>& r, int np, int nq, int64_t& I, int64_t& U,
                                               Meta& box) {
   const BatchArgs& a = *c.a;
   Meta mp, mq;
@@ -1338,46 +1456,80 @@ __device__ __forceinline__ SweepRec sweep_rec(const ChunkRecs& cr, int j) {
   s.cls = __builtin_amdgcn_readlane(cr.cls, j);
   return s;
 }
-// a sweep pair (both rings of at most kSweepRing vertices) with vertices
-__device__ __forceinline__ bool in_regs(const SweepRec& s) { return s.cls == kClsSweep && s.np + s.nq > 0; }
+// the records of pairs i0 + lane (lane < cnt) of a chunk, one coalesced load
+__device__ __forceinline__ ChunkRecs chunk_recs(const BatchArgs& a, int64_t i0, int cnt, int lane) {
+  ChunkRecs cr{0, 0, 0, 0, 0, 0, kClsDone};
+  if (lane < cnt) {
+    const int4 h = *reinterpret_cast<const int4*>(a.rec + i0 + lane);
+    const int4 t = *(reinterpret_cast<const int4*>(a.rec + i0 + lane) + 1);
+    cr = ChunkRecs{h.x, h.y, h.z, h.w, t.x, t.y, t.z};
+  }
+  return cr;
+}
 
-// Pair i = i0 + j of the chunk.  A pair counted on its union tile leaves
-// I | U << 16 in lane j of `packed` (written out with the chunk); any other
-// pair writes its counts (or, when it is listed for the persistent kernel,
-// the values its boxes add to) itself.
-__device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairRegs& r, int64_t i, int j,
+// the record of pair idx in every lane with `valid` set
+__device__ __forceinline__ ChunkRecs gather_recs(const BatchArgs& a, int idx, bool valid) {
+  ChunkRecs cr{0, 0, 0, 0, 0, 0, kClsDone};
+  if (valid) {
+    const int4 h = *reinterpret_cast<const int4*>(a.rec + idx);
+    const int4 t = *(reinterpret_cast<const int4*>(a.rec + idx) + 1);
+    cr = ChunkRecs{h.x, h.y, h.z, h.w, t.x, t.y, t.z};
+  }
+  return cr;
+}
+
+// Append pairs i0 + j (bit j of `m`) to a list with one reservation.
+__device__ __forceinline__ void list_append(Counter& count, int32_t* list, uint64_t m, int64_t i0, int lane) {
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(&count.v, (unsigned long long)__popcll(m));
+  base = (unsigned long long)uniform64((int64_t)__shfl((long long)base, 0, kWave));
+  if (lane_in(m)) list[base + (unsigned long long)lanes_below(m)] = (int32_t)(i0 + lane);
+}
+
+// Claim a chunk of `chunk` consecutive entries from per-stream counters (one
+// stream per XCD, exhausted streams marked in `empty`): its first entry, or
+// -1 when every stream is exhausted.
+__device__ __forceinline__ int64_t claim_chunk(Counter* next, int64_t n, int chunk, int xcd, int lane,
+                                               uint32_t& empty) {
+  const unsigned long long n_chunks = ((unsigned long long)n + chunk - 1) / chunk;
+  if (n_chunks == 0) empty = 0xffu;
+  while (empty != 0xffu) {
+    const int st = next_stream(empty, xcd);
+    unsigned long long k = 0;
+    if (lane == 0) k = atomicAdd(&next[st].v, 1ull);
+    k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
+    const unsigned long long g = k * kStreams + st;
+    if (g >= n_chunks) {
+      empty = uniform_u(empty | (1u << st));
+      continue;
+    }
+    return uniform64((int64_t)g * chunk);
+  }
+  return -1;
+}
+
+// Pair j of the chunk (a sweep pair): counted on its union tile, leaving
+// I | U << 16 in lane j of `packed` and bit j in `wmask` (written out with
+// the chunk); a pair left out (union box larger than a leaf tile) goes to
+// the medium list with the chunk.
+__device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairRegs<kUnionChunks>& r, int j,
                                           bool union_ok, uint32_t& packed, uint64_t& wmask) {
-  if (s.cls != kClsSweep) return;  // listed by the setup pass, or a bad index
-  const BatchArgs& a = *c.a;
+  if (s.cls != kClsSweep) return;  // another class, or a bad index
   const int lane = c.lane;
-  uint32_t t;
-  if (s.np + s.nq > 0 && union_ok &&
-      (s.np <= kWave && s.nq <= kWave ? union_small(c, r.p[0], s.np, r.q[0], s.nq, t)
-                                      : union_pair(c, r, s.np, s.nq, t))) {
+  uint32_t t = 0;
+  bool done = s.np + s.nq == 0;  // two empty rings: nothing in either
+  if (done) stat_add(c, 7, 1ull);
+  if (!done && union_ok)
+    done = s.np <= kWave && s.nq <= kWave ? union_small(c, r.p[0], s.np, r.q[0], s.nq, t)
+                                          : union_pair<kUnionChunks>(c, r, s.np, s.nq, t);
+  if (done) {
     if (lane == j) packed = t;
     wmask |= 1ull << j;
-    return;
-  }
-  int64_t I = 0, U = 0;
-  Meta box{0, 0, 0, 0};
-  uint8_t cls = kClsDone;
-  if (s.np + s.nq > 0)
-    cls = sweep_meta(c, r, s.np, s.nq, I, U, box);
-  else
-    stat_add(c, 7, 1ull);  // two empty rings
-  if (lane == 0) {
-    a.inter[i] = I;
-    a.uni[i] = U;
-    if (cls != kClsDone) {
-      const unsigned long long k = atomicAdd(&a.st->l_count.v, 1ull);
-      a.l_list[k] = (int32_t)i;
-      *reinterpret_cast<int4*>(a.hbox + k) = make_int4(box.x0, box.y0, box.x1, box.y1);
-      a.cls[i] = cls;
-    }
   }
 }
 
-__global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_waves_per_eu(SCCG_SWEEP_WAVES_PER_EU))) k_batch_sweep(BatchArgs args) {
+__global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_waves_per_eu(SCCG_SWEEP_WAVES_PER_EU)))
+k_batch_sweep(BatchArgs args) {
   __shared__ __align__(16) uint64_t sweep_slots[kSweepWaves * kLeafSlots];
   Ctx c;
   c.a = &args;
@@ -1389,67 +1541,134 @@ __global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_wave
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   const BatchArgs& a = args;
   const int lane = c.lane;
-  const unsigned long long n_chunks = ((unsigned long long)a.n_pairs + a.chunk - 1) / a.chunk;
   const bool union_ok = direct_union(a) || !(a.flags & SCCG_F_NO_UNION_TILE);
   uint32_t s_empty = 0;  // claim streams found exhausted (wave-uniform)
   for (;;) {
-    int64_t i0 = -1;
-    while (s_empty != 0xffu) {
-      const int st = next_stream(s_empty, c.xcd);
-      unsigned long long k = 0;
-      if (lane == 0) k = atomicAdd(&a.st->s_next[st].v, 1ull);
-      k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
-      const unsigned long long g = k * kStreams + st;
-      if (g >= n_chunks) {
-        s_empty = uniform_u(s_empty | (1u << st));
-        continue;
-      }
-      i0 = uniform64((int64_t)g * a.chunk);
-      break;
-    }
+    const int64_t i0 = claim_chunk(a.st->s_next, a.n_pairs, a.chunk, c.xcd, lane, s_empty);
     if (i0 < 0) break;
     const int cnt = uniform((int)min((int64_t)a.chunk, a.n_pairs - i0));
-    // the chunk's records, one per lane (one coalesced load)
-    ChunkRecs cr{0, 0, 0, 0, 0, 0, kClsDone};
-    if (lane < cnt) {
-      const int4 h = *reinterpret_cast<const int4*>(a.rec + i0 + lane);
-      const int4 t = *(reinterpret_cast<const int4*>(a.rec + i0 + lane) + 1);
-      cr = ChunkRecs{h.x, h.y, h.z, h.w, t.x, t.y, t.z};
-    }
+    const ChunkRecs cr = chunk_recs(a, i0, cnt, lane);
     // lane j: I | U << 16 of pair i0 + j when it is counted on its union tile
     uint32_t packed = 0;
     uint64_t wmask = 0;
     // the pair in hand (sc, rc) and the next one (sn, rn), whose loads are in
     // flight while the pair in hand is processed
-    PairRegs rc, rn;
+    PairRegs<kUnionChunks> rc, rn;
     SweepRec sc = sweep_rec(cr, 0);
-    if (in_regs(sc)) {
+    if (sc.cls == kClsSweep) {
       ring_load(a.A.xy + sc.op, sc.np, lane, rc.p);
       ring_load(a.B.xy + sc.oq, sc.nq, lane, rc.q);
     }
 #pragma unroll 1
     for (int j = 0; j < cnt; ++j) {
       SweepRec sn{0, 0, 0, 0, kClsDone};
-      bool gn = false;
       if (j + 1 < cnt) {
         sn = sweep_rec(cr, j + 1);
-        gn = in_regs(sn);
-        if (gn) {
+        if (sn.cls == kClsSweep) {
           ring_load(a.A.xy + sn.op, sn.np, lane, rn.p);
           ring_load(a.B.xy + sn.oq, sn.nq, lane, rn.q);
         }
       }
-      sweep_one(c, sc, rc, i0 + j, j, union_ok, packed, wmask);
+      sweep_one(c, sc, rc, j, union_ok, packed, wmask);
       sc = sn;
-      if (gn) {
-        ring_move(rc.p, rn.p, sn.np);
-        ring_move(rc.q, rn.q, sn.nq);
+      if (sn.cls == kClsSweep) {
+#pragma unroll
+        for (int ch = 0; ch < kUnionChunks; ++ch) {
+          if (ch * kWave < sn.np) rc.p[ch] = rn.p[ch];
+          if (ch * kWave < sn.nq) rc.q[ch] = rn.q[ch];
+        }
       }
     }
-    // the chunk's union-tile counts go out in one coalesced store per array
+    // the chunk's union-tile counts go out in one coalesced store per array,
+    // the sweep pairs it left out to the medium list with one reservation
     if (lane_in(wmask)) {
       a.inter[i0 + lane] = (int64_t)(packed & 0xffffu);
       a.uni[i0 + lane] = (int64_t)(packed >> 16);
+    }
+    const uint64_t left = ballot(lane < cnt && cr.cls == kClsSweep) & ~wmask;
+    if (left) list_append(a.st->m_count, a.m_list, left, i0, lane);
+  }
+}
+
+// ------------------------------------------------------------ medium sweep
+// Second pass over the medium list: pairs with rings of at most kMediumRing
+// vertices that the union tile did not take.  MBRs and areas come from the
+// rings in registers; a pair box at most kSweepRowTiles tiles wide is
+// pixelized at once (a box the persistent kernel would not classify), a
+// larger one is listed with its box.  A claim takes 64 consecutive entries.
+__device__ __forceinline__ void medium_one(Ctx& c, const SweepRec& s, const PairRegs<kMediumChunks>& r, int64_t i) {
+  const BatchArgs& a = *c.a;
+  int64_t I = 0, U = 0;
+  Meta box{0, 0, 0, 0};
+  uint8_t cls = sweep_meta(c, r, s.np, s.nq, I, U, box);
+  if (cls != kClsDone && !direct_union(a)) {
+    const int gx = (box.x1 - box.x0 + kTile - 1) / kTile, gy = (box.y1 - box.y0 + kTile - 1) / kTile;
+    if (gx <= kSweepRowTiles && gy <= kMaxGrid && (gx * gy == 1 || gx * gy < a.min_classify_cells)) {
+      I = (int64_t)sweep_rows(c, r, s.np, s.nq, box);
+      U -= I;
+      cls = kClsDone;
+    }
+  }
+  if (c.lane == 0) {
+    a.inter[i] = I;
+    a.uni[i] = U;
+    if (cls != kClsDone) {
+      const int bk = lpt_bucket(a, (int64_t)s.np + s.nq);
+      const unsigned long long k = atomicAdd(&a.st->l_count[bk].v, 1ull);
+      a.l_list[(int64_t)bk * a.n_pairs + (int64_t)k] = (int32_t)i;
+      *reinterpret_cast<int4*>(a.hbox + i) = make_int4(box.x0, box.y0, box.x1, box.y1);
+      a.cls[i] = cls;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs args) {
+  constexpr int kMediumSlots = 2 * kSweepRowTiles * kWave;
+  __shared__ __align__(16) uint64_t medium_slots[kSweepWaves * kMediumSlots];
+  Ctx c;
+  c.a = &args;
+  c.lane = lane_id();
+  c.slots = medium_slots + (threadIdx.x / kWave) * kMediumSlots;
+  c.local = nullptr;
+  c.lsp = 0;
+  c.home = 0;
+  c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
+  const BatchArgs& a = args;
+  const int lane = c.lane;
+  const int64_t n_med = (int64_t)a.st->m_count.v;
+  // entries per claim: 64, or fewer when the list gives the grid's waves
+  // less than 8 claims each
+  const int64_t per_wave = n_med / ((int64_t)gridDim.x * kSweepWaves * 8);
+  const int chunk = (int)max((int64_t)1, min((int64_t)kWave, per_wave));
+  uint32_t m_empty = 0;
+  for (;;) {
+    const int64_t e0 = claim_chunk(a.st->m_next, n_med, chunk, c.xcd, lane, m_empty);
+    if (e0 < 0) break;
+    const int cnt = uniform((int)min((int64_t)chunk, n_med - e0));
+    // lane j: pair index and record of entry e0 + j
+    const int idx = lane < cnt ? a.m_list[e0 + lane] : 0;
+    const ChunkRecs cr = gather_recs(a, idx, lane < cnt);
+    PairRegs<kMediumChunks> rc;
+    AheadRegs rn;
+    SweepRec sc = sweep_rec(cr, 0);
+    ring_load(a.A.xy + sc.op, sc.np, lane, rc.p);
+    ring_load(a.B.xy + sc.oq, sc.nq, lane, rc.q);
+#pragma unroll 1
+    for (int j = 0; j < cnt; ++j) {
+      SweepRec sn{0, 0, 0, 0, kClsDone};
+      if (j + 1 < cnt) {
+        sn = sweep_rec(cr, j + 1);
+        ring_load(a.A.xy + sn.op, sn.np, lane, rn.p);
+        ring_load(a.B.xy + sn.oq, sn.nq, lane, rn.q);
+      }
+      medium_one(c, sc, rc, (int64_t)__builtin_amdgcn_readlane(idx, j));
+      if (j + 1 >= cnt) break;
+      sc = sn;
+      ring_move(rc.p, rn.p, sn.np);
+      ring_move(rc.q, rn.q, sn.nq);
+      // the rest of longer rings now
+      if (sn.np > kAheadChunks * kWave) ring_load(a.A.xy + sn.op, sn.np, lane, rc.p, kAheadChunks);
+      if (sn.nq > kAheadChunks * kWave) ring_load(a.B.xy + sn.oq, sn.nq, lane, rc.q, kAheadChunks);
     }
   }
 }
@@ -1472,12 +1691,18 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
   const BatchArgs& a = args;
-  const unsigned long long n_list = a.st->l_count.v;
+  unsigned long long n_list[kLptBuckets], n_all = 0;
+#pragma unroll
+  for (int b = 0; b < kLptBuckets; ++b) {
+    n_list[b] = a.st->l_count[b].v;
+    n_all += n_list[b];
+  }
   // Boxes reach a queue only from splits with at least min_cells_to_queue
   // continuing cells (at most 64): otherwise no wave ever needs to look at
   // the queues.
-  const bool queues_used = n_list > 0 && !(a.flags & SCCG_F_NO_SPLIT_QUEUE) && a.min_cells_to_queue <= kWave;
-  uint32_t l_empty = 0;  // streams of the list this wave found exhausted (wave-uniform)
+  const bool queues_used = n_all > 0 && !(a.flags & SCCG_F_NO_SPLIT_QUEUE) && a.min_cells_to_queue <= kWave;
+  int bucket = kLptBuckets - 1;  // the bucket being claimed, largest first (wave-uniform)
+  uint32_t l_empty = 0;          // streams of that bucket found exhausted (wave-uniform)
   for (;;) {
     PairInfo pi;
     uint64_t task = 0;  // 0: a box that fits one leaf tile
@@ -1488,17 +1713,16 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
       task = w;
       have = true;
     }
-    while (!have && l_empty != 0xffu) {
-      const int st = next_stream(l_empty, c.xcd);
-      unsigned long long k = 0;
-      if (c.lane == 0) k = atomicAdd(&a.st->l_next[st].v, 1ull);
-      k = (unsigned long long)uniform64((int64_t)__shfl((long long)k, 0, kWave));
-      const unsigned long long e = k * kStreams + st;
-      if (e >= n_list) {
-        l_empty = uniform_u(l_empty | (1u << st));
+    while (!have && bucket >= 0) {
+      const unsigned long long nb = bucket == 3 ? n_list[3] : bucket == 2 ? n_list[2] : bucket == 1 ? n_list[1]
+                                                                                                     : n_list[0];
+      const int64_t e = claim_chunk(a.st->l_next[bucket], (int64_t)nb, 1, c.xcd, c.lane, l_empty);
+      if (e < 0) {
+        bucket = uniform(bucket - 1);
+        l_empty = 0;
         continue;
       }
-      pi = heavy_info(a, (int64_t)e);
+      pi = heavy_info(a, (int64_t)a.l_list[(int64_t)bucket * a.n_pairs + e]);
       const uint8_t cls = a.cls[pi.pair];
       if (cls == kClsDone) continue;  // settled by the prepass
       have = true;
@@ -1538,16 +1762,25 @@ __global__ void k_batch_clear_counters(BatchArgs a) {
   for (int k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0;
 }
 
-// Per pair: index check; pairs with many vertices go to the heavy list.
+// Per pair: index check, the pair's record and class: swept (rings of at
+// most kSweepRing vertices), medium (at most kMediumRing), or listed by
+// vertex count for the prepass and the persistent kernel (longer rings, or
+// at least heavy_verts vertices in all).
 __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a, int per) {
   // a block takes per x 256 consecutive pairs (coalesced rows of 256) and
-  // reserves room for its heavy pairs in the heavy list with one atomic:
-  // one per wave contended on the list counter
-  __shared__ uint32_t scan[256];
-  __shared__ unsigned long long base_s;
+  // reserves room for its listed pairs with one atomic per bucket: the
+  // per-thread counts of the four buckets travel as 16-bit fields of one
+  // 64-bit scan
+  __shared__ unsigned long long scan[256];
+  __shared__ unsigned long long base_s[kLptBuckets];
   const int tid = threadIdx.x;
   const int64_t b0 = (int64_t)blockIdx.x * 256 * per;
-  uint32_t hmask = 0;
+  __shared__ unsigned mscan[256];
+  __shared__ unsigned long long mbase_s;
+  uint32_t lmask = 0;      // bit t: pair t of this thread is listed
+  uint32_t bmask = 0;      // bits 2t, 2t+1: its bucket
+  uint32_t mmask = 0;      // bit t: pair t of this thread is a medium pair
+  unsigned long long cnt = 0;
   for (int t = 0; t < per; ++t) {
     const int64_t i = b0 + (int64_t)t * 256 + tid;
     if (i >= a.n_pairs) break;
@@ -1564,34 +1797,57 @@ __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a, int per) {
       r.np = (int32_t)(a.A.off[ia + 1] - r.op);
       r.oq = a.B.off[ib];
       r.nq = (int32_t)(a.B.off[ib + 1] - r.oq);
-      // the sweep holds rings of at most kSweepRing vertices in registers:
-      // longer ones are listed, as are (largest first) the heaviest pairs
-      if (r.np > kSweepRing || r.nq > kSweepRing ||
-          (!(a.flags & SCCG_F_NO_LPT) && (int64_t)r.np + r.nq >= a.heavy_verts)) {
-        hmask |= 1u << t;
+      const int64_t n = (int64_t)r.np + r.nq;
+      if (r.np > kMediumRing || r.nq > kMediumRing || n >= a.heavy_verts) {
+        const int bk = lpt_bucket(a, n);
+        lmask |= 1u << t;
+        bmask |= (uint32_t)bk << (2 * t);
+        cnt += 1ull << (16 * bk);
         cls = kClsHeavy;
+      } else if (r.np > kSweepRing || r.nq > kSweepRing) {
+        mmask |= 1u << t;
+        cls = kClsMedium;
       }
     }
     r.cls = cls;
     a.cls[i] = cls;
     a.rec[i] = r;
   }
-  // exclusive prefix of the per-thread heavy counts over the block
-  const uint32_t cnt = (uint32_t)__popc(hmask);
+  // exclusive prefix of the per-thread counts over the block
+  const unsigned mcnt = (unsigned)__popc(mmask);
   scan[tid] = cnt;
+  mscan[tid] = mcnt;
   __syncthreads();
   for (int d = 1; d < 256; d <<= 1) {
-    const uint32_t v = tid >= d ? scan[tid - d] : 0u;
+    const unsigned long long v = tid >= d ? scan[tid - d] : 0ull;
+    const unsigned mv = tid >= d ? mscan[tid - d] : 0u;
     __syncthreads();
     scan[tid] += v;
+    mscan[tid] += mv;
     __syncthreads();
   }
-  const uint32_t total = scan[255];
-  if (tid == 0) base_s = total ? atomicAdd(&a.st->l_count.v, (unsigned long long)total) : 0ull;
+  const unsigned long long total = scan[255];
+  if (tid < kLptBuckets) {
+    const unsigned long long nb = (total >> (16 * tid)) & 0xffffull;
+    base_s[tid] = nb ? atomicAdd(&a.st->l_count[tid].v, nb) : 0ull;
+  } else if (tid == kLptBuckets) {
+    const unsigned long long nm = mscan[255];
+    mbase_s = nm ? atomicAdd(&a.st->m_count.v, nm) : 0ull;
+  }
   __syncthreads();
-  unsigned long long pos = base_s + (scan[tid] - cnt);
-  for (uint32_t m = hmask; m; m &= m - 1)
-    a.l_list[pos++] = (int32_t)(b0 + (int64_t)(__ffs((int)m) - 1) * 256 + tid);
+  unsigned long long mpos = mbase_s + (mscan[tid] - mcnt);
+  for (uint32_t m = mmask; m; m &= m - 1)
+    a.m_list[mpos++] = (int32_t)(b0 + (int64_t)(__ffs((int)m) - 1) * 256 + tid);
+  const unsigned long long before = scan[tid] - cnt;
+  unsigned long long pos[kLptBuckets];
+#pragma unroll
+  for (int b = 0; b < kLptBuckets; ++b) pos[b] = base_s[b] + ((before >> (16 * b)) & 0xffffull);
+  for (uint32_t m = lmask; m; m &= m - 1) {
+    const int t = __ffs((int)m) - 1;
+    const int bk = (int)((bmask >> (2 * t)) & 3u);
+    const int64_t k = (int64_t)(bk == 3 ? pos[3]++ : bk == 2 ? pos[2]++ : bk == 1 ? pos[1]++ : pos[0]++);
+    a.l_list[(int64_t)bk * a.n_pairs + k] = (int32_t)(b0 + (int64_t)t * 256 + tid);
+  }
 }
 
 // One wave per heavy pair: MBRs and areas of both rings, the pair box and the
@@ -1600,9 +1856,24 @@ __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a, int per) {
 __global__ void __launch_bounds__(256) k_batch_heavy_meta(BatchArgs a) {
   const int lane = lane_id();
   const int waves = gridDim.x * (blockDim.x / kWave);
-  const int64_t n = (int64_t)a.st->l_count.v;
+  int64_t nb[kLptBuckets], n = 0;
+#pragma unroll
+  for (int b = 0; b < kLptBuckets; ++b) {
+    nb[b] = (int64_t)a.st->l_count[b].v;
+    n += nb[b];
+  }
   for (int64_t k = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; k < n; k += waves) {
-    const int64_t i = a.l_list[k];
+    // entry k of the buckets laid end to end, largest first
+    int64_t kk = k;
+    int bk = kLptBuckets - 1;
+#pragma unroll
+    for (int b = kLptBuckets - 1; b > 0; --b) {
+      if (bk == b && kk >= nb[b]) {
+        kk -= nb[b];
+        bk = b - 1;
+      }
+    }
+    const int64_t i = a.l_list[(int64_t)bk * a.n_pairs + kk];
     const int64_t ia = a.pa[i], ib = a.pb[i];
     const int64_t op = a.A.off[ia], oq = a.B.off[ib];
     Meta mp, mq;
@@ -1610,9 +1881,10 @@ __global__ void __launch_bounds__(256) k_batch_heavy_meta(BatchArgs a) {
     ring_scan(a.A.xy, op, a.A.off[ia + 1] - op, lane, mp, ap);
     ring_scan(a.B.xy, oq, a.B.off[ib + 1] - oq, lane, mq, aq);
     if (lane != 0) continue;
+    if (a.stats_on) atomicAdd(&a.st->stats[12], (unsigned long long)(a.A.off[ia + 1] - op + a.B.off[ib + 1] - oq));
     if (coords_bad(mp, a.A.off[ia + 1] - op) || coords_bad(mq, a.B.off[ib + 1] - oq)) latch_error(a.err, kErrCoord);
     const Meta b = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
-    *reinterpret_cast<int4*>(a.hbox + k) = make_int4(b.x0, b.y0, b.x1, b.y1);
+    *reinterpret_cast<int4*>(a.hbox + i) = make_int4(b.x0, b.y0, b.x1, b.y1);
     const int64_t w = (int64_t)b.x1 - b.x0, h = (int64_t)b.y1 - b.y0;
     uint8_t cls = kClsDone;
     a.inter[i] = 0;
@@ -1665,14 +1937,17 @@ int batch_occupancy(int waves_per_wg) {
 }
 
 int batch_sweep_occupancy() {
-  int n = 0;
+  int n = 0, m = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep, kSweepWaves * kWave, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_batch_medium, kSweepWaves * kWave, 0) != hipSuccess) return 1;
+  n = n < m ? n : m;
   return n > 0 ? n : 1;
 }
 
 hipError_t launch_batch_run(const BatchArgs& a, int sweep_grid, int grid, int waves_per_wg, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_sweep, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
+  hipLaunchKernelGGL(k_batch_medium, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
   const size_t lds = (size_t)waves_per_wg * batch_lds_bytes_per_wave();
   hipLaunchKernelGGL(k_batch_run, dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
   if (a.stats_on)

@@ -177,7 +177,7 @@ int ensure_pairs(sccg_ctx* c, int64_t n) {
   int64_t want = n + n / 4 + 1024;
   int r;
   if ((r = grow(c, &c->cls, want, "pair classes")) || (r = grow(c, &c->rec, want, "pair records")) ||
-      (r = grow(c, &c->l_list, want, "heavy list")) || (r = grow(c, &c->hbox, want, "heavy boxes"))) {
+      (r = grow(c, &c->l_list, want * (kLptBuckets + 1), "pair lists")) || (r = grow(c, &c->hbox, want, "heavy boxes"))) {
     c->cap_pairs = 0;
     return r;
   }
@@ -393,14 +393,14 @@ __global__ void k_zero_stats(unsigned long long* s) {
 
 static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int grid) {
   hipError_t e;
-  if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
-  if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (c->timing_on) {
     int r = timing_events(c, &t0, &t1);
     if (r) return r;
     HIP_TRY(c, hipEventRecord(t0, c->stream));
   }
+  if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
+  if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
   if ((e = launch_batch_run(ba, sweep_grid, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
     return hip_fail(c, e, "batch run");
   if (c->timing_on) HIP_TRY(c, hipEventRecord(t1, c->stream));
@@ -473,6 +473,7 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   ba.cls = c->cls;
   ba.rec = c->rec;
   ba.l_list = c->l_list;
+  ba.m_list = c->l_list + (size_t)kLptBuckets * (size_t)n_pairs;
   ba.hbox = c->hbox;
   ba.st = c->st;
   ba.queue = c->queue;

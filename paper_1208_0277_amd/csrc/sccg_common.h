@@ -22,10 +22,12 @@ enum : uint32_t {
   kErrWatchdog = 8u,  // a bounded wait in the persistent kernel ran out
 };
 
-// Pair classes of the batched path: done in a prepass, swept in index
-// order, or heavy (listed for the persistent kernel, claimed first); listed
-// pairs are then marked by their box (small: one leaf tile; large: split).
-enum : uint8_t { kClsDone = 0, kClsSweep = 1, kClsHeavy = 2, kClsSmall = 3, kClsLarge = 4 };
+// Pair classes of the batched path: done in a prepass, swept in index order
+// (rings short enough to be held in registers), medium (rings held in
+// registers by the second sweep), or heavy (listed for the persistent
+// kernel); listed pairs are then marked by their box (small: one leaf tile;
+// large: split).
+enum : uint8_t { kClsDone = 0, kClsSweep = 1, kClsHeavy = 2, kClsSmall = 3, kClsLarge = 4, kClsMedium = 5 };
 
 struct Polys {
   int64_t n;
@@ -84,10 +86,17 @@ constexpr int kStreams = 8;
 // Device-side state of the batched path (one block of device memory), reset
 // at the start of every call after the slots the previous call touched
 // (below max(head, tail) of each queue) are cleared.
+// Listed pairs are kept in kLptBuckets lists by vertex count (the cost the
+// setup pass can see): at least 4, 2 or 1 times heavy_verts, and the rest;
+// the persistent kernel claims the largest bucket first.
+constexpr int kLptBuckets = 4;
+
 struct BatchState {
-  Counter l_count;            // heavy pairs listed by the setup pass
-  Counter l_next[kStreams];   // per-stream claim counters over the heavy list
-  Counter s_next[kStreams];   // per-stream claim counters over pair chunks
+  Counter l_count[kLptBuckets];            // pairs listed per bucket
+  Counter l_next[kLptBuckets][kStreams];   // per-stream claim counters over each bucket
+  Counter s_next[kStreams];   // per-stream claim counters over pair chunks (the sweep)
+  Counter m_count;            // medium pairs listed (by the setup pass and the sweep)
+  Counter m_next[kStreams];   // per-stream claim counters over chunks of the medium list
   Counter q_head[kMaxGrid];   // per-queue ticket counters
   Counter q_tail[kMaxGrid];   // per-queue reservation counters
   unsigned long long stats[kNumStats];
@@ -112,8 +121,9 @@ struct BatchArgs {
   uint32_t* err;
   uint8_t* cls;                  // [n_pairs]
   PairRec* rec;                  // [n_pairs]
-  int32_t* l_list;               // [n_pairs] heavy pairs
-  Meta* hbox;                    // [n_pairs] pair box of heavy-list entry k
+  int32_t* l_list;               // [kLptBuckets][n_pairs] listed pairs, bucket b from b * n_pairs
+  int32_t* m_list;               // [n_pairs] medium pairs, in the order they were listed
+  Meta* hbox;                    // [n_pairs] pair box of a listed pair (by pair index)
   BatchState* st;
   unsigned long long* queue;     // [n_queues * queue_cap] task words, 0 = empty
   int32_t queue_cap;             // slots per queue
