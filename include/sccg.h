@@ -225,6 +225,25 @@ int sccg_relate_pairs(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, i
 int sccg_host_area_pairs(const sccg_polys* A, const sccg_polys* B, int64_t n_pairs, const int32_t* pair_a,
                          const int32_t* pair_b, int64_t* out_inter, int64_t* out_union, int n_threads);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * BATCHED mode of sccg_area_pairs, with the same arguments and the same
+ * results, that calls no hipMalloc, hipFree or other allocating routine.
+ * Its scratch (batched state, task queues, per-pair records and lists) is a
+ * static device array of about 19 MiB that every GPU the library runs on
+ * holds until the process ends; its device address is taken once per device
+ * by sccg_create.  Limits: at most 2^18 = 262144 pairs per call (more gives
+ * SCCG_E_ARG with a message naming the limit), task queues of at most 2^17
+ * slots in all (queue_cap is lowered to fit, which changes no count), device
+ * ordinals below 64.  Work counters and timing are not collected and no HIP
+ * graph is used (the kernels are launched on the context's stream).  Every
+ * call on one GPU uses that GPU's one array and leaves its state there for
+ * the next call, which clears what must start at zero: calls that overlap on
+ * one GPU (on different streams or contexts, without ordering between them)
+ * race and give wrong results. */
+int sccg_area_pairs_noalloc(sccg_ctx* ctx, const sccg_polys* A, const sccg_polys* B, int64_t n_pairs,
+                            const int32_t* pair_a, const int32_t* pair_b, int64_t* out_inter, int64_t* out_union);
+
 /* Check the input form the method assumes (Section 3.1 and Figure 3: a
  * segmented object's boundary follows pixel sides, so a polygon has integer
  * vertices and only horizontal and vertical edges): every ring of P has at

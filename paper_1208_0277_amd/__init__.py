@@ -50,7 +50,7 @@ SCCG_J_INCLUDE_ZERO = 1
 EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
            "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
            "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version",
-           "sccg_graph_launches", "sccg_valu_peak",
+           "sccg_graph_launches", "sccg_valu_peak", "sccg_area_pairs_noalloc",
            "sccg_join_sets", "sccg_relate_pairs", "sccg_host_area_pairs", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
            "sccg_server_clock", "sccg_server_last_error", "sccg_server_destroy")
 
@@ -138,6 +138,8 @@ def load_library(path: str = LIB_PATH):
         "sccg_reserve": ([P, i64, i64, i64], ctypes.c_int),
         "sccg_area_pairs": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P, u32],
                             ctypes.c_int),
+        "sccg_area_pairs_noalloc": ([P, ctypes.POINTER(sccg_polys), ctypes.POINTER(sccg_polys), i64, P, P, P, P],
+                                    ctypes.c_int),
         "sccg_jaccard_sets": ([P, i64, P, P, P, u32, P, P, P, P, P], ctypes.c_int),
         "sccg_validate_polys": ([P, ctypes.POINTER(sccg_polys), P], ctypes.c_int),
         "sccg_sync": ([P], ctypes.c_int),
@@ -312,6 +314,22 @@ class Context:
         ca, cb = A.c(), B.c()
         self._rc(self.lib.sccg_area_pairs(self.h, ctypes.byref(ca), ctypes.byref(cb), n, _ptr(pair_a),
                                           _ptr(pair_b), _ptr(out_inter), _ptr(out_union), mode))
+        return out_inter, out_union
+
+    def area_pairs_noalloc(self, A: DevicePolys, B: DevicePolys, pair_a, pair_b, out_inter, out_union):
+        """Queue sccg_area_pairs_noalloc (BATCHED counts, no device allocation
+        in the library; the caller passes both outputs)."""
+        import torch
+        _check_dev(pair_a, torch.int32, "pair_a")
+        _check_dev(pair_b, torch.int32, "pair_b")
+        _check_dev(out_inter, torch.int64, "out_inter")
+        _check_dev(out_union, torch.int64, "out_union")
+        n = int(pair_a.shape[0])
+        if int(pair_b.shape[0]) != n or int(out_inter.shape[0]) < n or int(out_union.shape[0]) < n:
+            raise ValueError("pair arrays differ in length or an output is shorter")
+        ca, cb = A.c(), B.c()
+        self._rc(self.lib.sccg_area_pairs_noalloc(self.h, ctypes.byref(ca), ctypes.byref(cb), n, _ptr(pair_a),
+                                                  _ptr(pair_b), _ptr(out_inter), _ptr(out_union)))
         return out_inter, out_union
 
     def jaccard_sets(self, set_pair_off, inter, uni, flags: int = SCCG_J_NONZERO_ONLY, jprime: bool = True):

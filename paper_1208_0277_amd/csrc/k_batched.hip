@@ -1054,7 +1054,8 @@ __device__ __forceinline__ void ring_corners(const int2 (&d)[N], int nr, uint64_
   if (nr <= 0) return;
   const int nc = (nr + kWave - 1) / kWave;
   const int le = (nr - 1) & (kWave - 1);  // lane of the last vertex, in the last chunk
-  const int xl_lane = nc == 1 ? d[0].x : nc == 2 ? d[1].x : nc == 3 ? d[2].x : d[N - 1].x;
+  const int xl_lane = nc == 1 ? d[0].x : nc == 2 ? d[1 < N ? 1 : N - 1].x : nc == 3 ? d[2 < N ? 2 : N - 1].x
+                                                                              : d[N - 1].x;
   const uint64_t last = __builtin_amdgcn_readlane(xl_lane, le) == __builtin_amdgcn_readlane(d[0].x, 0) ? 1ull : 0ull;
   uint64_t carry = last;  // the edge before vertex 0 is the ring's last
 #pragma unroll

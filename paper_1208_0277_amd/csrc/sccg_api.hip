@@ -4,6 +4,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -251,6 +253,59 @@ Polys to_polys(const sccg_polys* P) {
   return Polys{P->n_polys, P->offsets, reinterpret_cast<const int2*>(P->xy)};
 }
 
+// ---------------------------------------------- no-allocation scratch
+// Scratch of sccg_area_pairs_noalloc: one static device array per GPU,
+// holding the batched state, the task queues and the per-pair arrays for at
+// most kNoAllocMaxPairs pairs.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the device (kept in g_noalloc).
+constexpr int64_t kNoAllocMaxPairs = int64_t(1) << 18;
+constexpr int64_t kNoAllocQueueSlots = int64_t(1) << 17;  // all queues together
+constexpr int kNoAllocMaxDevices = 64;
+constexpr size_t na_align(size_t n) { return (n + 255) / 256 * 256; }
+constexpr size_t kNaQueue = na_align(sizeof(BatchState));
+constexpr size_t kNaRec = kNaQueue + na_align(sizeof(unsigned long long) * kNoAllocQueueSlots);
+constexpr size_t kNaHbox = kNaRec + na_align(sizeof(PairRec) * kNoAllocMaxPairs);
+constexpr size_t kNaList = kNaHbox + na_align(sizeof(Meta) * kNoAllocMaxPairs);
+constexpr size_t kNaCls = kNaList + na_align(sizeof(int32_t) * (kLptBuckets + 1) * kNoAllocMaxPairs);
+constexpr size_t kNoAllocBytes = kNaCls + na_align(kNoAllocMaxPairs);
+
+struct NoAllocDevice {
+  unsigned char* ptr = nullptr;  // device address of `scratch` on this GPU
+  int32_t nq = 0, cap = 0;       // queue layout of the last call (0: every slot clear)
+};
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+__global__ void k_noalloc_clear(unsigned long long* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// Once per device, with the device current: the device address of the
+// scratch array, cleared once so that every queue slot reads empty.
+int noalloc_setup(sccg_ctx* c) {
+  if (c->device >= kNoAllocMaxDevices) return SCCG_OK;  // the entry point reports it
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  NoAllocDevice& d = g_noalloc[c->device];
+  if (d.ptr) return SCCG_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+  e = hipMemset(p, 0, kNoAllocBytes);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return hip_fail(c, e, "clearing the no-allocation scratch");
+  d.ptr = static_cast<unsigned char*>(p);
+  d.nq = 0;
+  d.cap = 0;
+  return SCCG_OK;
+}
+
 }  // namespace
 
 uint32_t* sccg::ctx_error_word(sccg_ctx* c) { return c->err; }
@@ -292,6 +347,10 @@ int sccg_create(sccg_ctx** out, int hip_device, void* hip_stream, const sccg_par
   }
   if (hipMemset(c->err, 0, sizeof(uint32_t)) != hipSuccess || hipMemset(c->st, 0, sizeof(BatchState)) != hipSuccess ||
       hipMemset(c->plain_stats, 0, kNumStats * sizeof(unsigned long long)) != hipSuccess) {
+    sccg_destroy(c);
+    return SCCG_E_HIP;
+  }
+  if (noalloc_setup(c) != SCCG_OK) {
     sccg_destroy(c);
     return SCCG_E_HIP;
   }
@@ -518,6 +577,74 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   }
   HIP_TRY(c, hipGraphLaunch(c->gexec, c->stream));
   c->graph_launches += 1;
+  return SCCG_OK;
+}
+
+int sccg_area_pairs_noalloc(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64_t n_pairs,
+                            const int32_t* pair_a, const int32_t* pair_b, int64_t* out_inter, int64_t* out_union) {
+  if (!c) return SCCG_E_ARG;
+  int r;
+  if ((r = check_polys(c, A, "A")) || (r = check_polys(c, B, "B"))) return r;
+  if (n_pairs < 0) return fail(c, SCCG_E_ARG, "n_pairs < 0");
+  if (n_pairs > kNoAllocMaxPairs)
+    return fail(c, SCCG_E_ARG, "n_pairs %lld above the no-allocation limit of %lld pairs", (long long)n_pairs,
+                (long long)kNoAllocMaxPairs);
+  if (n_pairs == 0) return SCCG_OK;
+  if (!pair_a || !pair_b || !out_inter || !out_union) return fail(c, SCCG_E_ARG, "NULL pair or output array");
+  if (c->device >= kNoAllocMaxDevices)
+    return fail(c, SCCG_E_ARG, "device %d above the no-allocation limit of %d devices", c->device,
+                kNoAllocMaxDevices);
+  HIP_TRY(c, hipSetDevice(c->device));
+  const int32_t nq = c->p.n_queues;
+  const int32_t cap = (int32_t)std::min<int64_t>(c->p.queue_cap, kNoAllocQueueSlots / nq);
+  unsigned char* base;
+  {
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    NoAllocDevice& d = g_noalloc[c->device];
+    if (!d.ptr) return fail(c, SCCG_E_HIP, "no-allocation scratch not set up on device %d", c->device);
+    base = d.ptr;
+    // the reset kernel clears the slots the previous call used in that
+    // call's layout: a new layout needs every slot cleared first
+    if (d.nq != 0 && (d.nq != nq || d.cap != cap)) {
+      hipLaunchKernelGGL(k_noalloc_clear, dim3(256), dim3(256), 0, c->stream,
+                         reinterpret_cast<unsigned long long*>(base + kNaQueue), (int64_t)kNoAllocQueueSlots);
+      HIP_TRY(c, hipGetLastError());
+    }
+    d.nq = nq;
+    d.cap = cap;
+  }
+  BatchArgs ba{};
+  ba.A = to_polys(A);
+  ba.B = to_polys(B);
+  ba.n_pairs = n_pairs;
+  ba.pa = pair_a;
+  ba.pb = pair_b;
+  ba.inter = out_inter;
+  ba.uni = out_union;
+  ba.err = c->err;
+  ba.st = reinterpret_cast<BatchState*>(base);
+  ba.queue = reinterpret_cast<unsigned long long*>(base + kNaQueue);
+  ba.rec = reinterpret_cast<PairRec*>(base + kNaRec);
+  ba.hbox = reinterpret_cast<Meta*>(base + kNaHbox);
+  ba.l_list = reinterpret_cast<int32_t*>(base + kNaList);
+  ba.m_list = ba.l_list + (size_t)kLptBuckets * (size_t)n_pairs;
+  ba.cls = base + kNaCls;
+  ba.queue_cap = cap;
+  ba.n_queues = nq;
+  ba.chunk = c->p.queue_chunk;
+  ba.heavy_verts = c->p.heavy_verts;
+  ba.min_cells_to_queue = c->p.min_queue_cells;
+  ba.min_classify_cells = c->p.min_classify_cells;
+  ba.flags = c->p.flags;
+  ba.stats_on = 0;
+  int grid = c->p.grid;
+  if (grid == 0) grid = c->cu_count * batch_occupancy(c->p.waves_per_wg);
+  const int sweep_grid = c->cu_count * batch_sweep_occupancy();
+  hipError_t e;
+  if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
+  if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
+  if ((e = launch_batch_run(ba, sweep_grid, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "batch run");
   return SCCG_OK;
 }
 
