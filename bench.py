@@ -73,8 +73,12 @@ ALGO_OPS = {
     "union_tile_vertices": 4,
     "leaf_boxes": 26 * 64,
 }
-# int32 VALU peak of MI355X: 256 CUs x 4 SIMD16 = 64 lanes per CU per clock at 2.4 GHz
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# int32 VALU peak of MI355X, lane-operations per second: the fp32 vector peak
+# of 157.3 TFLOP/s counts an FMA as two flops, so the vector units retire
+# 78.6 T lane-instructions/s (128 lanes per CU per clock at 2.4 GHz), and a
+# plain 32-bit integer add or XOR issues at that rate (the device's own
+# add/xor microbenchmark sustains about 59 T, well above the 64-lane figure)
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
 HBM_PEAK = 8.0e12
 
 
@@ -123,7 +127,25 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+#: the calibration sample of the autotuner is drawn with the timed
+#: workload's seed plus this offset
+CALIBRATION_SEED_OFFSET = 1_000_003
+
 PROFILE_STEMS = {3: "k_batch_run_heavy_tailed_2M", 4: "k_batch_run_set_level_64_tiles"}
+
+
+def tail_summary(wt):
+    """Load balance of one kernel from its waves' (start, end) stamps (100 MHz
+    counter): the span from the first start to the last end, the median
+    wave's end, and the tail fraction (last end - median end) / span."""
+    if len(wt) == 0:
+        return None
+    t0 = int(wt[:, 0].min())
+    ends = wt[:, 1].astype(np.float64) - t0
+    span = float(ends.max())
+    med = float(np.median(ends))
+    return {"waves": int(len(wt)), "span_us": span / 100.0, "median_end_us": med / 100.0,
+            "tail_frac": (span - med) / span if span > 0 else 0.0}
 
 
 def profile_summary(workload: int, params: dict):
@@ -515,6 +537,28 @@ def main(argv=None):
     ctx.reserve(dA.n, dB.n, wl.n_pairs)
     wkey = f"w{args.workload}/{wl.n_pairs}"
 
+    # The autotuner scores candidates on a calibration sample: the same mix
+    # drawn under another seed (workload 4: a quarter of the tiles), never
+    # the timed pairs.
+    calib = {}
+    cal_dev = None
+    if not args.params and not args.no_autotune:
+        t = time.perf_counter()
+        cseed = wl.seed + CALIBRATION_SEED_OFFSET
+        if with_sets:
+            cwl = sccg_gen.sets(n_tiles=max(1, args.tiles // 4), tile_side=8192, cell=64, seed=cseed)
+        else:
+            cwl = sccg_gen.pairs(args.workload, wl.n_pairs, seed=cseed)
+        cal_dev = (sccg.DevicePolys.from_host(cwl.A.off, cwl.A.xy, dev),
+                   sccg.DevicePolys.from_host(cwl.B.off, cwl.B.xy, dev),
+                   torch.from_numpy(cwl.pa).to(dev), torch.from_numpy(cwl.pb).to(dev),
+                   torch.empty(cwl.n_pairs, dtype=torch.int64, device=dev),
+                   torch.empty(cwl.n_pairs, dtype=torch.int64, device=dev))
+        calib = {"sample": f"{WORKLOADS[args.workload].split(':')[0]}, {cwl.n_pairs} pairs, seed {cseed} "
+                           f"(the timed pairs use seed {wl.seed})", "seed": cseed, "n_pairs": cwl.n_pairs}
+        torch.cuda.synchronize()
+        log(f"calibration sample: {cwl.n_pairs} pairs, seed {cseed} ({time.perf_counter() - t:.1f} s)")
+
     with torch.cuda.stream(stream):
         tuned = {}
         if args.params:
@@ -523,9 +567,11 @@ def main(argv=None):
             log(f"fixed batched parameters {tuned}")
         elif not args.no_autotune:
             t = time.perf_counter()
-            tuned = autotune.tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key=wkey,
-                                  use_cache=False, log=log)
-            log(f"autotuned batched parameters {tuned} in {time.perf_counter() - t:.1f} s")
+            ctx.reserve(max(dA.n, cal_dev[0].n), max(dB.n, cal_dev[1].n), max(wl.n_pairs, calib["n_pairs"]))
+            tuned = autotune.tune(ctx, *cal_dev, mode=sccg.SCCG_BATCHED, workload_key=wkey, use_cache=False,
+                                  log=log)
+            calib["batched_params"] = tuned
+            log(f"autotuned batched parameters {tuned} on the calibration sample in {time.perf_counter() - t:.1f} s")
 
         sets_out = [None]
 
@@ -559,7 +605,13 @@ def main(argv=None):
         k_ms, k_n = ctx.get_timing()
         ctx.set_timing(False)
         k_avg_ms = k_ms / max(k_n, 1)
-        # work counters (instrumented call, not timed)
+        # per-wave stamps (a call without counters: their atomics would
+        # slow it), then the work counters (instrumented call); neither timed
+        ctx.set_stats(False, stamps=True)
+        step()
+        ctx.sync()
+        balance = {name: tail_summary(ctx.wave_times(k))
+                   for k, name in enumerate(("union_sweep", "medium_sweep", "persistent"))}
         ctx.set_stats(True)
         step()
         ctx.sync()
@@ -572,10 +624,11 @@ def main(argv=None):
         if not args.no_plain:
             pctx = sccg.Context(0, stream=stream)
             ptuned = {}
-            if not args.no_autotune:
+            if cal_dev is not None:
                 t = time.perf_counter()
-                ptuned = autotune.tune(pctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_PLAIN, workload_key=wkey,
-                                       steps=1, use_cache=False, log=log)
+                ptuned = autotune.tune(pctx, *cal_dev, mode=sccg.SCCG_PLAIN, workload_key=wkey, steps=1,
+                                       use_cache=False, log=log)
+                calib["plain_params"] = ptuned
                 log(f"autotuned plain parameters {ptuned} in {time.perf_counter() - t:.1f} s")
             pctx.area_pairs(dA, dB, pa, pb, out_inter=I, out_union=U, mode=sccg.SCCG_PLAIN)
             pctx.sync()
@@ -708,6 +761,8 @@ def main(argv=None):
         "oracle_sample_pairs": n_sample,
         "repeat_identical": bool(same),
         **sets_info,
+        "autotune": calib or None,
+        "load_balance": balance,
         "stats": st,
         "roofline": roofline,
         "cpu_baseline": cpu,

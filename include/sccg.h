@@ -261,7 +261,9 @@ int sccg_sync(sccg_ctx* ctx);
 
 /* Work counters of the last sccg_area_pairs call, valid after sccg_sync.
  * Counting costs a few atomics per box and is on only while
- * sccg_set_stats(ctx, 1) is in effect (the HIP graph is rebuilt on a change).
+ * sccg_set_stats(ctx, flags) has bit 0 set; bit 1 turns on the per-wave
+ * stamps of sccg_get_wave_times (no atomics), other bits give SCCG_E_ARG
+ * (the HIP graph is rebuilt on a change).
  *   [0] leaf pixel tests: pixels of leaf boxes x polygons tested there
  *   [1] leaf boxes       [2] split boxes
  *   [3] boxes published to the device queue (BATCHED)
@@ -282,6 +284,16 @@ int sccg_sync(sccg_ctx* ctx);
  * Writes min(n, 16) values to out; returns that count (or an error < 0). */
 int sccg_set_stats(sccg_ctx* ctx, int enable);
 int sccg_get_stats(sccg_ctx* ctx, int64_t* out, int n);
+
+/* Load balance of BATCHED mode (Algorithm 1's pairs spread over the grid):
+ * while stamps are on (sccg_set_stats bit 1), every wave of the union sweep (kernel 0), the
+ * medium sweep (1) and the persistent kernel (2) stamps its start and its
+ * end with the device's constant-rate 100 MHz counter.  Waits for the
+ * context's stream, writes min(waves, max_waves) (start, end) pairs of the
+ * last such call's kernel to out (host int64 [2 * max_waves]) and returns
+ * the kernel's wave count (0 before any such call), or an error < 0
+ * (SCCG_E_ARG for a kernel outside [0, 2] or a NULL out with max_waves > 0). */
+int64_t sccg_get_wave_times(sccg_ctx* ctx, int kernel, int64_t* out, int64_t max_waves);
 
 /* Time the kernels of every sccg_area_pairs call (the plain kernel, or every
  * launch of BATCHED mode, from the reset of its state to the persistent

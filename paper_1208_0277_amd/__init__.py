@@ -50,7 +50,7 @@ SCCG_J_INCLUDE_ZERO = 1
 EXPORTS = ("sccg_create", "sccg_destroy", "sccg_set_params", "sccg_get_params", "sccg_reserve",
            "sccg_area_pairs", "sccg_jaccard_sets", "sccg_validate_polys", "sccg_sync", "sccg_set_stats",
            "sccg_get_stats", "sccg_set_timing", "sccg_get_timing", "sccg_last_error", "sccg_version",
-           "sccg_graph_launches", "sccg_valu_peak", "sccg_area_pairs_noalloc",
+           "sccg_graph_launches", "sccg_valu_peak", "sccg_area_pairs_noalloc", "sccg_get_wave_times",
            "sccg_join_sets", "sccg_relate_pairs", "sccg_host_area_pairs", "sccg_server_create", "sccg_server_submit", "sccg_server_poll", "sccg_server_get_stats",
            "sccg_server_clock", "sccg_server_last_error", "sccg_server_destroy")
 
@@ -145,6 +145,7 @@ def load_library(path: str = LIB_PATH):
         "sccg_sync": ([P], ctypes.c_int),
         "sccg_set_stats": ([P, ctypes.c_int], ctypes.c_int),
         "sccg_get_stats": ([P, P, ctypes.c_int], ctypes.c_int),
+        "sccg_get_wave_times": ([P, ctypes.c_int, P, i64], ctypes.c_int64),
         "sccg_set_timing": ([P, ctypes.c_int], ctypes.c_int),
         "sccg_get_timing": ([P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "sccg_last_error": ([P], ctypes.c_char_p),
@@ -265,8 +266,9 @@ class Context:
     def reserve(self, max_polys_a: int, max_polys_b: int, max_pairs: int):
         self._rc(self.lib.sccg_reserve(self.h, max_polys_a, max_polys_b, max_pairs))
 
-    def set_stats(self, enable: bool):
-        self._rc(self.lib.sccg_set_stats(self.h, 1 if enable else 0))
+    def set_stats(self, enable: bool, stamps: bool = False):
+        """Work counters (enable) and per-wave stamps (stamps) of later calls."""
+        self._rc(self.lib.sccg_set_stats(self.h, (1 if enable else 0) | (2 if stamps else 0)))
 
     def get_stats(self) -> dict:
         out = np.zeros(16, np.int64)
@@ -274,6 +276,20 @@ class Context:
         if n < 0:
             self._rc(n)
         return dict(zip(STAT_KEYS, (int(v) for v in out[:n])))
+
+    def wave_times(self, kernel: int):
+        """(start, end) counter stamps (100 MHz) of every wave of a batched
+        kernel (0 union sweep, 1 medium sweep, 2 persistent) in the last call
+        made with stamps on (set_stats(2)): an int64 array of shape (waves, 2)."""
+        n = self.lib.sccg_get_wave_times(self.h, kernel, None, 0)
+        if n < 0:
+            self._rc(int(n))
+        out = np.zeros((max(int(n), 0), 2), np.int64)
+        if n > 0:
+            m = self.lib.sccg_get_wave_times(self.h, kernel, out.ctypes.data, int(n))
+            if m < 0:
+                self._rc(int(m))
+        return out
 
     def valu_peak(self, iters: int = 20000):
         """(sustained integer VALU lane-operations per second, kernel ms)."""

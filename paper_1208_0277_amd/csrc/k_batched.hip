@@ -133,6 +133,20 @@ __device__ __forceinline__ int next_stream(uint32_t empty, int from) {
   return uniform((from + __ffs((int)rot) - 1) % kStreams);
 }
 
+// Stamp of the device's constant-rate counter (100 MHz), read by the wave.
+__device__ __forceinline__ unsigned long long wave_stamp(const BatchArgs& a) {
+  return a.wave_t ? (unsigned long long)__builtin_amdgcn_s_memrealtime() : 0ull;
+}
+// A wave's (start, end) stamps of kernel `kernel` (see BatchArgs::wave_t).
+__device__ __forceinline__ void wave_stamps(const BatchArgs& a, int kernel, unsigned long long t0, int lane) {
+  if (!a.wave_t || lane != 0) return;
+  const unsigned w = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (w >= (unsigned)a.wave_cap) return;
+  unsigned long long* p = a.wave_t + 2 * ((size_t)kernel * (size_t)a.wave_cap + w);
+  p[0] = t0;
+  p[1] = (unsigned long long)__builtin_amdgcn_s_memrealtime();
+}
+
 __device__ __forceinline__ void stat_add(const Ctx& c, int k, unsigned long long v) {
   if (c.a->stats_on && c.lane == 0 && v) atomicAdd(&c.a->st->stats[k], v);
 }
@@ -1015,6 +1029,10 @@ template <int N>
 struct PairRegs {
   int2 p[N], q[N];
 };
+// pairs of the union sweep whose rings are in flight beyond the pair in
+// hand (deeper lookahead measured no faster: the sweep is bound by
+// instruction issue, not by load latency)
+constexpr int kSweepAhead = 1;
 
 // Chunks [c0, c1) of a ring of nr vertices.
 template <int N>
@@ -1543,6 +1561,7 @@ k_batch_sweep(BatchArgs args) {
   const BatchArgs& a = args;
   const int lane = c.lane;
   const bool union_ok = direct_union(a) || !(a.flags & SCCG_F_NO_UNION_TILE);
+  const unsigned long long t_start = wave_stamp(a);
   uint32_t s_empty = 0;  // claim streams found exhausted (wave-uniform)
   for (;;) {
     const int64_t i0 = claim_chunk(a.st->s_next, a.n_pairs, a.chunk, c.xcd, lane, s_empty);
@@ -1552,32 +1571,31 @@ k_batch_sweep(BatchArgs args) {
     // lane j: I | U << 16 of pair i0 + j when it is counted on its union tile
     uint32_t packed = 0;
     uint64_t wmask = 0;
-    // the pair in hand (sc, rc) and the next one (sn, rn), whose loads are in
-    // flight while the pair in hand is processed
-    PairRegs<kUnionChunks> rc, rn;
-    SweepRec sc = sweep_rec(cr, 0);
-    if (sc.cls == kClsSweep) {
-      ring_load(a.A.xy + sc.op, sc.np, lane, rc.p);
-      ring_load(a.B.xy + sc.oq, sc.nq, lane, rc.q);
+    // the pair in hand (s[0], r[0]) and the next kSweepAhead ones, whose ring
+    // loads are in flight while the pair in hand is processed
+    SweepRec s[kSweepAhead + 1];
+    PairRegs<kUnionChunks> r[kSweepAhead + 1];
+#pragma unroll
+    for (int k = 0; k <= kSweepAhead; ++k) {
+      s[k] = k < cnt ? sweep_rec(cr, k) : SweepRec{0, 0, 0, 0, kClsDone};
+      if (s[k].cls == kClsSweep) {
+        ring_load(a.A.xy + s[k].op, s[k].np, lane, r[k].p);
+        ring_load(a.B.xy + s[k].oq, s[k].nq, lane, r[k].q);
+      }
     }
 #pragma unroll 1
     for (int j = 0; j < cnt; ++j) {
-      SweepRec sn{0, 0, 0, 0, kClsDone};
-      if (j + 1 < cnt) {
-        sn = sweep_rec(cr, j + 1);
-        if (sn.cls == kClsSweep) {
-          ring_load(a.A.xy + sn.op, sn.np, lane, rn.p);
-          ring_load(a.B.xy + sn.oq, sn.nq, lane, rn.q);
-        }
-      }
-      sweep_one(c, sc, rc, j, union_ok, packed, wmask);
-      sc = sn;
-      if (sn.cls == kClsSweep) {
+      sweep_one(c, s[0], r[0], j, union_ok, packed, wmask);
 #pragma unroll
-        for (int ch = 0; ch < kUnionChunks; ++ch) {
-          if (ch * kWave < sn.np) rc.p[ch] = rn.p[ch];
-          if (ch * kWave < sn.nq) rc.q[ch] = rn.q[ch];
-        }
+      for (int k = 0; k < kSweepAhead; ++k) {
+        s[k] = s[k + 1];
+        r[k] = r[k + 1];
+      }
+      const int jn = j + kSweepAhead + 1;
+      s[kSweepAhead] = jn < cnt ? sweep_rec(cr, jn) : SweepRec{0, 0, 0, 0, kClsDone};
+      if (s[kSweepAhead].cls == kClsSweep) {
+        ring_load(a.A.xy + s[kSweepAhead].op, s[kSweepAhead].np, lane, r[kSweepAhead].p);
+        ring_load(a.B.xy + s[kSweepAhead].oq, s[kSweepAhead].nq, lane, r[kSweepAhead].q);
       }
     }
     // the chunk's union-tile counts go out in one coalesced store per array,
@@ -1589,6 +1607,7 @@ k_batch_sweep(BatchArgs args) {
     const uint64_t left = ballot(lane < cnt && cr.cls == kClsSweep) & ~wmask;
     if (left) list_append(a.st->m_count, a.m_list, left, i0, lane);
   }
+  wave_stamps(a, 0, t_start, lane);
 }
 
 // ------------------------------------------------------------ medium sweep
@@ -1636,6 +1655,7 @@ __global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs a
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   const BatchArgs& a = args;
   const int lane = c.lane;
+  const unsigned long long t_start = wave_stamp(a);
   const int64_t n_med = (int64_t)a.st->m_count.v;
   // entries per claim: 64, or fewer when the list gives the grid's waves
   // less than 8 claims each
@@ -1672,6 +1692,7 @@ __global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs a
       if (sn.nq > kAheadChunks * kWave) ring_load(a.B.xy + sn.oq, sn.nq, lane, rc.q, kAheadChunks);
     }
   }
+  wave_stamps(a, 1, t_start, lane);
 }
 
 // ----------------------------------------------------------- persistent run
@@ -1692,6 +1713,7 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   c.xcd = (int)(blockIdx.x % (unsigned)kStreams);
   c.home = c.xcd % args.n_queues;
   const BatchArgs& a = args;
+  const unsigned long long t_start = wave_stamp(a);
   unsigned long long n_list[kLptBuckets], n_all = 0;
 #pragma unroll
   for (int b = 0; b < kLptBuckets; ++b) {
@@ -1742,6 +1764,7 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
       I = run_large(c, pi, task);
     if (c.lane == 0) add_counts(a, pi.pair, I);
   }
+  wave_stamps(a, 2, t_start, c.lane);
 }
 
 // ------------------------------------------------------------ setup / reset
@@ -1944,6 +1967,8 @@ int batch_sweep_occupancy() {
   n = n < m ? n : m;
   return n > 0 ? n : 1;
 }
+
+int batch_sweep_waves_per_wg() { return kSweepWaves; }
 
 hipError_t launch_batch_run(const BatchArgs& a, int sweep_grid, int grid, int waves_per_wg, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;

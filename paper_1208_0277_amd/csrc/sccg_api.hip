@@ -43,6 +43,11 @@ struct sccg_ctx {
   int32_t queue_nq = 0, queue_per = 0;  // the layout the queue slots were last cleared for
   unsigned long long* plain_stats = nullptr;
   int stats_on = 0;
+  int stamps_on = 0;
+  // per-wave stamps of the batched kernels (calls with work counters on)
+  unsigned long long* wave_t = nullptr;
+  int64_t wave_cap = 0;                        // waves per kernel the buffer holds
+  int64_t wave_n[kStampedKernels] = {0, 0, 0};  // waves of each kernel in the last stamped call
   uint32_t last_mode = 0;
   // graph cache for the batched sequence
   hipGraphExec_t gexec = nullptr;
@@ -366,7 +371,7 @@ int sccg_destroy(sccg_ctx* c) {
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   void* ptrs[] = {c->metaA,  c->areaA,  c->bigA,        c->metaB,  c->areaB,   c->bigB,    c->big_count,
                   c->err,    c->cls,    c->rec,         c->l_list, c->hbox,    c->st,      c->queue,
-                  c->plain_stats,
+                  c->plain_stats, c->wave_t,
                   c->j_bbox, c->j_grid, c->j_cells,     c->j_cell_base, c->j_sums, c->j_count, c->j_start,
                   c->j_list, c->j_bcount, c->j_bstart};
   for (void* p : ptrs)
@@ -403,9 +408,25 @@ int sccg_reserve(sccg_ctx* c, int64_t na, int64_t nb, int64_t np) {
 
 int sccg_set_stats(sccg_ctx* c, int enable) {
   if (!c) return SCCG_E_ARG;
-  c->stats_on = enable ? 1 : 0;
+  if (enable & ~3) return fail(c, SCCG_E_ARG, "unknown stats flags 0x%x", enable);
+  c->stats_on = enable & 1;
+  c->stamps_on = (enable >> 1) & 1;
   drop_graph(c);
   return SCCG_OK;
+}
+
+int64_t sccg_get_wave_times(sccg_ctx* c, int kernel, int64_t* out, int64_t max_waves) {
+  if (!c) return SCCG_E_ARG;
+  if (kernel < 0 || kernel >= kStampedKernels) return fail(c, SCCG_E_ARG, "kernel %d outside [0, 2]", kernel);
+  if (max_waves < 0 || (max_waves > 0 && !out)) return fail(c, SCCG_E_ARG, "NULL output or max_waves < 0");
+  if (!c->wave_t || c->wave_n[kernel] == 0) return 0;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int64_t n = std::min(max_waves, c->wave_n[kernel]);
+  if (n > 0)
+    HIP_TRY(c, hipMemcpy(out, c->wave_t + 2 * (size_t)kernel * (size_t)c->wave_cap,
+                         2 * sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost));
+  return c->wave_n[kernel];
 }
 
 int sccg_set_timing(sccg_ctx* c, int enable) {
@@ -547,6 +568,25 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   int grid = c->p.grid;
   if (grid == 0) grid = c->cu_count * batch_occupancy(c->p.waves_per_wg);
   const int sweep_grid = c->cu_count * batch_sweep_occupancy();
+  if (c->stamps_on) {
+    // every wave of the sweeps and of the persistent kernel stamps its start and end
+    const int64_t sweep_waves = (int64_t)sweep_grid * batch_sweep_waves_per_wg();
+    const int64_t run_waves = (int64_t)grid * c->p.waves_per_wg;
+    const int64_t want = std::max(sweep_waves, run_waves);
+    if (want > c->wave_cap) {
+      (void)hipStreamSynchronize(c->stream);
+      drop_graph(c);
+      if ((r = grow(c, &c->wave_t, 2 * kStampedKernels * want, "wave stamps"))) {
+        c->wave_cap = 0;
+        return r;
+      }
+      c->wave_cap = want;
+    }
+    ba.wave_t = c->wave_t;
+    ba.wave_cap = (int32_t)c->wave_cap;
+    c->wave_n[0] = c->wave_n[1] = sweep_waves;
+    c->wave_n[2] = run_waves;
+  }
   const bool use_graph = c->stream != nullptr && !(c->p.flags & SCCG_F_NO_GRAPH) && !c->timing_on;
   if (!use_graph) return launch_batched(c, ba, sweep_grid, grid);
   // the graph is keyed on every launch argument
@@ -555,7 +595,7 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
            (long long)A->n_polys, (const void*)A->offsets, (const void*)A->xy,
            (long long)B->n_polys, (const void*)B->offsets, (const void*)B->xy, (long long)n_pairs,
            (const void*)pair_a, (const void*)pair_b, (void*)out_inter, (void*)out_union, ba.queue_cap, ba.n_queues,
-           ba.chunk, ba.heavy_verts, ba.min_cells_to_queue, ba.min_classify_cells, ba.flags, ba.stats_on, grid);
+           ba.chunk, ba.heavy_verts, ba.min_cells_to_queue, ba.min_classify_cells, ba.flags, ba.stats_on | (c->stamps_on << 1), grid);
   if (!c->gexec || c->gkey != key) {
     drop_graph(c);
     hipGraph_t g = nullptr;

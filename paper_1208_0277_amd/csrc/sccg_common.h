@@ -134,7 +134,14 @@ struct BatchArgs {
   int32_t min_classify_cells;    // a leaf-level split classifies its tiles only from this many cells
   uint32_t flags;                // SCCG_F_*
   int32_t stats_on;
+  // nullable: per wave, (start, end) stamps of the device's constant-rate
+  // counter, wave_cap waves per kernel: the sweep, the medium sweep, then
+  // the persistent kernel
+  unsigned long long* wave_t;
+  int32_t wave_cap;
 };
+// kernels whose waves are stamped (see BatchArgs::wave_t)
+constexpr int kStampedKernels = 3;
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s);
 // The sweep (sweep_grid workgroups) then the persistent kernel (grid).
@@ -142,6 +149,7 @@ hipError_t launch_batch_run(const BatchArgs& a, int sweep_grid, int grid, int wa
 int batch_lds_bytes_per_wave();
 int batch_occupancy(int waves_per_wg);
 int batch_sweep_occupancy();
+int batch_sweep_waves_per_wg();
 
 // Set-level Jaccard.
 hipError_t launch_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter, const int64_t* uni,

@@ -40,7 +40,7 @@ def test_profile_summary_needs_the_same_kernel_source_and_params(monkeypatch):
 def test_algorithmic_weights_name_work_counters():
     assert set(bench.ALGO_OPS) <= set(sccg.STAT_KEYS)
     assert all(w > 0 for w in bench.ALGO_OPS.values())
-    assert bench.VALU_PEAK_OPS == 256 * 64 * 2.4e9
+    assert bench.VALU_PEAK_OPS == 256 * 128 * 2.4e9
 
 
 def test_more_than_one_gpu_is_refused():

@@ -619,6 +619,29 @@ def test_batched_stats(wl3s):
     assert s["union_tile_vertices"] > 0 and s["ring_scan_vertices"] > 0
 
 
+def test_wave_stamps(wl3s):
+    """Every wave of the three batched kernels stamps a start and a later end;
+    the kernels run in stream order."""
+    import torch
+    wl, _, _ = wl3s
+    c = sccg.Context(0)
+    assert len(c.wave_times(0)) == 0  # no call with stamps yet
+    c.set_stats(False, stamps=True)
+    run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    spans = []
+    for k in range(3):
+        wt = c.wave_times(k)
+        assert len(wt) >= cus, f"kernel {k}: {len(wt)} waves"
+        assert (wt[:, 0] > 0).all() and (wt[:, 1] >= wt[:, 0]).all(), f"kernel {k}"
+        spans.append((int(wt[:, 0].min()), int(wt[:, 1].max())))
+    # the union sweep ends before the medium sweep starts, and so on
+    assert spans[0][1] <= spans[1][0] and spans[1][1] <= spans[2][0], spans
+    with pytest.raises(sccg.SccgError):
+        c.wave_times(3)
+    c.close()
+
+
 def test_kernel_timing(wl3s):
     wl, _, _ = wl3s
     c = sccg.Context(0)
