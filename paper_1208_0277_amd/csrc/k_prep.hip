@@ -127,70 +127,133 @@ hipError_t launch_validate(const Polys& P, int64_t* first_bad, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------- Jaccard
-// Per-set sums; J' by the exact ratio sum of fix192.h.
-__global__ void __launch_bounds__(256) k_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter,
-                                                 const int64_t* uni, uint32_t flags, int64_t* sum_i,
-                                                 int64_t* sum_u, int64_t* n_contrib, double* jout,
-                                                 double* jprime) {
-  __shared__ uint64_t red[4][256];
-  __shared__ uint64_t fx[3][256];
+// Per-set sums of Eq. 1 over the pairs of each set; J' by the exact ratio
+// sum of fix192.h.  Workgroups claim chunks of kJacChunk consecutive pairs
+// of the whole pair range, so that a large set is shared by many
+// workgroups and many small sets by one.  For each set a chunk overlaps,
+// the workgroup reduces its part and adds it to the set's accumulator:
+// 64-bit atomics for the integer sums, and for the Fix192 ratio sum six
+// 32-bit limbs, each added into a 64-bit counter (carry-save: a set gets at
+// most 2^31 / kJacChunk + 1 additions, far from overflowing a counter).
+// Integer and fixed-point addition do not depend on order, so the result is
+// the same bits as any sequential sum.  A second pass normalizes the limbs
+// and divides.
+constexpr int kJacChunk = 4096;
+
+__global__ void k_jaccard_clear(JacAcc* acc, int64_t n_sets, unsigned long long* next) {
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(acc);
+  const int64_t n = n_sets * (int64_t)(sizeof(JacAcc) / 8);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *next = 0;
+}
+
+__global__ void __launch_bounds__(256) k_jaccard_chunks(int64_t n_sets, const int64_t* set_off,
+                                                        const int64_t* inter, const int64_t* uni, uint32_t flags,
+                                                        bool want_jp, JacAcc* acc, unsigned long long* next) {
+  __shared__ uint64_t red[6][256];
+  __shared__ int64_t chunk_s;
   const bool include_zero = (flags & SCCG_J_INCLUDE_ZERO) != 0;
-  const bool want_jp = jprime != nullptr;
-  for (int64_t s = blockIdx.x; s < n_sets; s += gridDim.x) {
-    const int64_t o0 = set_off[s], o1 = set_off[s + 1];
-    uint64_t si = 0, su = 0, nn = 0;
-    Fix192 acc;
-    for (int64_t k = o0 + threadIdx.x; k < o1; k += blockDim.x) {
-      const int64_t I = inter[k], U = uni[k];
-      if (!include_zero && I == 0) continue;
-      si += (uint64_t)I;
-      su += (uint64_t)U;
-      nn += 1;
-      if (want_jp && U > 0) acc.add_ratio((double)I / (double)U);
-    }
-    red[0][threadIdx.x] = si;
-    red[1][threadIdx.x] = su;
-    red[2][threadIdx.x] = nn;
-    fx[0][threadIdx.x] = acc.w[0];
-    fx[1][threadIdx.x] = acc.w[1];
-    fx[2][threadIdx.x] = acc.w[2];
+  const int64_t base = set_off[0], end = set_off[n_sets];  // the pairs of all sets
+  const int64_t n_chunks = (end - base + kJacChunk - 1) / kJacChunk;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) chunk_s = (int64_t)atomicAdd(next, 1ull);
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-      if ((int)threadIdx.x < h) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + h];
-        red[1][threadIdx.x] += red[1][threadIdx.x + h];
-        red[2][threadIdx.x] += red[2][threadIdx.x + h];
-        Fix192 a, b;
-        a.w[0] = fx[0][threadIdx.x]; a.w[1] = fx[1][threadIdx.x]; a.w[2] = fx[2][threadIdx.x];
-        b.w[0] = fx[0][threadIdx.x + h]; b.w[1] = fx[1][threadIdx.x + h]; b.w[2] = fx[2][threadIdx.x + h];
-        a.add(b);
-        fx[0][threadIdx.x] = a.w[0]; fx[1][threadIdx.x] = a.w[1]; fx[2][threadIdx.x] = a.w[2];
+    const int64_t chunk = chunk_s;
+    __syncthreads();
+    if (chunk >= n_chunks) break;
+    const int64_t c0 = base + chunk * kJacChunk, c1 = min(c0 + (int64_t)kJacChunk, end);
+    // the set holding pair c0: the last s with set_off[s] <= c0
+    int64_t lo = 0, hi = n_sets - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      if (set_off[mid] <= c0) lo = mid;
+      else hi = mid - 1;
+    }
+    for (int64_t s = lo; s < n_sets; ++s) {
+      const int64_t o0 = max(set_off[s], c0), o1 = min(set_off[s + 1], c1);
+      uint64_t si = 0, su = 0, nn = 0;
+      Fix192 fx;
+      for (int64_t k = o0 + tid; k < o1; k += blockDim.x) {
+        const int64_t I = inter[k], U = uni[k];
+        if (!include_zero && I == 0) continue;
+        si += (uint64_t)I;
+        su += (uint64_t)U;
+        nn += 1;
+        if (want_jp && U > 0) fx.add_ratio((double)I / (double)U);
+      }
+      red[0][tid] = si;
+      red[1][tid] = su;
+      red[2][tid] = nn;
+      red[3][tid] = fx.w[0];
+      red[4][tid] = fx.w[1];
+      red[5][tid] = fx.w[2];
+      __syncthreads();
+      for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+          red[0][tid] += red[0][tid + h];
+          red[1][tid] += red[1][tid + h];
+          red[2][tid] += red[2][tid + h];
+          Fix192 x, y;
+          x.w[0] = red[3][tid]; x.w[1] = red[4][tid]; x.w[2] = red[5][tid];
+          y.w[0] = red[3][tid + h]; y.w[1] = red[4][tid + h]; y.w[2] = red[5][tid + h];
+          x.add(y);
+          red[3][tid] = x.w[0]; red[4][tid] = x.w[1]; red[5][tid] = x.w[2];
+        }
+        __syncthreads();
+      }
+      if (tid == 0 && red[2][0] != 0) {
+        JacAcc& A = acc[s];
+        atomicAdd(&A.si, (unsigned long long)red[0][0]);
+        atomicAdd(&A.su, (unsigned long long)red[1][0]);
+        atomicAdd(&A.nn, (unsigned long long)red[2][0]);
+        for (int k = 0; k < 3; ++k) {
+          const uint64_t w = red[3 + k][0];
+          if (w & 0xffffffffull) atomicAdd(&A.limb[2 * k], (unsigned long long)(w & 0xffffffffull));
+          if (w >> 32) atomicAdd(&A.limb[2 * k + 1], (unsigned long long)(w >> 32));
+        }
       }
       __syncthreads();
+      if (set_off[s + 1] >= c1) break;
     }
-    if (threadIdx.x == 0) {
-      const int64_t tI = (int64_t)red[0][0], tU = (int64_t)red[1][0], tn = (int64_t)red[2][0];
-      sum_i[s] = tI;
-      sum_u[s] = tU;
-      n_contrib[s] = tn;
-      jout[s] = tU > 0 ? (double)tI / (double)tU : 0.0;
-      if (want_jp) {
-        Fix192 a;
-        a.w[0] = fx[0][0]; a.w[1] = fx[1][0]; a.w[2] = fx[2][0];
-        jprime[s] = tn > 0 ? a.to_double() / (double)tn : 0.0;
-      }
+  }
+}
+
+__global__ void k_jaccard_final(int64_t n_sets, const JacAcc* acc, bool want_jp, int64_t* sum_i, int64_t* sum_u,
+                                int64_t* n_contrib, double* jout, double* jprime) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_sets) return;
+  const JacAcc A = acc[s];
+  const int64_t tI = (int64_t)A.si, tU = (int64_t)A.su, tn = (int64_t)A.nn;
+  sum_i[s] = tI;
+  sum_u[s] = tU;
+  n_contrib[s] = tn;
+  jout[s] = tU > 0 ? (double)tI / (double)tU : 0.0;
+  if (want_jp) {
+    // limb k weighs 2^(32 k): add them up with carries into three words
+    Fix192 f;
+    for (int k = 0; k < 6; ++k) {
+      Fix192 t;
+      const uint64_t v = A.limb[k];
+      const int sh = 32 * k, w = sh >> 6, off = sh & 63;
+      t.w[w] = v << off;
+      if (off && w + 1 < 3) t.w[w + 1] = v >> (64 - off);
+      f.add(t);
     }
-    __syncthreads();
+    jprime[s] = tn > 0 ? f.to_double() / (double)tn : 0.0;
   }
 }
 
 hipError_t launch_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter, const int64_t* uni,
                           uint32_t flags, int64_t* sum_i, int64_t* sum_u, int64_t* n_contrib, double* j,
-                          double* jprime, hipStream_t s) {
+                          double* jprime, JacAcc* acc, unsigned long long* next, int grid, hipStream_t s) {
   if (n_sets <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)(n_sets < 65536 ? n_sets : 65536);
-  hipLaunchKernelGGL(k_jaccard, dim3(grid), dim3(256), 0, s, n_sets, set_off, inter, uni, flags, sum_i, sum_u,
-                     n_contrib, j, jprime);
+  hipLaunchKernelGGL(k_jaccard_clear, dim3(256), dim3(256), 0, s, acc, n_sets, next);
+  hipLaunchKernelGGL(k_jaccard_chunks, dim3(grid), dim3(256), 0, s, n_sets, set_off, inter, uni, flags,
+                     jprime != nullptr, acc, next);
+  hipLaunchKernelGGL(k_jaccard_final, dim3((unsigned)((n_sets + 255) / 256)), dim3(256), 0, s, n_sets, acc,
+                     jprime != nullptr, sum_i, sum_u, n_contrib, j, jprime);
   return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ struct sccg_ctx {
   int32_t* j_list = nullptr;
   int32_t* j_bcount = nullptr;
   int64_t* j_bstart = nullptr;
+  JacAcc* j_acc = nullptr;  // per-set accumulators of sccg_jaccard_sets
   int64_t j_cap[10] = {};
   // kernel timing
   int timing_on = 0;
@@ -373,7 +374,7 @@ int sccg_destroy(sccg_ctx* c) {
                   c->err,    c->cls,    c->rec,         c->l_list, c->hbox,    c->st,      c->queue,
                   c->plain_stats, c->wave_t,
                   c->j_bbox, c->j_grid, c->j_cells,     c->j_cell_base, c->j_sums, c->j_count, c->j_start,
-                  c->j_list, c->j_bcount, c->j_bstart};
+                  c->j_list, c->j_bcount, c->j_bstart, c->j_acc};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -698,8 +699,12 @@ int sccg_jaccard_sets(sccg_ctx* c, int64_t n_sets, const int64_t* set_pair_off, 
   if (!set_pair_off || !inter || !uni || !out_sum_i || !out_sum_u || !out_n_contrib || !out_j)
     return fail(c, SCCG_E_ARG, "NULL array");
   HIP_TRY(c, hipSetDevice(c->device));
+  int r;
+  // one accumulator per set, and past them the chunk counter
+  if ((r = need(c, &c->j_acc, c->j_cap[8], n_sets + 1, "set accumulators"))) return r;
+  const int grid = c->cu_count * 4;
   hipError_t e = launch_jaccard(n_sets, set_pair_off, inter, uni, flags, out_sum_i, out_sum_u, out_n_contrib, out_j,
-                                out_jprime, c->stream);
+                                out_jprime, c->j_acc, &c->j_acc[n_sets].si, grid, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "jaccard");
   return SCCG_OK;
 }

@@ -151,10 +151,15 @@ int batch_occupancy(int waves_per_wg);
 int batch_sweep_occupancy();
 int batch_sweep_waves_per_wg();
 
-// Set-level Jaccard.
+// Set-level Jaccard: per-set accumulators (a cache line each), a chunk
+// counter and `grid` workgroups that claim chunks of the pair range.
+struct alignas(128) JacAcc {
+  unsigned long long si, su, nn;
+  unsigned long long limb[6];  // Fix192 ratio sum as 32-bit limbs, carry-save
+};
 hipError_t launch_jaccard(int64_t n_sets, const int64_t* set_off, const int64_t* inter, const int64_t* uni,
                           uint32_t flags, int64_t* sum_i, int64_t* sum_u, int64_t* n_contrib, double* j,
-                          double* jprime, hipStream_t s);
+                          double* jprime, JacAcc* acc, unsigned long long* next, int grid, hipStream_t s);
 
 // Ring validation.
 hipError_t launch_validate(const Polys& P, int64_t* first_bad, hipStream_t s);

@@ -605,6 +605,29 @@ def test_jaccard_sets(ctx, wl3s, include_zero):
     assert np.array_equal(jp.cpu().numpy(), ojp)
 
 
+@pytest.mark.parametrize("layout", ["one_set", "tiny_sets", "offset_start"])
+def test_jaccard_sets_layouts(ctx, wl3s, layout):
+    """Set sums against the oracle when one set spans every chunk of the
+    pair range, when a chunk holds hundreds of sets, and when the first set
+    starts past pair 0."""
+    import torch
+    wl, eI, eU = wl3s
+    n = wl.n_pairs
+    if layout == "one_set":
+        so = np.array([0, n], np.int64)
+    elif layout == "tiny_sets":
+        so = np.concatenate([np.arange(0, n, 7), [n]]).astype(np.int64)
+    else:
+        so = np.array([12345, 12345, 20000, 40001, n - 3], np.int64)
+    tI, tU = torch.from_numpy(eI).cuda(), torch.from_numpy(eU).cuda()
+    si, su, nn, j, jp = ctx.jaccard_sets(torch.from_numpy(so).cuda(), tI, tU)
+    ctx.sync()
+    osi, osu, onn, oj, ojp = oracle.jaccard_sets(so, eI, eU)
+    assert np.array_equal(si.cpu().numpy(), osi) and np.array_equal(su.cpu().numpy(), osu)
+    assert np.array_equal(nn.cpu().numpy(), onn)
+    assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(jp.cpu().numpy(), ojp)
+
+
 def test_batched_stats(wl3s):
     wl, _, _ = wl3s
     c = sccg.Context(0, min_classify_cells=1)
