@@ -351,9 +351,77 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
   }
 }
 
-__device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv, int lane, Meta& m, int64_t& area) {
-  RingRegs r;
-  ring_extent(xy, o, nv, lane, r, m, area);
+// The same extent and area for the prepass of listed (long) rings: each
+// lane loads its vertices and their successors directly, kScanBatch chunks
+// of 64 per round trip, so that a long ring costs few memory latencies.
+constexpr int kScanBatch = 4;
+__device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv64, int lane, Meta& m, int64_t& area) {
+  const int nv = uniform((int)nv64);
+  m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};  // covers nothing
+  area = 0;
+  if (nv <= 0) return;
+  const int2* R = xy + o;
+  const int2 f = R[0];
+  int x0 = f.x, y0 = f.y, x1 = f.x, y1 = f.y;
+  uint32_t twice = 0;  // relative to the first vertex, wrapping (exact for extents below 2^14)
+#pragma unroll 1
+  for (int base = 0; base < nv; base += kScanBatch * kWave) {
+    int2 v[kScanBatch], w[kScanBatch];
+#pragma unroll
+    for (int c = 0; c < kScanBatch; ++c) {
+      v[c] = w[c] = f;
+      if (base + c * kWave < nv) {
+        const int k = base + c * kWave + lane;
+        v[c] = R[min(k, nv - 1)];
+        w[c] = R[k + 1 < nv ? k + 1 : 0];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kScanBatch; ++c) {
+      if (base + c * kWave + lane < nv) {
+        x0 = min(x0, v[c].x);
+        y0 = min(y0, v[c].y);
+        x1 = max(x1, v[c].x);
+        y1 = max(y1, v[c].y);
+        twice += (uint32_t)__mul24(v[c].x - f.x, w[c].y - f.y) - (uint32_t)__mul24(w[c].x - f.x, v[c].y - f.y);
+      }
+    }
+  }
+  m.x0 = wave_min_i32(x0);
+  m.y0 = wave_min_i32(y0);
+  m.x1 = wave_max_i32(x1);
+  m.y1 = wave_max_i32(y1);
+  if (side_u(m.x0, m.x1) < 16384u && side_u(m.y0, m.y1) < 16384u) {
+    const int32_t t = (int32_t)wave_sum_u32(twice);
+    area = (int64_t)(t < 0 ? -(int64_t)t : (int64_t)t) / 2;
+  } else {
+    // twice the area is at most 2^63 in size, so the magnitude of the
+    // wrapped 64-bit sum is exact in unsigned form
+    uint64_t tw = 0;
+#pragma unroll 1
+    for (int base = 0; base < nv; base += kScanBatch * kWave) {
+      int2 v[kScanBatch], w[kScanBatch];
+#pragma unroll
+      for (int c = 0; c < kScanBatch; ++c) {
+        v[c] = w[c] = f;
+        if (base + c * kWave < nv) {
+          const int k = base + c * kWave + lane;
+          v[c] = R[min(k, nv - 1)];
+          w[c] = R[k + 1 < nv ? k + 1 : 0];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kScanBatch; ++c)
+        if (base + c * kWave + lane < nv)
+          tw += (uint64_t)((int64_t)v[c].x * w[c].y) - (uint64_t)((int64_t)w[c].x * v[c].y);
+    }
+    const uint64_t t64 = wave_sum_u64(tw);
+    area = (int64_t)(((int64_t)t64 < 0 ? 0 - t64 : t64) / 2);
+  }
+  if (m.x0 < -kMaxCoord || m.y0 < -kMaxCoord || m.x1 > kMaxCoord || m.y1 > kMaxCoord) {
+    m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+    area = 0;
+  }
 }
 
 __device__ __forceinline__ bool coords_bad(const Meta& m, int64_t nv) {
