@@ -36,7 +36,8 @@ WORKLOADS = {
        "PixelBox-NoSep and PixelBox (batched) and the plain Algorithm 1 kernel, each autotuned",
     5: "serving: Poisson job arrivals at 5, 20 and 80 jobs/s, 600 jobs per rate (first 20 not measured), "
        "each job a window of 1e3-5e5 pairs (log-uniform) of a pinned 500,000-pair uniform-mix corpus",
-    4: "set-level: 64 tiles of 8192^2 px, per tile set A packed with 10-60 px shapes and set B = 85% shifted "
+    4: "set-level: 64 tiles of 8192^2 px, per tile set A of 10-60 px shapes packed pixel-disjoint (skyline "
+       "drop, 37.7k per tile) and set B = 85% shifted "
        "and dilated/eroded copies + 15% fresh shapes, candidate pairs from a 64-px grid MBR join; "
        "step = pair counts + per-tile Jaccard",
     3: "heavy-tailed mix: 2,000,000 pairs, MBR side lognormal (median 24 px, clipped 8-400 px), "

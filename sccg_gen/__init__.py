@@ -175,7 +175,8 @@ class SetWorkload:
 def sets(n_tiles: int = 64, tile_side: int = 8192, cell: int = 64, seed: int | None = None,
          threads: int | None = None) -> SetWorkload:
     """Workload 4: n_tiles tiles of tile_side^2 px.  In each tile set A is
-    filled with workload-2 shapes (10-60 px, 16-120 vertices) by shelf packing
+    filled pixel-disjoint with workload-2 shapes (10-60 px, 16-120 vertices),
+    each dropped onto a per-column skyline near a cursor that walks the tile,
     until the tile is full; set B holds a shifted, dilated or eroded copy of
     85% of A's shapes plus 15% * |A| fresh shapes at uniform positions."""
     lib = _load()

@@ -418,9 +418,14 @@ void gen_pairs(Dataset& D, int config, uint64_t seed, int64_t n, int n_threads, 
 
 // ------------------------------------------------------- set-level tiles ----
 // Workload 4: n_tiles square tiles; in each, set A is filled with
-// workload-2 shapes by shelf packing until the tile is full; set B holds, for
-// 85% of A's shapes (one draw per shape), a shifted and dilated or eroded
-// copy, plus 15% * |A| fresh shapes at uniform positions in the tile.
+// workload-2 shapes until the tile is full, pixel-disjoint: a cursor walks
+// the tile's columns left to right (wrapping), and each shape drops onto a
+// per-column skyline (the row above the highest pixel placed in the column)
+// until one of its columns touches, at the lowest such drop within half its
+// width of the cursor, so that shapes nest into the profile of the row
+// below; set B holds, for 85% of A's shapes (one draw per shape),
+// a shifted and dilated or eroded copy, plus 15% * |A| fresh shapes at
+// uniform positions in the tile.
 // Candidate pairs come from a uniform-grid join of the MBRs (cell side
 // `cell`): a pair is emitted when the MBRs share at least one pixel, once, in
 // the cell that holds the lower-left pixel of their intersection.
@@ -432,9 +437,13 @@ struct TileSets {
 
 void gen_tile(TileSets& T, uint64_t seed, int64_t tile, int64_t tile_side, int64_t ox, int64_t oy, int cell) {
   const uint64_t base = (uint64_t)tile << 32;
-  // A: shelf packing, pad 1
-  int64_t cx = 0, cy = 0, shelf = 0;
-  for (int64_t k = 0;; ++k) {
+  // A: skyline drop (see above; each shape takes the lowest drop within
+  // half its width of the cursor); a run of shapes that no longer fit below
+  // the top of the tile ends the tile
+  std::vector<int64_t> sky((size_t)tile_side, 0);
+  std::vector<int64_t> lo, hi;
+  int64_t cx = 0, misses = 0;
+  for (int64_t k = 0; misses < 256; ++k) {
     Rng g(seed, base | (uint64_t)k);
     bool blob = false;
     ShapeSpec sp = spec_for(2, g, blob);
@@ -442,13 +451,40 @@ void gen_tile(TileSets& T, uint64_t seed, int64_t tile, int64_t tile_side, int64
     int used = 0;
     make_shape(g, sp, A, &used);
     if (A.ring.size() < 8) continue;
-    const int64_t w = A.mask.w + 2, h = A.mask.h + 2;
-    if (cx + w > tile_side) { cx = 0; cy += shelf; shelf = 0; }
-    if (cy + h > tile_side) break;
-    T.ax.push_back(ox + cx + 1);
-    T.ay.push_back(oy + cy + 1);
+    const int64_t w = A.mask.w, h = A.mask.h;
+    if (w > tile_side || h > tile_side) continue;
+    if (cx + w > tile_side) cx = 0;
+    // lowest and one past the highest pixel row of each column (a cropped,
+    // connected shape has a pixel in every column)
+    lo.assign((size_t)w, h);
+    hi.assign((size_t)w, 0);
+    for (int64_t y = 0; y < h; ++y)
+      for (int64_t x = 0; x < w; ++x)
+        if (A.mask.at((int)x, (int)y)) {
+          lo[(size_t)x] = std::min(lo[(size_t)x], y);
+          hi[(size_t)x] = std::max(hi[(size_t)x], y + 1);
+        }
+    // the lowest drop among positions around the cursor
+    int64_t y0 = INT64_MAX, bx = cx;
+    for (int64_t x0 = std::max<int64_t>(0, cx - w / 2); x0 <= std::min(cx + w / 2, tile_side - w); x0 += 2) {
+      int64_t y = 0;
+      for (int64_t x = 0; x < w && y < y0; ++x) y = std::max(y, sky[(size_t)(x0 + x)] - lo[(size_t)x]);
+      if (y < y0) {
+        y0 = y;
+        bx = x0;
+      }
+    }
+    cx = bx;
+    if (y0 + h > tile_side) {
+      ++misses;
+      cx += w;
+      continue;
+    }
+    misses = 0;
+    for (int64_t x = 0; x < w; ++x) sky[(size_t)(cx + x)] = y0 + hi[(size_t)x];
+    T.ax.push_back(ox + cx);
+    T.ay.push_back(oy + y0);
     cx += w;
-    shelf = std::max(shelf, h);
     // B derived from A with probability 0.85
     Rng gb(seed ^ 0x5bd1e995ull, base | (uint64_t)k);
     if (gb.unit() < 0.85) {

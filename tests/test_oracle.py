@@ -297,8 +297,10 @@ def test_jprime_exact_sum():
 
 
 def test_set_workload_join_is_exact():
-    """Workload 4's candidate pairs are exactly the (A, B) pairs whose MBRs
-    share a pixel, each once (brute force over small tiles)."""
+    """Workload 4's candidate pairs are exactly the (A, B) pairs of one tile
+    whose MBRs share a pixel, each once (brute force over small tiles; a B
+    shape near a tile's edge may reach into the next tile, whose A shapes
+    belong to another set)."""
     wl = sccg_gen.sets(n_tiles=2, tile_side=768, cell=64)
 
     def mbrs(P):
@@ -314,13 +316,15 @@ def test_set_workload_join_is_exact():
     by_b = {}
     for (a, b) in got:
         by_b.setdefault(b, set()).add(a)
-    for t in range(1):
-        for b in range(len(mb)):
-            x0 = np.maximum(ma[:, 0], mb[b, 0])
-            y0 = np.maximum(ma[:, 1], mb[b, 1])
-            x1 = np.minimum(ma[:, 2], mb[b, 2])
-            y1 = np.minimum(ma[:, 3], mb[b, 3])
-            hit = set(a_ids[(x0 < x1) & (y0 < y1)].tolist())
+    for t in range(len(wl.a_set_off) - 1):
+        a_lo, a_hi = int(wl.a_set_off[t]), int(wl.a_set_off[t + 1])
+        ids = a_ids[a_lo:a_hi]
+        for b in range(int(wl.b_set_off[t]), int(wl.b_set_off[t + 1])):
+            x0 = np.maximum(ma[a_lo:a_hi, 0], mb[b, 0])
+            y0 = np.maximum(ma[a_lo:a_hi, 1], mb[b, 1])
+            x1 = np.minimum(ma[a_lo:a_hi, 2], mb[b, 2])
+            y1 = np.minimum(ma[a_lo:a_hi, 3], mb[b, 3])
+            hit = set(ids[(x0 < x1) & (y0 < y1)].tolist())
             assert hit == by_b.get(b, set()), b
     assert wl.stats["polys_a"] > 0 and wl.n_pairs > 0
 
