@@ -1258,22 +1258,23 @@ __device__ __forceinline__ uint32_t union_tile_count(const uint64_t* slots, int 
 
 // One ring of at most 64 vertices (lane L: vertex L; lanes past the end hold
 // the last vertex again) scattered into a union tile's 64-bit slots from
-// `base` on (see union_counts).  Returns the vertices scattered.
+// `base` on (see union_counts).  Each lane finds whether its vertex is a
+// corner from its two neighbours' x (the last vertex's successor is the
+// first, the first's predecessor the last), so that the lane masks combine
+// in few scalar steps.  Returns the vertices scattered.
 __device__ __forceinline__ uint32_t scatter_small_ring(uint64_t* slots, int2 v, int nr, int x0, int y0, int W, int base,
                                                        int lane) {
   if (nr <= 0) return 0;
   const int le = nr - 1;
-  const uint64_t close = __builtin_amdgcn_readlane(v.x, le) == __builtin_amdgcn_readlane(v.x, 0) ? 1ull : 0ull;
-  // b: the vertex's edge to its successor is vertical (the last vertex's
-  // successor is the first)
-  const uint64_t b = (ballot(v.x == next_lane_x(v.x)) & lanes_below_k(le)) | (close << le);
-  // the vertex's two edges differ
-  const uint64_t cm = (b ^ ((b << 1) | close)) & lanes_upto_m(nr);
+  const int x_first = __builtin_amdgcn_readfirstlane(v.x), x_last = __builtin_amdgcn_readlane(v.x, le);
+  // the neighbours' x, read by every lane before the selections
+  const int xn = next_lane_x(v.x), xb = __builtin_amdgcn_update_dpp(0, v.x, 0x138, 0xf, 0xf, false);  // wave_shr:1
+  const int xs = lane == le ? x_first : xn;
+  const int xp = lane == 0 ? x_last : xb;
   const int dx = v.x - x0, ty = v.y - y0;
-  const uint64_t keep = cm & ballot(dx > 0) & ballot(ty < kWave);
-  uint64_t* sp = slots + (base + W - dx);
-  if (lane_in(keep)) slot_xor(sp, 0, ~0ull << ty);
-  return (uint32_t)__popcll(keep);
+  const bool keep = (lane <= le) & ((v.x == xs) != (v.x == xp)) & (dx > 0) & (ty < kWave);
+  if (keep) slot_xor(slots + (base + W - dx), 0, ~0ull << ty);
+  return (uint32_t)__popcll(ballot(keep));
 }
 
 // A pair whose rings have at most 64 vertices each, one chunk per ring in
@@ -1595,6 +1596,23 @@ __device__ __forceinline__ int64_t claim_chunk(Counter* next, int64_t n, int chu
   return -1;
 }
 
+// The rings of a sweep pair (lane L: vertices L and 64 + L, clamped to the
+// last), or for any other record a read of `dummy`: the same loads in every
+// case, so that the compiler can count the loads in flight and wait only
+// for those of the pair in hand, not for the ones just issued ahead of it.
+__device__ __forceinline__ void sweep_load(const BatchArgs& a, const SweepRec& s, const int2* dummy, int lane,
+                                           PairRegs<kUnionChunks>& r) {
+  const bool mine = s.cls == kClsSweep;
+  const int2* P = mine && s.np > 0 ? a.A.xy + s.op : dummy;
+  const int2* Q = mine && s.nq > 0 ? a.B.xy + s.oq : dummy;
+  const int lp = mine ? max(s.np - 1, 0) : 0, lq = mine ? max(s.nq - 1, 0) : 0;
+#pragma unroll
+  for (int c = 0; c < kUnionChunks; ++c) {
+    r.p[c] = P[min(c * kWave + lane, lp)];
+    r.q[c] = Q[min(c * kWave + lane, lq)];
+  }
+}
+
 // Pair j of the chunk (a sweep pair): counted on its union tile, leaving
 // I | U << 16 in lane j of `packed` and bit j in `wmask` (written out with
 // the chunk); a pair left out (union box larger than a leaf tile) goes to
@@ -1643,13 +1661,11 @@ k_batch_sweep(BatchArgs args) {
     // loads are in flight while the pair in hand is processed
     SweepRec s[kSweepAhead + 1];
     PairRegs<kUnionChunks> r[kSweepAhead + 1];
+    const int2* dummy = reinterpret_cast<const int2*>(a.rec + i0);
 #pragma unroll
     for (int k = 0; k <= kSweepAhead; ++k) {
       s[k] = k < cnt ? sweep_rec(cr, k) : SweepRec{0, 0, 0, 0, kClsDone};
-      if (s[k].cls == kClsSweep) {
-        ring_load(a.A.xy + s[k].op, s[k].np, lane, r[k].p);
-        ring_load(a.B.xy + s[k].oq, s[k].nq, lane, r[k].q);
-      }
+      sweep_load(a, s[k], dummy, lane, r[k]);
     }
 #pragma unroll 1
     for (int j = 0; j < cnt; ++j) {
@@ -1661,10 +1677,7 @@ k_batch_sweep(BatchArgs args) {
       }
       const int jn = j + kSweepAhead + 1;
       s[kSweepAhead] = jn < cnt ? sweep_rec(cr, jn) : SweepRec{0, 0, 0, 0, kClsDone};
-      if (s[kSweepAhead].cls == kClsSweep) {
-        ring_load(a.A.xy + s[kSweepAhead].op, s[kSweepAhead].np, lane, r[kSweepAhead].p);
-        ring_load(a.B.xy + s[kSweepAhead].oq, s[kSweepAhead].nq, lane, r[kSweepAhead].q);
-      }
+      sweep_load(a, s[kSweepAhead], dummy, lane, r[kSweepAhead]);
     }
     // the chunk's union-tile counts go out in one coalesced store per array,
     // the sweep pairs it left out to the medium list with one reservation
