@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -135,7 +136,7 @@ SATURATED_RATE = 2000.0
 #: workload's seed plus this offset
 CALIBRATION_SEED_OFFSET = 1_000_003
 
-PROFILE_STEMS = {3: "k_batch_run_heavy_tailed_2M", 4: "k_batch_run_set_level_64_tiles"}
+PROFILE_STEMS = {3: "k_batch_call_heavy_tailed_2M", 4: "k_batch_call_set_level_64_tiles"}
 
 
 def tail_summary(wt):
@@ -254,7 +255,6 @@ def run_serving(rates, jobs, cpu_threads=0, cpu_max_pairs=0):
     to results on the host (the server's clock).  Every job is checked
     against the oracle's counts of the corpus.  Returns (per-rate records,
     all bit-exact, corpus pairs)."""
-    import math
     import threading
 
     import torch

@@ -2,7 +2,8 @@
 
 Coordinate descent over a small candidate grid: each parameter is swept in
 turn with the others held at the best values found so far; a candidate is
-scored by pairs/s over a few timed calls on the caller's workload.  Every
+scored by pairs/s over a few timed calls on the caller's workload and
+replaces the best only when it is faster by more than MARGIN.  Every
 candidate must reproduce the first candidate's counts bit for bit (no tuning
 parameter may change a result); a candidate that does not is an error.
 Results are cached in JSON, keyed by GPU architecture, CU count, mode and a
@@ -34,6 +35,9 @@ PLAIN_SPACE = [
     ("wg_size", [64, 128]),
 ]
 
+#: fraction by which a candidate must beat the best so far to replace it
+MARGIN = 0.02
+
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sccg", "autotune.json")
 
 
@@ -51,7 +55,7 @@ def _device_key() -> str:
     return f"{arch}/{p.multi_processor_count}"
 
 
-def tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key="", steps=3, use_cache=True,
+def tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key="", steps=8, use_cache=True,
          space=None, log=None):
     """Return the best parameter dict for this workload and leave it set on ctx."""
     space = space or (BATCHED_SPACE if mode == sccg.SCCG_BATCHED else PLAIN_SPACE)
@@ -102,7 +106,9 @@ def tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key="", ste
             cand = dict(best)
             cand[name] = v
             t = score(cand)
-            if t < best_t:
+            # a candidate must win by more than timing noise, so that
+            # repeated tunings of one workload settle on the same values
+            if t < best_t * (1.0 - MARGIN):
                 best, best_t = cand, t
     p = dict(base)
     p.update(best)
