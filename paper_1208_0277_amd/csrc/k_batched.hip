@@ -1101,6 +1101,17 @@ struct PairRegs {
 // hand (deeper lookahead measured no faster: the sweep is bound by
 // instruction issue, not by load latency)
 constexpr int kSweepAhead = 1;
+#ifndef SCCG_RUN_STEAL
+#define SCCG_RUN_STEAL 0
+#endif
+// whether the persistent kernel's waves also claim listed pairs from other
+// XCDs' streams
+constexpr bool kRunSteal = SCCG_RUN_STEAL != 0;
+#ifndef SCCG_SWEEP_STEAL
+#define SCCG_SWEEP_STEAL 0
+#endif
+// whether the sweeps' waves also claim from other XCDs' streams
+constexpr bool kSweepSteal = SCCG_SWEEP_STEAL != 0;
 
 // Chunks [c0, c1) of a ring of nr vertices.
 template <int N>
@@ -1648,7 +1659,11 @@ k_batch_sweep(BatchArgs args) {
   const int lane = c.lane;
   const bool union_ok = direct_union(a) || !(a.flags & SCCG_F_NO_UNION_TILE);
   const unsigned long long t_start = wave_stamp(a);
-  uint32_t s_empty = 0;  // claim streams found exhausted (wave-uniform)
+  // claim streams found exhausted (wave-uniform); a wave claims only from
+  // its own XCD's stream (the streams hold equal interleaved shares), so
+  // that running dry costs it one claim, not one per stream (a grid too
+  // small to give every stream a workgroup claims from all of them)
+  uint32_t s_empty = kSweepSteal || gridDim.x < (unsigned)kStreams ? 0u : (0xffu & ~(1u << c.xcd));
   for (;;) {
     const int64_t i0 = claim_chunk(a.st->s_next, a.n_pairs, a.chunk, c.xcd, lane, s_empty);
     if (i0 < 0) break;
@@ -1742,7 +1757,7 @@ __global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs a
   // less than 8 claims each
   const int64_t per_wave = n_med / ((int64_t)gridDim.x * kSweepWaves * 8);
   const int chunk = (int)max((int64_t)1, min((int64_t)kWave, per_wave));
-  uint32_t m_empty = 0;
+  uint32_t m_empty = kSweepSteal || gridDim.x < (unsigned)kStreams ? 0u : (0xffu & ~(1u << c.xcd));
   for (;;) {
     const int64_t e0 = claim_chunk(a.st->m_next, n_med, chunk, c.xcd, lane, m_empty);
     if (e0 < 0) break;
@@ -1806,7 +1821,10 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   // the queues.
   const bool queues_used = n_all > 0 && !(a.flags & SCCG_F_NO_SPLIT_QUEUE) && a.min_cells_to_queue <= kWave;
   int bucket = kLptBuckets - 1;  // the bucket being claimed, largest first (wave-uniform)
-  uint32_t l_empty = 0;          // streams of that bucket found exhausted (wave-uniform)
+  // streams of that bucket found exhausted (wave-uniform); as in the sweeps,
+  // a wave claims only from its XCD's stream unless kRunSteal
+  const uint32_t l_start = kRunSteal || gridDim.x < (unsigned)kStreams ? 0u : (0xffu & ~(1u << c.xcd));
+  uint32_t l_empty = l_start;
   for (;;) {
     PairInfo pi;
     uint64_t task = 0;  // 0: a box that fits one leaf tile
@@ -1823,7 +1841,7 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
       const int64_t e = claim_chunk(a.st->l_next[bucket], (int64_t)nb, 1, c.xcd, c.lane, l_empty);
       if (e < 0) {
         bucket = uniform(bucket - 1);
-        l_empty = 0;
+        l_empty = l_start;
         continue;
       }
       pi = heavy_info(a, (int64_t)a.l_list[(int64_t)bucket * a.n_pairs + e]);

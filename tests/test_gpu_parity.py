@@ -137,7 +137,8 @@ def test_config3_full_size():
     import json
     import os
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    with open(os.path.join(root, "profiles", "k_batch_run_heavy_tailed_2M.json")) as f:
+    import bench
+    with open(os.path.join(root, "profiles", bench.PROFILE_STEMS[3] + ".json")) as f:
         params = json.load(f)["params"]
     wl = sccg_gen.pairs(3, 2_000_000)
     print(f"[gpu] generated {len(wl.pa)} pairs, params {params}", flush=True)
