@@ -156,8 +156,8 @@ def tail_summary(wt):
 def profile_summary(workload: int, params: dict):
     """The committed counter summary of the batched kernels on this workload
     (profiles/<stem>.json), or None when it is missing, was taken on another
-    version of the kernel source, or with other tuning parameters than the
-    timed run's."""
+    version of the kernel source, or with other tuning parameters than
+    `params` (None: any parameters)."""
     stem = PROFILE_STEMS.get(workload)
     if stem is None:
         return None
@@ -171,7 +171,8 @@ def profile_summary(workload: int, params: dict):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    if {k: int(v) for k, v in (d.get("params") or {}).items()} != {k: int(v) for k, v in params.items()}:
+    if params is not None and \
+            {k: int(v) for k, v in (d.get("params") or {}).items()} != {k: int(v) for k, v in params.items()}:
         return None
     return d
 
@@ -572,9 +573,14 @@ def main(argv=None):
         elif not args.no_autotune:
             t = time.perf_counter()
             ctx.reserve(max(dA.n, cal_dev[0].n), max(dB.n, cal_dev[1].n), max(wl.n_pairs, calib["n_pairs"]))
+            # the descent starts from the committed profile's parameters when
+            # that profile was taken on this kernel source
+            prof0 = profile_summary(args.workload, None)
+            start = prof0["params"] if prof0 else None
             tuned = autotune.tune(ctx, *cal_dev, mode=sccg.SCCG_BATCHED, workload_key=wkey, use_cache=False,
-                                  log=log)
+                                  log=log, start=start)
             calib["batched_params"] = tuned
+            calib["start"] = start
             log(f"autotuned batched parameters {tuned} on the calibration sample in {time.perf_counter() - t:.1f} s")
 
         sets_out = [None]
@@ -657,7 +663,7 @@ def main(argv=None):
     prof = profile_summary(args.workload, tuned)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_OPS, "traffic": prof["bytes_per_launch"] if prof else None,
-                "kernel": "batched call: k_batch_clear_*, k_batch_setup, k_batch_heavy_meta, k_batch_sweep, "
+                "kernel": "batched call: k_batch_clear_*, k_batch_setup, k_batch_prepass, k_batch_sweep, "
                           "k_batch_medium, k_batch_run (one HIP event bracket)", "kernel_ms": k_avg_ms,
                 "algorithmic_ops_per_launch": algo_ops, "algorithmic_bytes_per_launch": algo_bytes,
                 "hbm_frac_algorithmic": (algo_bytes / (k_avg_ms / 1e3)) / HBM_PEAK}

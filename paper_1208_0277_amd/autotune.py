@@ -56,8 +56,10 @@ def _device_key() -> str:
 
 
 def tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key="", steps=8, use_cache=True,
-         space=None, log=None):
-    """Return the best parameter dict for this workload and leave it set on ctx."""
+         space=None, log=None, start=None):
+    """Return the best parameter dict for this workload and leave it set on ctx.
+    `start` (optional): the values the descent starts from, e.g. an earlier
+    tuning's result; each must be one of its parameter's candidates."""
     space = space or (BATCHED_SPACE if mode == sccg.SCCG_BATCHED else PLAIN_SPACE)
     key = f"{_device_key()}/{'batched' if mode == sccg.SCCG_BATCHED else 'plain'}/{workload_key}"
     cache = {}
@@ -77,6 +79,9 @@ def tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key="", ste
     if any(name == "wg_size" for name, _ in space):
         base["split_gx"] = base["split_gy"] = 0  # the split grid follows the block size
     best = {name: vals[0] for name, vals in space}
+    for name, vals in space:
+        if start and name in start and int(start[name]) in vals:
+            best[name] = int(start[name])
     call_args = (dA, dB, pa, pb)
     ref = None
     scores = {}
@@ -102,7 +107,9 @@ def tune(ctx, dA, dB, pa, pb, I, U, mode=sccg.SCCG_BATCHED, workload_key="", ste
 
     best_t = score(best)
     for name, vals in space:
-        for v in vals[1:]:
+        for v in vals:
+            if v == best[name]:
+                continue
             cand = dict(best)
             cand[name] = v
             t = score(cand)

@@ -1644,6 +1644,65 @@ __device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairR
   }
 }
 
+// The prepass of the pairs the setup pass listed: per pair, one wave
+// reduces the MBRs and areas of both rings and records the pair box and the
+// pair's class; the outputs start at I = 0, U = |p| + |q| (boxes add to I and
+// subtract from U atomically).  Wave w takes entries w, w + waves, ... of
+// the buckets laid end to end, largest first.
+__global__ void __launch_bounds__(256) k_batch_prepass(BatchArgs args) {
+  const BatchArgs& a = args;
+  const int lane = lane_id();
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  int64_t nb[kLptBuckets], n = 0;
+#pragma unroll
+  for (int b = 0; b < kLptBuckets; ++b) {
+    nb[b] = (int64_t)a.st->l_count[b].v;
+    n += nb[b];
+  }
+  for (int64_t k = wave; k < n; k += waves) {
+    // entry k of the buckets laid end to end, largest first
+    int64_t kk = k;
+    int bk = kLptBuckets - 1;
+#pragma unroll
+    for (int b = kLptBuckets - 1; b > 0; --b) {
+      if (bk == b && kk >= nb[b]) {
+        kk -= nb[b];
+        bk = b - 1;
+      }
+    }
+    const int64_t i = a.l_list[(int64_t)bk * a.n_pairs + kk];
+    const int64_t ia = a.pa[i], ib = a.pb[i];
+    const int64_t op = a.A.off[ia], oq = a.B.off[ib];
+    Meta mp, mq;
+    int64_t ap, aq;
+    ring_scan(a.A.xy, op, a.A.off[ia + 1] - op, lane, mp, ap);
+    ring_scan(a.B.xy, oq, a.B.off[ib + 1] - oq, lane, mq, aq);
+    if (lane != 0) continue;
+    if (a.stats_on) atomicAdd(&a.st->stats[12], (unsigned long long)(a.A.off[ia + 1] - op + a.B.off[ib + 1] - oq));
+    if (coords_bad(mp, a.A.off[ia + 1] - op) || coords_bad(mq, a.B.off[ib + 1] - oq)) latch_error(a.err, kErrCoord);
+    const Meta b = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
+    *reinterpret_cast<int4*>(a.hbox + i) = make_int4(b.x0, b.y0, b.x1, b.y1);
+    const int64_t w = (int64_t)b.x1 - b.x0, h = (int64_t)b.y1 - b.y0;
+    uint8_t cls = kClsDone;
+    a.inter[i] = 0;
+    a.uni[i] = direct_union(a) ? 0 : ap + aq;
+    if (b.x0 >= b.x1 || b.y0 >= b.y1) {
+      cls = kClsDone;
+    } else if (w > kMaxSide || h > kMaxSide) {
+      latch_error(a.err, kErrSide);
+      a.uni[i] = 0;
+    } else {
+      cls = (w <= kTile && h <= kTile) ? kClsSmall : kClsLarge;
+      if (a.stats_on) {
+        atomicAdd(&a.st->stats[cls == kClsSmall ? 5 : 6], 1ull);
+        atomicAdd(&a.st->stats[11], (unsigned long long)(w * h));
+      }
+    }
+    a.cls[i] = cls;
+  }
+}
+
 __global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_waves_per_eu(SCCG_SWEEP_WAVES_PER_EU)))
 k_batch_sweep(BatchArgs args) {
   __shared__ __align__(16) uint64_t sweep_slots[kSweepWaves * kLeafSlots];
@@ -1973,61 +2032,6 @@ __global__ void __launch_bounds__(256) k_batch_setup(BatchArgs a, int per) {
   }
 }
 
-// One wave per heavy pair: MBRs and areas of both rings, the pair box and the
-// pair's class; the outputs start at I = 0, U = |p| + |q| (boxes add to I and
-// subtract from U atomically).
-__global__ void __launch_bounds__(256) k_batch_heavy_meta(BatchArgs a) {
-  const int lane = lane_id();
-  const int waves = gridDim.x * (blockDim.x / kWave);
-  int64_t nb[kLptBuckets], n = 0;
-#pragma unroll
-  for (int b = 0; b < kLptBuckets; ++b) {
-    nb[b] = (int64_t)a.st->l_count[b].v;
-    n += nb[b];
-  }
-  for (int64_t k = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; k < n; k += waves) {
-    // entry k of the buckets laid end to end, largest first
-    int64_t kk = k;
-    int bk = kLptBuckets - 1;
-#pragma unroll
-    for (int b = kLptBuckets - 1; b > 0; --b) {
-      if (bk == b && kk >= nb[b]) {
-        kk -= nb[b];
-        bk = b - 1;
-      }
-    }
-    const int64_t i = a.l_list[(int64_t)bk * a.n_pairs + kk];
-    const int64_t ia = a.pa[i], ib = a.pb[i];
-    const int64_t op = a.A.off[ia], oq = a.B.off[ib];
-    Meta mp, mq;
-    int64_t ap, aq;
-    ring_scan(a.A.xy, op, a.A.off[ia + 1] - op, lane, mp, ap);
-    ring_scan(a.B.xy, oq, a.B.off[ib + 1] - oq, lane, mq, aq);
-    if (lane != 0) continue;
-    if (a.stats_on) atomicAdd(&a.st->stats[12], (unsigned long long)(a.A.off[ia + 1] - op + a.B.off[ib + 1] - oq));
-    if (coords_bad(mp, a.A.off[ia + 1] - op) || coords_bad(mq, a.B.off[ib + 1] - oq)) latch_error(a.err, kErrCoord);
-    const Meta b = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
-    *reinterpret_cast<int4*>(a.hbox + i) = make_int4(b.x0, b.y0, b.x1, b.y1);
-    const int64_t w = (int64_t)b.x1 - b.x0, h = (int64_t)b.y1 - b.y0;
-    uint8_t cls = kClsDone;
-    a.inter[i] = 0;
-    a.uni[i] = direct_union(a) ? 0 : ap + aq;
-    if (b.x0 >= b.x1 || b.y0 >= b.y1) {
-      cls = kClsDone;
-    } else if (w > kMaxSide || h > kMaxSide) {
-      latch_error(a.err, kErrSide);
-      a.uni[i] = 0;
-    } else {
-      cls = (w <= kTile && h <= kTile) ? kClsSmall : kClsLarge;
-      if (a.stats_on) {
-        atomicAdd(&a.st->stats[cls == kClsSmall ? 5 : 6], 1ull);
-        atomicAdd(&a.st->stats[11], (unsigned long long)(w * h));
-      }
-    }
-    a.cls[i] = cls;
-  }
-}
-
 __global__ void k_batch_stats_empty(BatchArgs a) {
   // pairs that ended in setup or in the heavy prepass (stats only)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2040,6 +2044,12 @@ hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_batch_prepass(const BatchArgs& a, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_prepass, dim3(2048), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
   // enough blocks to fill the chip (about 1024), at most kSetupPerThread pairs per thread
@@ -2047,7 +2057,6 @@ hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s) {
   const int64_t per_block = 256 * (int64_t)per;
   const unsigned blocks = (unsigned)((a.n_pairs + per_block - 1) / per_block);
   hipLaunchKernelGGL(k_batch_setup, dim3(blocks), dim3(256), 0, s, a, per);
-  hipLaunchKernelGGL(k_batch_heavy_meta, dim3(2048), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2069,10 +2078,15 @@ int batch_sweep_occupancy() {
 
 int batch_sweep_waves_per_wg() { return kSweepWaves; }
 
-hipError_t launch_batch_run(const BatchArgs& a, int sweep_grid, int grid, int waves_per_wg, hipStream_t s) {
+hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_batch_sweep, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
   hipLaunchKernelGGL(k_batch_medium, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_persistent(const BatchArgs& a, int grid, int waves_per_wg, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
   const size_t lds = (size_t)waves_per_wg * batch_lds_bytes_per_wave();
   hipLaunchKernelGGL(k_batch_run, dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
   if (a.stats_on)

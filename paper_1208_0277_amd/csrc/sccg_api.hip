@@ -472,6 +472,21 @@ __global__ void k_zero_stats(unsigned long long* s) {
   if ((int)threadIdx.x < kNumStats) s[threadIdx.x] = 0;
 }
 
+// The launches of one BATCHED call on the context's stream: reset, setup,
+// the prepass of listed pairs, the two sweeps, the persistent kernel.  (A
+// prepass on a second stream beside the sweeps measured no faster: it takes
+// the sweeps' issue slots.)
+static int launch_batch_sequence(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int grid) {
+  hipError_t e;
+  if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
+  if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
+  if ((e = launch_batch_prepass(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch prepass");
+  if ((e = launch_batch_sweeps(ba, sweep_grid, c->stream)) != hipSuccess) return hip_fail(c, e, "batch sweeps");
+  if ((e = launch_batch_persistent(ba, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "batch persistent kernel");
+  return SCCG_OK;
+}
+
 static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int grid) {
   hipError_t e;
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -480,10 +495,7 @@ static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int 
     if (r) return r;
     HIP_TRY(c, hipEventRecord(t0, c->stream));
   }
-  if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
-  if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
-  if ((e = launch_batch_run(ba, sweep_grid, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
-    return hip_fail(c, e, "batch run");
+  if (int r = launch_batch_sequence(c, ba, sweep_grid, grid)) return r;
   if (c->timing_on) HIP_TRY(c, hipEventRecord(t1, c->stream));
   return SCCG_OK;
 }
@@ -681,12 +693,7 @@ int sccg_area_pairs_noalloc(sccg_ctx* c, const sccg_polys* A, const sccg_polys* 
   int grid = c->p.grid;
   if (grid == 0) grid = c->cu_count * batch_occupancy(c->p.waves_per_wg);
   const int sweep_grid = c->cu_count * batch_sweep_occupancy();
-  hipError_t e;
-  if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
-  if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
-  if ((e = launch_batch_run(ba, sweep_grid, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
-    return hip_fail(c, e, "batch run");
-  return SCCG_OK;
+  return launch_batch_sequence(c, ba, sweep_grid, grid);
 }
 
 int sccg_jaccard_sets(sccg_ctx* c, int64_t n_sets, const int64_t* set_pair_off, const int64_t* inter,

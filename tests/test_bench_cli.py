@@ -30,6 +30,7 @@ def test_profile_summary_needs_the_same_kernel_source_and_params(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: committed["kernel_source_hash"])
     d = bench.profile_summary(3, params)
     assert d is not None and d["bytes_per_launch"] > 0
+    assert bench.profile_summary(3, None) is not None  # any parameters (the autotuner's starting point)
     # other tuning parameters than the timed run's: not used
     other = dict(params, queue_chunk=int(params["queue_chunk"]) + 1)
     assert bench.profile_summary(3, other) is None
