@@ -354,7 +354,7 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
 // The same extent and area for the prepass of listed (long) rings: each
 // lane loads its vertices and their successors directly, kScanBatch chunks
 // of 64 per round trip, so that a long ring costs few memory latencies.
-constexpr int kScanBatch = 4;
+constexpr int kScanBatch = 8;
 __device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv64, int lane, Meta& m, int64_t& area) {
   const int nv = uniform((int)nv64);
   m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};  // covers nothing
@@ -1113,27 +1113,6 @@ constexpr bool kRunSteal = SCCG_RUN_STEAL != 0;
 // whether the sweeps' waves also claim from other XCDs' streams
 constexpr bool kSweepSteal = SCCG_SWEEP_STEAL != 0;
 
-// Chunks [c0, c1) of a ring of nr vertices.
-template <int N>
-__device__ __forceinline__ void ring_load(const int2* R, int nr, int lane, int2 (&d)[N], int c0 = 0, int c1 = N) {
-#pragma unroll
-  for (int c = 0; c < N; ++c)
-    if (c >= c0 && c < c1 && c * kWave < nr) d[c] = R[min(c * kWave + lane, nr - 1)];
-}
-
-// The next pair's rings are loaded ahead up to this many chunks each; the
-// rest of a longer ring is loaded when its pair comes up.
-constexpr int kAheadChunks = 2;
-struct AheadRegs {
-  int2 p[kAheadChunks], q[kAheadChunks];
-};
-
-template <int N>
-__device__ __forceinline__ void ring_move(int2 (&d)[N], const int2 (&s)[kAheadChunks], int nr) {
-#pragma unroll
-  for (int c = 0; c < kAheadChunks; ++c)
-    if (c * kWave < nr) d[c] = s[c];
-}
 
 // lanes [0, k) for 0 <= k <= 63, and lanes [0, m) for 1 <= m <= 64
 __device__ __forceinline__ uint64_t lanes_below_k(int k) { return (1ull << k) - 1ull; }
@@ -1771,6 +1750,20 @@ k_batch_sweep(BatchArgs args) {
 // rings in registers; a pair box at most kSweepRowTiles tiles wide is
 // pixelized at once (a box the persistent kernel would not classify), a
 // larger one is listed with its box.  A claim takes 64 consecutive entries.
+// Every chunk of both rings of a medium pair (clamped to each ring's last
+// vertex), or for no pair reads of `dummy`.
+__device__ __forceinline__ void medium_load(const BatchArgs& a, const SweepRec& s, const int2* dummy, int lane,
+                                            PairRegs<kMediumChunks>& r) {
+  const int2* P = s.np > 0 ? a.A.xy + s.op : dummy;
+  const int2* Q = s.nq > 0 ? a.B.xy + s.oq : dummy;
+  const int lp = max(s.np - 1, 0), lq = max(s.nq - 1, 0);
+#pragma unroll
+  for (int c = 0; c < kMediumChunks; ++c) {
+    r.p[c] = P[min(c * kWave + lane, lp)];
+    r.q[c] = Q[min(c * kWave + lane, lq)];
+  }
+}
+
 __device__ __forceinline__ void medium_one(Ctx& c, const SweepRec& s, const PairRegs<kMediumChunks>& r, int64_t i) {
   const BatchArgs& a = *c.a;
   int64_t I = 0, U = 0;
@@ -1824,27 +1817,21 @@ __global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs a
     // lane j: pair index and record of entry e0 + j
     const int idx = lane < cnt ? a.m_list[e0 + lane] : 0;
     const ChunkRecs cr = gather_recs(a, idx, lane < cnt);
-    PairRegs<kMediumChunks> rc;
-    AheadRegs rn;
+    const int2* dummy = reinterpret_cast<const int2*>(a.rec + __builtin_amdgcn_readfirstlane(idx));
+    // the pair in hand (sc, rc) and the next one (sn, rn), whose loads are in
+    // flight while the pair in hand is processed: every chunk of both rings,
+    // loaded the same way whatever the pair, so that the compiler waits only
+    // for the pair in hand's loads
+    PairRegs<kMediumChunks> rc, rn;
     SweepRec sc = sweep_rec(cr, 0);
-    ring_load(a.A.xy + sc.op, sc.np, lane, rc.p);
-    ring_load(a.B.xy + sc.oq, sc.nq, lane, rc.q);
+    medium_load(a, sc, dummy, lane, rc);
 #pragma unroll 1
     for (int j = 0; j < cnt; ++j) {
-      SweepRec sn{0, 0, 0, 0, kClsDone};
-      if (j + 1 < cnt) {
-        sn = sweep_rec(cr, j + 1);
-        ring_load(a.A.xy + sn.op, sn.np, lane, rn.p);
-        ring_load(a.B.xy + sn.oq, sn.nq, lane, rn.q);
-      }
+      const SweepRec sn = j + 1 < cnt ? sweep_rec(cr, j + 1) : SweepRec{0, 0, 0, 0, kClsDone};
+      medium_load(a, sn, dummy, lane, rn);
       medium_one(c, sc, rc, (int64_t)__builtin_amdgcn_readlane(idx, j));
-      if (j + 1 >= cnt) break;
       sc = sn;
-      ring_move(rc.p, rn.p, sn.np);
-      ring_move(rc.q, rn.q, sn.nq);
-      // the rest of longer rings now
-      if (sn.np > kAheadChunks * kWave) ring_load(a.A.xy + sn.op, sn.np, lane, rc.p, kAheadChunks);
-      if (sn.nq > kAheadChunks * kWave) ring_load(a.B.xy + sn.oq, sn.nq, lane, rc.q, kAheadChunks);
+      rc = rn;
     }
   }
   wave_stamps(a, 1, t_start, lane);
