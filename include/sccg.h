@@ -361,9 +361,9 @@ typedef struct {
 
 typedef struct {
   uint64_t job_id;       /* as returned by sccg_server_submit                                        */
-  int32_t status;        /* SCCG_OK, or SCCG_E_RANGE / SCCG_E_DEVICE latched by the job's launch, or
-                            SCCG_E_HIP if the server failed; a migrated job reports SCCG_E_RANGE for
-                            its own rejected pairs only                                               */
+  int32_t status;        /* SCCG_OK, or SCCG_E_RANGE / SCCG_E_DEVICE for the job's own pairs (a launch
+                            that latches an error runs each of its jobs again alone to attribute it),
+                            or SCCG_E_HIP if the server failed; the same alone and in a mix          */
   int32_t jobs_in_launch;/* jobs that shared the job's launch; 0 = run on host threads (migrated)     */
   int64_t n_pairs;
   int64_t sum_i, sum_u, n_contrib; /* as sccg_jaccard_sets over the job's pairs                      */

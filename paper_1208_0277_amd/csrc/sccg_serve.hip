@@ -279,12 +279,44 @@ struct HipExec {
     return true;
   }
 
+  // The status one job's pairs give alone: run them again (they are still
+  // resident) and read the error word they latch.
+  int alone_status(int64_t off, int64_t n) {
+    if (n <= 0) return SCCG_OK;
+    sccg_polys arena{s->cfg.slot_cap - 1, s->d_off, s->d_xy};
+    if (sccg_area_pairs(s->ctx, &arena, &arena, n, s->d_pa + off, s->d_pb + off, s->d_i + off, s->d_u + off,
+                        SCCG_BATCHED) != SCCG_OK)
+      return SCCG_E_HIP;
+    uint32_t* errw = ctx_error_word(s->ctx);
+    uint32_t e = 0;
+    if (hipMemcpyAsync(&e, errw, 4, hipMemcpyDeviceToHost, s->stream) != hipSuccess) return SCCG_E_HIP;
+    hipLaunchKernelGGL(k_serve_clear_word, dim3(1), dim3(64), 0, s->stream, errw);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) return SCCG_E_HIP;
+    return (e & kErrWatchdog) ? SCCG_E_DEVICE : (e ? SCCG_E_RANGE : SCCG_OK);
+  }
+
   // Results of a finished launch: counts to the callers' arrays, sums to
   // the result queue.  The pipeline retires the jobs afterwards.
   void finish(const Step& st, Job* const* jobs, int si) {
     const Slot& sl = s->slots[si];
     const uint32_t err = *sl.h_err;
     const int status = (err & kErrWatchdog) ? SCCG_E_DEVICE : (err ? SCCG_E_RANGE : SCCG_OK);
+    // A launch of several jobs that latched an error runs each job's pairs
+    // again alone to learn which jobs the error belongs to, so that a job
+    // reports the same status alone and in a mix (the counts are per pair
+    // and do not change).  Should no job reproduce it, every job keeps the
+    // launch's status.
+    std::vector<int> job_status((size_t)st.count, status);
+    if (err && st.count > 1) {
+      int64_t p = st.pair_off;
+      bool any = false;
+      for (int c = 0; c < st.count; ++c) {
+        job_status[(size_t)c] = alone_status(p, jobs[c]->n_pairs);
+        any |= job_status[(size_t)c] != SCCG_OK;
+        p += jobs[c]->n_pairs;
+      }
+      if (!any) std::fill(job_status.begin(), job_status.end(), status);
+    }
     std::vector<sccg_job_result> out;
     out.reserve(st.count);
     int64_t pos = st.pair_off;
@@ -293,7 +325,7 @@ struct HipExec {
       if (j->out_i) memcpy(j->out_i, s->h_i + pos, (size_t)j->n_pairs * 8);
       if (j->out_u) memcpy(j->out_u, s->h_u + pos, (size_t)j->n_pairs * 8);
       pos += j->n_pairs;
-      sccg_job_result r = result_of(j, status);
+      sccg_job_result r = result_of(j, job_status[(size_t)c]);
       r.jobs_in_launch = st.count;
       r.sum_i = sl.h_sums[c];
       r.sum_u = sl.h_sums[kStepJobs + c];

@@ -148,6 +148,52 @@ def test_alone_equals_in_mix(corpus):
     assert any(res[jid]["jobs_in_launch"] > 1 for jid, _ in probes) or len(jobs) > 1
 
 
+def bad_window(wl, s, n, k):
+    """Job arrays for pairs [s, s + n) whose k-th A polygon lies beyond the
+    2^30 coordinate limit: that polygon counts as empty and the job reports
+    SCCG_E_RANGE."""
+    a_off, a_xy, b_off, b_xy, pa, pb = window(wl, s, n)
+    xy = a_xy.reshape(-1, 2).copy()
+    xy[int(a_off[k]):int(a_off[k + 1]), 0] += (1 << 30) + 5
+    return a_off, xy.reshape(-1), b_off, b_xy, pa, pb
+
+
+def test_status_alone_equals_in_mix(corpus):
+    """A job whose pairs latch a range error reports SCCG_E_RANGE, and the
+    same counts, alone and in a launch shared with good jobs, which report
+    SCCG_OK and exact counts."""
+    wl, I, U = corpus
+    arrs = bad_window(wl, 4000, 300, 7)
+    srv = sccg.Server(0, max_inflight=1)
+    try:
+        oi_a, ou_a = np.zeros(300, np.int64), np.zeros(300, np.int64)
+        ja = srv.submit(*arrs, out_inter=oi_a, out_union=ou_a)
+        r_alone = collect(srv, 1)[ja]
+        # a large job keeps the device busy while the rest queue and merge
+        jobs = submit_windows(srv, wl, [(0, 15000)])
+        jobs.update(submit_windows(srv, wl, [(15000 + 100 * k, 90) for k in range(8)]))
+        oi_m, ou_m = np.zeros(300, np.int64), np.zeros(300, np.int64)
+        jm = srv.submit(*arrs, out_inter=oi_m, out_union=ou_m)
+        jobs.update(submit_windows(srv, wl, [(16000 + 100 * k, 90) for k in range(8)]))
+        res = collect(srv, len(jobs) + 1)
+    finally:
+        srv.close()
+    assert r_alone["status"] == sccg.SCCG_E_RANGE
+    assert res[jm]["status"] == sccg.SCCG_E_RANGE
+    assert res[jm]["jobs_in_launch"] > 1, "the bad job ran alone: the mix was not exercised"
+    assert np.array_equal(oi_m, oi_a) and np.array_equal(ou_m, ou_a)
+    # the out-of-range polygon counts as empty: I = 0, U = |B|
+    rb = wl.B.ring(4007).astype(np.int64)
+    area_b = abs(int(np.sum(rb[:, 0] * np.roll(rb[:, 1], -1) - np.roll(rb[:, 0], -1) * rb[:, 1]))) // 2
+    assert oi_a[7] == 0 and ou_a[7] == area_b
+    keep = np.arange(300) != 7
+    assert np.array_equal(oi_a[keep], I[4000:4300][keep]) and np.array_equal(ou_a[keep], U[4000:4300][keep])
+    for k in ("sum_i", "sum_u", "n_contrib", "j", "jprime"):
+        assert res[jm][k] == r_alone[k]
+    for jid, (s, n, oi, ou) in jobs.items():
+        check_job(res[jid], (oi, ou), (I, U), s, n)
+
+
 def test_pinned_corpus(corpus):
     import torch
     wl, I, U = corpus
