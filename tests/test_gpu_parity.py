@@ -371,6 +371,70 @@ def test_redundant_vertices(ctx, mode):
     assert_exact(gI, gU, eI, eU, f"redundant vertices mode {mode}")
 
 
+def _boundary_pairs(seed=23, n=400):
+    """Band-polygon pairs sitting on BATCHED mode's class boundaries: union
+    boxes of 31-33 and 63-65 pixels a side (the union tile, its halves, the
+    medium sweep), rings padded to 64, 65, 128, 129, 256 and 257 vertices,
+    and some pairs of 255 + 256 and 256 + 256 vertices (heavy_verts 512).
+    Returns the rings and the closed-form counts."""
+    rng = np.random.default_rng(seed)
+    targets = {31, 32, 33, 63, 64, 65}
+    sizes = [0, 64, 65, 128, 129, 256, 257]
+    ra, rb, expect = [], [], []
+    while len(ra) < n:
+        def stair():
+            nb = int(rng.integers(1, 5))
+            w = int(rng.integers(8, 60))
+            return staircase(nb, int(rng.integers(8, 70)), int(rng.integers(0, w)), w)
+        (ya, aa, ba), (yb, ab, bb) = stair(), stair()
+        dx, dy = (int(v) for v in rng.integers(-12, 13, 2))
+        yb, ab, bb = [y + dy for y in yb], [x + dx for x in ab], [x + dx for x in bb]
+        ux = max(max(ba), max(bb)) - min(min(aa), min(ab))
+        uy = max(ya[-1], yb[-1]) - min(ya[0], yb[0])
+        if ux not in targets and uy not in targets and rng.random() < 0.9:
+            continue
+        ring_a, rects_a = band_ring(ya, aa, ba), band_rects(ya, aa, ba)
+        ring_b, rects_b = band_ring(yb, ab, bb), band_rects(yb, ab, bb)
+        if rng.random() < 0.1:
+            na, nq = 256, int(rng.choice([255, 256]))
+        else:
+            na, nq = int(rng.choice(sizes)), int(rng.choice(sizes))
+        if na > len(ring_a):
+            ring_a = _redundant(ring_a, rng, na - len(ring_a))
+        if nq > len(ring_b):
+            ring_b = _redundant(ring_b, rng, nq - len(ring_b))
+        sx, sy = (1 if rng.random() < 0.5 else -1), (1 if rng.random() < 0.5 else -1)
+        sw = bool(rng.random() < 0.5)
+        tx, ty = (int(v) for v in rng.integers(-50000, 50000, 2))
+        ring_a, rects_a = transform(ring_a, rects_a, sx, sy, sw, tx, ty, 1)
+        ring_b, rects_b = transform(ring_b, rects_b, sx, sy, sw, tx, ty, 1)
+        ra.append(np.asarray(ring_a, np.int32))
+        rb.append(np.asarray(ring_b, np.int32))
+        i = rects_inter(rects_a, rects_b)
+        expect.append((i, rects_area(rects_a) + rects_area(rects_b) - i))
+    return ra, rb, expect
+
+
+@pytest.mark.parametrize("case", ["plain", "batched", "batched_heavy64"])
+def test_class_boundaries(case):
+    """Counts at every class boundary of BATCHED mode equal the closed form
+    (and the oracle), in both modes and with heavy_verts moved to 64."""
+    ra, rb, expect = _boundary_pairs()
+    A, B = concat(ra), concat(rb)
+    idx = np.arange(len(ra), dtype=np.int32)
+    eI = np.array([e[0] for e in expect], np.int64)
+    eU = np.array([e[1] for e in expect], np.int64)
+    oI, oU = oracle.area_pairs(A, B, idx, idx, form=oracle.ROWS)
+    assert np.array_equal(oI, eI) and np.array_equal(oU, eU)
+    c = sccg.Context(0, heavy_verts=64) if case == "batched_heavy64" else sccg.Context(0)
+    try:
+        mode = sccg.SCCG_PLAIN if case == "plain" else sccg.SCCG_BATCHED
+        gI, gU = run(c, device_workload(A, B, idx, idx), mode)
+    finally:
+        c.close()
+    assert_exact(gI, gU, eI, eU, f"class boundaries ({case})")
+
+
 def _comb(width, height, base, tooth, gap):
     """A comb: `base` full rows, then teeth `tooth` px wide every
     tooth + gap px up to `height`: many vertical edges in every 64-row band."""
