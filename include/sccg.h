@@ -128,6 +128,11 @@ typedef struct {
   int32_t min_classify_cells; /* BATCHED: a split into 64-pixel leaf tiles classifies its tiles (Lemma
                              1) only when it has at least this many, 1..65; a smaller split pixelizes
                              every tile of a polygon not known to contain it (default 26)           */
+  int32_t sweep_pair_box; /* BATCHED: 2 = the union sweep also counts, on its pair box MBR(p) ∩ MBR(q)
+                             (Section 3.2), a pair whose union box exceeds a 64 x 64 leaf tile but
+                             whose pair box fits one, from the rings it already holds; pays on mixes
+                             with many such pairs (densely packed sets).  1 = it leaves them to the
+                             medium sweep, which loads the rings again (default 1)                  */
 } sccg_params;
 
 /* Create a context on HIP device `hip_device` using stream `hip_stream`

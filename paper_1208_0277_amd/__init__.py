@@ -78,7 +78,8 @@ class sccg_params(ctypes.Structure):
                 ("split_gy", ctypes.c_int32), ("queue_chunk", ctypes.c_int32), ("lds_vertex_cap", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("grid", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("waves_per_wg", ctypes.c_int32), ("min_queue_cells", ctypes.c_int32),
-                ("n_queues", ctypes.c_int32), ("heavy_verts", ctypes.c_int32), ("min_classify_cells", ctypes.c_int32)]
+                ("n_queues", ctypes.c_int32), ("heavy_verts", ctypes.c_int32), ("min_classify_cells", ctypes.c_int32),
+                ("sweep_pair_box", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

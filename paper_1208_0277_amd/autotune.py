@@ -26,6 +26,7 @@ BATCHED_SPACE = [
     ("waves_per_wg", [4, 2, 8]),
     ("heavy_verts", [512, 1024, 2048]),
     ("min_classify_cells", [26, 1, 10, 65]),
+    ("sweep_pair_box", [1, 2]),
 ]
 
 #: plain-mode candidates: the pixelization threshold T (Section 3.4 puts the

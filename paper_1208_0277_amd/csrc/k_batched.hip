@@ -1406,8 +1406,9 @@ __device__ __forceinline__ void ring_meta_regs(const int2 (&d)[N], int nr, int l
 // below a band row of the box sets all of the band's rows and one above it
 // none.  Each band row is laid out as in leaf_rows: the columns of both
 // rings in one slot array each, tiles scanned right to left with the XOR of
-// the tiles to their right carried.
-template <int N>
+// the tiles to their right carried.  kQ: q's first slot (p's is slot 0); a
+// box gx tiles wide uses slots [0, gx kWave) and [kQ, kQ + gx kWave).
+template <int N, int kQ = kSweepRowTiles * kWave>
 __device__ __forceinline__ uint64_t sweep_rows(Ctx& c, const PairRegs<N>& r, int np, int nq, const Meta& box) {
   const int lane = c.lane;
   const int bw = box.x1 - box.x0, bh = box.y1 - box.y0;
@@ -1428,7 +1429,7 @@ __device__ __forceinline__ uint64_t sweep_rows(Ctx& c, const PairRegs<N>& r, int
 #pragma unroll
     for (int ch = 0; ch < N; ++ch) {
       const int dx = min(r.q[ch].x, box.x0 + wpad) - box.x0;
-      posq[ch] = lane_in(cm[ch]) && dx > 0 ? kSweepRowTiles * kWave + wpad - dx : -1;
+      posq[ch] = lane_in(cm[ch]) && dx > 0 ? kQ + wpad - dx : -1;
     }
   }
   uint64_t* slots = c.slots;
@@ -1440,7 +1441,7 @@ __device__ __forceinline__ uint64_t sweep_rows(Ctx& c, const PairRegs<N>& r, int
 #pragma unroll 1
     for (int b = 0; b < gx; ++b) {
       slots[b * kWave + lane] = fresh_zero<uint64_t>();
-      slots[kSweepRowTiles * kWave + b * kWave + lane] = fresh_zero<uint64_t>();
+      slots[kQ + b * kWave + lane] = fresh_zero<uint64_t>();
     }
     wave_sync_lds();
 #pragma unroll
@@ -1460,7 +1461,7 @@ __device__ __forceinline__ uint64_t sweep_rows(Ctx& c, const PairRegs<N>& r, int
     for (int i = gx - 1; i >= 0; --i) {
       const int b = gx - 1 - i;
       const uint64_t xp = wave_prefix_xor<false>(slots[b * kWave + lane]);
-      const uint64_t xq = wave_prefix_xor<false>(slots[kSweepRowTiles * kWave + b * kWave + lane]);
+      const uint64_t xq = wave_prefix_xor<false>(slots[kQ + b * kWave + lane]);
       const int tw = min(kTile, bw - kTile * i);
       if (kWave - 1 - lane < tw) ni += (uint32_t)__popcll((xp ^ carry_p) & (xq ^ carry_q) & full);
       carry_p ^= (uint64_t)readlane64((int64_t)xp, kWave - 1);
@@ -1482,9 +1483,11 @@ __device__ __forceinline__ uint64_t sweep_rows(Ctx& c, const PairRegs<N>& r, int
 // out of range: I and U are final), or small / large (the pair is to be
 // listed for the persistent kernel with `box`, I = 0 and U = |p| + |q|, or 0
 // when the union is counted directly, as the values its boxes add to).
+// small_only: a pair that would be large is returned as large with nothing
+// counted in the statistics (another pass takes it and counts it).
 template <int N>
 __device__ __forceinline__ uint8_t sweep_meta(Ctx& c, const PairRegs<N>& r, int np, int nq, int64_t& I, int64_t& U,
-                                              Meta& box) {
+                                              Meta& box, bool small_only = false) {
   const BatchArgs& a = *c.a;
   Meta mp, mq;
   int64_t ap, aq;
@@ -1492,23 +1495,26 @@ __device__ __forceinline__ uint8_t sweep_meta(Ctx& c, const PairRegs<N>& r, int 
   ring_meta_regs(r.p, np, c.lane, mp, ap, bp);
   ring_meta_regs(r.q, nq, c.lane, mq, aq, bq);
   if (c.lane == 0 && (bp || bq)) latch_error(a.err, kErrCoord);
-  stat_add(c, 12, (unsigned long long)(np + nq));
   const bool direct = direct_union(a);
   box = direct ? union_box(mp, mq) : pair_box(mp, mq);
   I = 0;
   U = direct ? 0 : ap + aq;
   if (box.x0 >= box.x1 || box.y0 >= box.y1) {
+    stat_add(c, 12, (unsigned long long)(np + nq));
     stat_add(c, 7, 1ull);  // empty pair box: nothing in common
     return kClsDone;
   }
   const uint32_t bw = side_u(box.x0, box.x1), bh = side_u(box.y0, box.y1);
   if (bw > (uint32_t)kMaxSide || bh > (uint32_t)kMaxSide) {
     if (c.lane == 0) latch_error(a.err, kErrSide);
+    stat_add(c, 12, (unsigned long long)(np + nq));
     stat_add(c, 7, 1ull);
     U = 0;
     return kClsDone;
   }
   const bool small = bw <= (uint32_t)kTile && bh <= (uint32_t)kTile;
+  if (small_only && !small) return kClsLarge;
+  stat_add(c, 12, (unsigned long long)(np + nq));
   stat_add(c, small ? 5 : 6, 1ull);
   stat_add(c, 11, (unsigned long long)bw * bh);
   return small ? kClsSmall : kClsLarge;
@@ -1603,12 +1609,36 @@ __device__ __forceinline__ void sweep_load(const BatchArgs& a, const SweepRec& s
   }
 }
 
-// Pair j of the chunk (a sweep pair): counted on its union tile, leaving
-// I | U << 16 in lane j of `packed` and bit j in `wmask` (written out with
-// the chunk); a pair left out (union box larger than a leaf tile) goes to
-// the medium list with the chunk.
-__device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairRegs<kUnionChunks>& r, int j,
-                                          bool union_ok, uint32_t& packed, uint64_t& wmask) {
+// A sweep pair that its union tile did not take, from its rings in
+// registers: MBRs and areas, and when the pair box MBR(p) ∩ MBR(q) is empty
+// or fits one leaf tile, I over that box and U = |p| + |q| - I (Section 3.2),
+// written out at once, and true.  A larger pair box is left, with nothing
+// written or counted, to the medium sweep (false).
+__device__ __forceinline__ bool pair_tile(Ctx& c, const SweepRec& s, const PairRegs<kUnionChunks>& r, int64_t i) {
+  int64_t I = 0, U = 0;
+  Meta box{0, 0, 0, 0};
+  const uint8_t cls = sweep_meta(c, r, s.np, s.nq, I, U, box, true);
+  if (cls == kClsLarge) return false;
+  if (cls == kClsSmall) {
+    I = (int64_t)sweep_rows<kUnionChunks, kWave>(c, r, s.np, s.nq, box);
+    U -= I;
+  }
+  if (c.lane == 0) {
+    c.a->inter[i] = I;
+    c.a->uni[i] = U;
+  }
+  return true;
+}
+
+// Pair j of the chunk (a sweep pair, index i0 + j): counted on its union
+// tile, leaving I | U << 16 in lane j of `packed` and bit j in `wmask`
+// (written out with the chunk); else, with kPairBox and the union not being
+// counted directly, counted on its pair box when that fits one leaf tile,
+// written out at once, with bit j in `dmask`; a pair left out goes to the
+// medium list with the chunk.
+template <bool kPairBox>
+__device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairRegs<kUnionChunks>& r, int64_t i0,
+                                          int j, bool union_ok, uint32_t& packed, uint64_t& wmask, uint64_t& dmask) {
   if (s.cls != kClsSweep) return;  // another class, or a bad index
   const int lane = c.lane;
   uint32_t t = 0;
@@ -1620,6 +1650,8 @@ __device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairR
   if (done) {
     if (lane == j) packed = t;
     wmask |= 1ull << j;
+  } else if (kPairBox && !direct_union(*c.a) && pair_tile(c, s, r, i0 + j)) {
+    dmask |= 1ull << j;
   }
 }
 
@@ -1682,6 +1714,11 @@ __global__ void __launch_bounds__(256) k_batch_prepass(BatchArgs args) {
   }
 }
 
+// kPairBox: pairs whose union box exceeds a leaf tile are counted on their
+// pair box when it fits one (the same counts as the medium sweep's, without
+// loading the rings again); a separate instance keeps the extra registers
+// off the plain sweep, which most mixes run.
+template <bool kPairBox>
 __global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_waves_per_eu(SCCG_SWEEP_WAVES_PER_EU)))
 k_batch_sweep(BatchArgs args) {
   __shared__ __align__(16) uint64_t sweep_slots[kSweepWaves * kLeafSlots];
@@ -1709,7 +1746,7 @@ k_batch_sweep(BatchArgs args) {
     const ChunkRecs cr = chunk_recs(a, i0, cnt, lane);
     // lane j: I | U << 16 of pair i0 + j when it is counted on its union tile
     uint32_t packed = 0;
-    uint64_t wmask = 0;
+    uint64_t wmask = 0, dmask = 0;
     // the pair in hand (s[0], r[0]) and the next kSweepAhead ones, whose ring
     // loads are in flight while the pair in hand is processed
     SweepRec s[kSweepAhead + 1];
@@ -1722,7 +1759,7 @@ k_batch_sweep(BatchArgs args) {
     }
 #pragma unroll 1
     for (int j = 0; j < cnt; ++j) {
-      sweep_one(c, s[0], r[0], j, union_ok, packed, wmask);
+      sweep_one<kPairBox>(c, s[0], r[0], i0, j, union_ok, packed, wmask, dmask);
 #pragma unroll
       for (int k = 0; k < kSweepAhead; ++k) {
         s[k] = s[k + 1];
@@ -1738,7 +1775,7 @@ k_batch_sweep(BatchArgs args) {
       a.inter[i0 + lane] = (int64_t)(packed & 0xffffu);
       a.uni[i0 + lane] = (int64_t)(packed >> 16);
     }
-    const uint64_t left = ballot(lane < cnt && cr.cls == kClsSweep) & ~wmask;
+    const uint64_t left = ballot(lane < cnt && cr.cls == kClsSweep) & ~(wmask | dmask);
     if (left) list_append(a.st->m_count, a.m_list, left, i0, lane);
   }
   wave_stamps(a, 0, t_start, lane);
@@ -1746,7 +1783,9 @@ k_batch_sweep(BatchArgs args) {
 
 // ------------------------------------------------------------ medium sweep
 // Second pass over the medium list: pairs with rings of at most kMediumRing
-// vertices that the union tile did not take.  MBRs and areas come from the
+// vertices that the union sweep did not finish (a ring over kSweepRing
+// vertices, a pair box larger than a leaf tile, or, with the union counted
+// directly, a union box larger than one).  MBRs and areas come from the
 // rings in registers; a pair box at most kSweepRowTiles tiles wide is
 // pixelized at once (a box the persistent kernel would not classify), a
 // larger one is listed with its box.  A claim takes 64 consecutive entries.
@@ -2057,7 +2096,11 @@ int batch_occupancy(int waves_per_wg) {
 
 int batch_sweep_occupancy() {
   int n = 0, m = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep, kSweepWaves * kWave, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep<false>, kSweepWaves * kWave, 0) != hipSuccess)
+    return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_batch_sweep<true>, kSweepWaves * kWave, 0) != hipSuccess)
+    return 1;
+  n = n < m ? n : m;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_batch_medium, kSweepWaves * kWave, 0) != hipSuccess) return 1;
   n = n < m ? n : m;
   return n > 0 ? n : 1;
@@ -2065,9 +2108,12 @@ int batch_sweep_occupancy() {
 
 int batch_sweep_waves_per_wg() { return kSweepWaves; }
 
-hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, hipStream_t s) {
+hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, bool pair_box, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_sweep, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
+  if (pair_box)
+    hipLaunchKernelGGL(k_batch_sweep<true>, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_batch_sweep<false>, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
   hipLaunchKernelGGL(k_batch_medium, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
   return hipGetLastError();
 }

@@ -136,6 +136,8 @@ int resolve_params(sccg_ctx* c, const sccg_params* in, sccg_params* out) {
   if (p.min_classify_cells == 0) p.min_classify_cells = 26;
   if (p.min_classify_cells < 1 || p.min_classify_cells > 65)
     return fail(c, SCCG_E_ARG, "min_classify_cells outside [1, 65]");
+  if (p.sweep_pair_box == 0) p.sweep_pair_box = 1;
+  if (p.sweep_pair_box < 1 || p.sweep_pair_box > 2) return fail(c, SCCG_E_ARG, "sweep_pair_box must be 1 or 2");
   *out = p;
   return SCCG_OK;
 }
@@ -481,7 +483,8 @@ static int launch_batch_sequence(sccg_ctx* c, const BatchArgs& ba, int sweep_gri
   if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
   if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
   if ((e = launch_batch_prepass(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch prepass");
-  if ((e = launch_batch_sweeps(ba, sweep_grid, c->stream)) != hipSuccess) return hip_fail(c, e, "batch sweeps");
+  if ((e = launch_batch_sweeps(ba, sweep_grid, c->p.sweep_pair_box == 2, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "batch sweeps");
   if ((e = launch_batch_persistent(ba, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
     return hip_fail(c, e, "batch persistent kernel");
   return SCCG_OK;
@@ -604,11 +607,12 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   if (!use_graph) return launch_batched(c, ba, sweep_grid, grid);
   // the graph is keyed on every launch argument
   char key[512];
-  snprintf(key, sizeof(key), "%lld/%p/%p|%lld/%p/%p|%lld/%p/%p/%p/%p|%d/%d/%d/%d/%d/%d/%u/%d/%d",
+  snprintf(key, sizeof(key), "%lld/%p/%p|%lld/%p/%p|%lld/%p/%p/%p/%p|%d/%d/%d/%d/%d/%d/%u/%d/%d/%d",
            (long long)A->n_polys, (const void*)A->offsets, (const void*)A->xy,
            (long long)B->n_polys, (const void*)B->offsets, (const void*)B->xy, (long long)n_pairs,
            (const void*)pair_a, (const void*)pair_b, (void*)out_inter, (void*)out_union, ba.queue_cap, ba.n_queues,
-           ba.chunk, ba.heavy_verts, ba.min_cells_to_queue, ba.min_classify_cells, ba.flags, ba.stats_on | (c->stamps_on << 1), grid);
+           ba.chunk, ba.heavy_verts, ba.min_cells_to_queue, ba.min_classify_cells, ba.flags, ba.stats_on | (c->stamps_on << 1), grid,
+           c->p.sweep_pair_box);
   if (!c->gexec || c->gkey != key) {
     drop_graph(c);
     hipGraph_t g = nullptr;

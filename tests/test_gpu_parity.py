@@ -173,30 +173,35 @@ def test_config2_full_size(ctx, mode):
 
 def test_config4_full_size():
     """Workload 4 at its full size (64 tiles of 8192 x 8192, the grid-join
-    candidates in one launch through the captured graph): every pair and
-    every tile's sums, J and J' equal the oracle."""
+    candidates in one launch through the captured graph), with the union
+    sweep leaving pair boxes to the medium sweep and counting them itself:
+    every pair and every tile's sums, J and J' equal the oracle."""
     import os
     import torch
     wl = sccg_gen.sets(n_tiles=64, tile_side=8192, cell=64)
     print(f"[gpu] generated {wl.n_pairs} pairs in {len(wl.set_off) - 1} tiles", flush=True)
     dwl = device_workload(wl.A, wl.B, wl.pa, wl.pb)
     so = torch.from_numpy(wl.set_off).cuda()
-    c = graph_context()
-    try:
-        gI, gU = run_graph(c, dwl)
-        I, U = torch.from_numpy(gI).cuda(), torch.from_numpy(gU).cuda()
-        torch.cuda.synchronize()
-        with torch.cuda.stream(c.stream):
-            si, su, nn, j, jp = c.jaccard_sets(so, I, U)
-        c.sync()
-    finally:
-        c.close()
+    got = []
+    for spb in (1, 2):
+        c = graph_context(sweep_pair_box=spb)
+        try:
+            gI, gU = run_graph(c, dwl)
+            I, U = torch.from_numpy(gI).cuda(), torch.from_numpy(gU).cuda()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(c.stream):
+                sets = c.jaccard_sets(so, I, U)
+            c.sync()
+            got.append((spb, gI, gU, [t.cpu().numpy() for t in sets]))
+        finally:
+            c.close()
     eI, eU = oracle.area_pairs(wl.A, wl.B, wl.pa, wl.pb, form=oracle.ROWS, threads=min(os.cpu_count() or 1, 16))
-    assert_exact(gI, gU, eI, eU, "set workload, 64 tiles")
     osi, osu, onn, oj, ojp = oracle.jaccard_sets(wl.set_off, eI, eU)
-    assert np.array_equal(si.cpu().numpy(), osi) and np.array_equal(su.cpu().numpy(), osu)
-    assert np.array_equal(nn.cpu().numpy(), onn)
-    assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(jp.cpu().numpy(), ojp)
+    for spb, gI, gU, (si, su, nn, j, jp) in got:
+        assert_exact(gI, gU, eI, eU, f"set workload, 64 tiles, sweep_pair_box {spb}")
+        assert np.array_equal(si, osi) and np.array_equal(su, osu)
+        assert np.array_equal(nn, onn)
+        assert np.array_equal(j, oj) and np.array_equal(jp, ojp)
 
 
 PLAIN_TUNINGS = [
@@ -226,6 +231,9 @@ BATCH_TUNINGS = [
     dict(flags=sccg.SCCG_F_NO_SEP), dict(flags=sccg.SCCG_F_PIXEL_ONLY),
     dict(flags=sccg.SCCG_F_NO_SEP, heavy_verts=1, min_queue_cells=1),
     dict(flags=sccg.SCCG_F_PIXEL_ONLY | sccg.SCCG_F_NO_KNOWN_INSIDE, heavy_verts=1, min_queue_cells=1),
+    dict(sweep_pair_box=2), dict(sweep_pair_box=2, flags=sccg.SCCG_F_NO_UNION_TILE),
+    dict(sweep_pair_box=2, queue_chunk=1, flags=sccg.SCCG_F_NO_GRAPH), dict(sweep_pair_box=2, flags=sccg.SCCG_F_NO_SEP),
+    dict(sweep_pair_box=2, flags=sccg.SCCG_F_PIXEL_ONLY),
 ]
 
 
@@ -415,10 +423,11 @@ def _boundary_pairs(seed=23, n=400):
     return ra, rb, expect
 
 
-@pytest.mark.parametrize("case", ["plain", "batched", "batched_heavy64"])
+@pytest.mark.parametrize("case", ["plain", "batched", "batched_heavy64", "batched_pair_box", "batched_pair_box_only"])
 def test_class_boundaries(case):
     """Counts at every class boundary of BATCHED mode equal the closed form
-    (and the oracle), in both modes and with heavy_verts moved to 64."""
+    (and the oracle), in both modes, with heavy_verts moved to 64, and with
+    the union sweep counting pair boxes (alone: without the union tile)."""
     ra, rb, expect = _boundary_pairs()
     A, B = concat(ra), concat(rb)
     idx = np.arange(len(ra), dtype=np.int32)
@@ -426,7 +435,9 @@ def test_class_boundaries(case):
     eU = np.array([e[1] for e in expect], np.int64)
     oI, oU = oracle.area_pairs(A, B, idx, idx, form=oracle.ROWS)
     assert np.array_equal(oI, eI) and np.array_equal(oU, eU)
-    c = sccg.Context(0, heavy_verts=64) if case == "batched_heavy64" else sccg.Context(0)
+    kw = {"batched_heavy64": dict(heavy_verts=64), "batched_pair_box": dict(sweep_pair_box=2),
+          "batched_pair_box_only": dict(sweep_pair_box=2, flags=sccg.SCCG_F_NO_UNION_TILE)}.get(case, {})
+    c = sccg.Context(0, **kw)
     try:
         mode = sccg.SCCG_PLAIN if case == "plain" else sccg.SCCG_BATCHED
         gI, gU = run(c, device_workload(A, B, idx, idx), mode)
@@ -464,6 +475,21 @@ def test_dense_band_rows(ctx, mode):
     assert_exact(gI, gU, eI, eU, f"dense band rows mode {mode}")
 
 
+@pytest.mark.parametrize("bad", [dict(sweep_pair_box=3), dict(sweep_pair_box=-1), dict(min_classify_cells=66),
+                                 dict(queue_chunk=65), dict(waves_per_wg=9), dict(wg_size=96)])
+def test_parameter_ranges(ctx, bad):
+    """A tuning value outside its documented range is refused with
+    SCCG_E_ARG, at creation and by set_params (which keeps the old values)."""
+    with pytest.raises(sccg.SccgError) as e:
+        sccg.Context(0, **bad)
+    assert e.value.code == sccg.SCCG_E_ARG
+    before = ctx.get_params()
+    with pytest.raises(sccg.SccgError) as e:
+        ctx.set_params(**bad)
+    assert e.value.code == sccg.SCCG_E_ARG
+    assert ctx.get_params() == before
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_empty_call_and_argument_errors(ctx, wl1, mode):
     import torch
@@ -496,13 +522,19 @@ def test_range_errors_latch_and_zero(ctx, mode):
     pa = np.array([0, 1, 2, 5], np.int32)
     pb = np.array([0, 1, 2, 0], np.int32)
     dwl = device_workload(A, B, pa, pb)
-    I, U = ctx.area_pairs(*dwl, mode=mode)
-    assert ctx.sync_code() == sccg.SCCG_E_RANGE
-    assert ctx.sync_code() == sccg.SCCG_OK  # latched error is cleared by the sync that reports it
-    gI, gU = I.cpu().numpy(), U.cpu().numpy()
-    assert gI.tolist() == [25, 0, 0, 0]
-    assert gU.tolist()[0] == 25 and gU.tolist()[1] == 0 and gU.tolist()[3] == 0
-    assert gU.tolist()[2] == 25  # the rejected polygon counts as empty
+    # BATCHED also with the union sweep counting pair boxes (where the side
+    # and coordinate checks then run)
+    ctxs = [ctx] + ([sccg.Context(0, sweep_pair_box=2)] if mode == sccg.SCCG_BATCHED else [])
+    for c in ctxs:
+        I, U = c.area_pairs(*dwl, mode=mode)
+        assert c.sync_code() == sccg.SCCG_E_RANGE
+        assert c.sync_code() == sccg.SCCG_OK  # latched error is cleared by the sync that reports it
+        gI, gU = I.cpu().numpy(), U.cpu().numpy()
+        assert gI.tolist() == [25, 0, 0, 0]
+        assert gU.tolist()[0] == 25 and gU.tolist()[1] == 0 and gU.tolist()[3] == 0
+        assert gU.tolist()[2] == 25  # the rejected polygon counts as empty
+    for c in ctxs[1:]:
+        c.close()
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -575,15 +607,15 @@ def test_comb_band_rows(mode, flags):
     cases = comb_pairs(150, 300) + comb_pairs(320, 200)
     A, B = concat([k[0] for k in cases]), concat([k[1] for k in cases])
     idx = np.arange(len(cases), dtype=np.int32)
-    for mcc in (1, 26, 65):
-        c = sccg.Context(0, flags=flags, min_classify_cells=mcc)
+    for mcc, spb in ((1, 1), (26, 1), (65, 1), (26, 2)):
+        c = sccg.Context(0, flags=flags, min_classify_cells=mcc, sweep_pair_box=spb)
         try:
             I, U = c.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
             assert c.sync_code() == sccg.SCCG_OK
             got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
         finally:
             c.close()
-        assert got == [(k[2], k[3]) for k in cases], f"min_classify_cells {mcc}"
+        assert got == [(k[2], k[3]) for k in cases], f"min_classify_cells {mcc}, sweep_pair_box {spb}"
 
 
 def _stair_bands(n_bands, x0, y0, width, step=1, h=1):
@@ -624,14 +656,14 @@ def test_tile_and_chunk_boundaries(ctx, mode):
     A, B = concat(rings_a), concat(rings_b)
     assert {4 * 16, 4 * 17, 4 * 32, 4 * 33} <= set(np.diff(A.off).tolist())
     idx = np.arange(len(cases), dtype=np.int32)
-    for flags in (0, sccg.SCCG_F_NO_UNION_TILE):
-        c = sccg.Context(0, flags=flags) if mode == sccg.SCCG_BATCHED else ctx
+    for flags, spb in ((0, 1), (sccg.SCCG_F_NO_UNION_TILE, 1), (0, 2), (sccg.SCCG_F_NO_UNION_TILE, 2)):
+        c = sccg.Context(0, flags=flags, sweep_pair_box=spb) if mode == sccg.SCCG_BATCHED else ctx
         I, U = c.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
         assert c.sync_code() == sccg.SCCG_OK
         got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
         if c is not ctx:
             c.close()
-        assert got == expect, f"flags {flags}"
+        assert got == expect, f"flags {flags}, sweep_pair_box {spb}"
 
 
 def test_validate_polys(ctx):
