@@ -1064,9 +1064,14 @@ constexpr int kSweepRing = 2 * kWave;                 // longest ring of the uni
 constexpr int kMediumRing = 4 * kWave;                // longest ring of the medium sweep
 constexpr int kSweepWaves = 4;                        // waves per workgroup of the sweep
 constexpr int kSweepRowTiles = 4;                     // widest box (in leaf tiles) the sweep pixelizes
-// Occupancy target of the sweep (waves per SIMD), a build-time tuning knob.
+// Occupancy target of the sweep (waves per SIMD), a build-time tuning knob;
+// the sweep that also counts pair boxes holds more wave-uniform values and
+// runs fewer waves, each with the largest scalar register file.
 #ifndef SCCG_SWEEP_WAVES_PER_EU
 #define SCCG_SWEEP_WAVES_PER_EU 8
+#endif
+#ifndef SCCG_SWEEP_PB_WAVES_PER_EU
+#define SCCG_SWEEP_PB_WAVES_PER_EU 6
 #endif
 
 // the lanes named by a wave-uniform mask (the mask is the lane condition)
@@ -1153,8 +1158,9 @@ __device__ __forceinline__ void ring_corners(const int2 (&d)[N], int nr, uint64_
 
 // Scatter of one ring of a union tile (see union_counts): every corner XORs
 // the rows at or above it into the slot of the rightmost column left of it.
-// `base`: the ring's first slot.  Returns the vertices scattered.
-template <typename M, int W, int R, int N>
+// `base`: the ring's first slot.  kClip: vertices may lie outside the tile
+// (see union_counts).  Returns the vertices scattered.
+template <typename M, int W, int R, int N, bool kClip = false>
 __device__ __forceinline__ uint32_t ring_scatter(M* slots, const int2 (&d)[N], int nr, int x0, int y0,
                                                  int lane, int base) {
   if (nr <= 0) return 0;
@@ -1164,7 +1170,8 @@ __device__ __forceinline__ uint32_t ring_scatter(M* slots, const int2 (&d)[N], i
 #pragma unroll
   for (int c = 0; c < N; ++c) {
     if (c * kWave < nr) {
-      const int dx = d[c].x - x0, ty = d[c].y - y0;
+      const int dx = kClip ? min(d[c].x, x0 + W) - x0 : d[c].x - x0;
+      const int ty = kClip ? max(min(d[c].y, y0 + R) - y0, 0) : d[c].y - y0;
       const uint64_t keep = cm[c] & ballot(dx > 0) & ballot(ty < R);
       M* sp = slots + (base + W - dx);
       if (lane_in(keep)) slot_xor(sp, 0, (M)(~(M)0 << ty));
@@ -1191,7 +1198,15 @@ __device__ __forceinline__ uint32_t ring_scatter(M* slots, const int2 (&d)[N], i
 // rows and columns past the union box come out outside, and nothing needs
 // clipping.  kHalves: W = 32, p's columns in lanes 0-31 and q's in lanes
 // 32-63, one scan; else W = 64 and one scan per ring.  M: 32- or 64-bit rows.
-template <bool kHalves, typename M, int N>
+//
+// kClip: the tile [x0, x0 + W) x [y0, y0 + R) is a pair box, and vertices
+// may lie outside it.  A corner left of it toggles none of its columns and
+// one right of it all of them (its x is taken as x0 + W); a corner below it
+// sets all of its rows and one above it none.  Every pixel's parities in the
+// tile stay exact, and a pixel of the tile outside the pair box is outside
+// MBR(p) or MBR(q), so the intersection count is exact; the union count is
+// not (the caller takes U from the areas).
+template <bool kHalves, typename M, int N, bool kClip = false>
 __device__ __forceinline__ uint32_t union_counts(Ctx& c, const PairRegs<N>& r, int np, int nq, int x0, int y0) {
   constexpr int W = kHalves ? 32 : kWave;
   constexpr int R = (int)sizeof(M) * 8;
@@ -1200,8 +1215,8 @@ __device__ __forceinline__ uint32_t union_counts(Ctx& c, const PairRegs<N>& r, i
   slots[lane] = (M)0;
   if (!kHalves) slots[kWave + lane] = (M)0;
   wave_sync_lds();
-  uint32_t kept = ring_scatter<M, W, R, N>(slots, r.p, np, x0, y0, lane, 0);
-  kept += ring_scatter<M, W, R, N>(slots, r.q, nq, x0, y0, lane, W);
+  uint32_t kept = ring_scatter<M, W, R, N, kClip>(slots, r.p, np, x0, y0, lane, 0);
+  kept += ring_scatter<M, W, R, N, kClip>(slots, r.q, nq, x0, y0, lane, W);
   wave_sync_lds();
   uint32_t t;
   if (kHalves) {
@@ -1270,14 +1285,11 @@ __device__ __forceinline__ uint32_t scatter_small_ring(uint64_t* slots, int2 v, 
 // A pair whose rings have at most 64 vertices each, one chunk per ring in
 // registers: when the union of its MBRs fits one leaf tile (and every
 // coordinate is in range), its counts packed as I | U << 16 in t, and true.
-__device__ __forceinline__ bool union_small(Ctx& c, int2 vp, int np, int2 vq, int nq, uint32_t& t) {
+// The counts of such a pair on its union box [x0, x1) x [y0, y1), which fits
+// one leaf tile, packed as I | U << 16 in t.
+__device__ __forceinline__ void union_small_box(Ctx& c, int2 vp, int np, int2 vq, int nq, int x0, int y0, int x1,
+                                                int y1, uint32_t& t) {
   const int lane = c.lane;
-  const int2 a = np > 0 ? vp : vq, b = nq > 0 ? vq : vp;  // an empty ring takes the other's vertices
-  const int x0 = wave_min_i32(min(a.x, b.x)), y0 = wave_min_i32(min(a.y, b.y));
-  const int x1 = wave_max_i32(max(a.x, b.x)), y1 = wave_max_i32(max(a.y, b.y));
-  if (!(x0 >= -kMaxCoord && y0 >= -kMaxCoord && x1 <= kMaxCoord && y1 <= kMaxCoord &&
-        side_u(x0, x1) <= (uint32_t)kTile && side_u(y0, y1) <= (uint32_t)kTile))
-    return false;
   const int uw = x1 - x0, uh = y1 - y0;
   const int W = uw <= 32 ? 32 : kWave;
   uint64_t* slots = c.slots;
@@ -1302,7 +1314,40 @@ __device__ __forceinline__ bool union_small(Ctx& c, int2 vp, int np, int2 vq, in
     stat_add(c, 0, 2ull * (unsigned long long)uw * uh);
     stat_add(c, 10, (unsigned long long)n);
   }
+}
+
+__device__ __forceinline__ bool union_small(Ctx& c, int2 vp, int np, int2 vq, int nq, uint32_t& t) {
+  const int2 a = np > 0 ? vp : vq, b = nq > 0 ? vq : vp;  // an empty ring takes the other's vertices
+  const int x0 = wave_min_i32(min(a.x, b.x)), y0 = wave_min_i32(min(a.y, b.y));
+  const int x1 = wave_max_i32(max(a.x, b.x)), y1 = wave_max_i32(max(a.y, b.y));
+  if (!(x0 >= -kMaxCoord && y0 >= -kMaxCoord && x1 <= kMaxCoord && y1 <= kMaxCoord &&
+        side_u(x0, x1) <= (uint32_t)kTile && side_u(y0, y1) <= (uint32_t)kTile))
+    return false;
+  union_small_box(c, vp, np, vq, nq, x0, y0, x1, y1, t);
   return true;
+}
+
+// The counts of such a pair on its union box [x0, x1) x [y0, y1), which fits
+// one leaf tile, packed as I | U << 16 in t.
+template <int N>
+__device__ __forceinline__ void union_pair_box(Ctx& c, const PairRegs<N>& r, int np, int nq, int x0, int y0, int x1,
+                                               int y1, uint32_t& t) {
+  const int uw = x1 - x0, uh = y1 - y0;
+  if (uw <= 32)
+    t = uh <= 32 ? union_counts<true, uint32_t, N>(c, r, np, nq, x0, y0)
+                 : union_counts<true, uint64_t, N>(c, r, np, nq, x0, y0);
+  else
+    t = uh <= 32 ? union_counts<false, uint32_t, N>(c, r, np, nq, x0, y0)
+                 : union_counts<false, uint64_t, N>(c, r, np, nq, x0, y0);
+  if (c.a->stats_on) {
+    const int n = np + nq;
+    stat_add(c, 5, 1ull);
+    stat_add(c, 11, (unsigned long long)uw * uh);
+    stat_add(c, 13, (unsigned long long)n);
+    stat_add(c, 1, 1ull);
+    stat_add(c, 0, 2ull * (unsigned long long)uw * uh);
+    stat_add(c, 10, (unsigned long long)n);
+  }
 }
 
 // A pair held in registers: when the union of its MBRs fits one leaf tile
@@ -1328,36 +1373,18 @@ __device__ __forceinline__ bool union_pair(Ctx& c, const PairRegs<N>& r, int np,
   if (!(x0 >= -kMaxCoord && y0 >= -kMaxCoord && x1 <= kMaxCoord && y1 <= kMaxCoord &&
         side_u(x0, x1) <= (uint32_t)kTile && side_u(y0, y1) <= (uint32_t)kTile))
     return false;
-  const int uw = x1 - x0, uh = y1 - y0;
-  if (uw <= 32)
-    t = uh <= 32 ? union_counts<true, uint32_t, N>(c, r, np, nq, x0, y0)
-                 : union_counts<true, uint64_t, N>(c, r, np, nq, x0, y0);
-  else
-    t = uh <= 32 ? union_counts<false, uint32_t, N>(c, r, np, nq, x0, y0)
-                 : union_counts<false, uint64_t, N>(c, r, np, nq, x0, y0);
-  if (c.a->stats_on) {
-    const int n = np + nq;
-    stat_add(c, 5, 1ull);
-    stat_add(c, 11, (unsigned long long)uw * uh);
-    stat_add(c, 13, (unsigned long long)n);
-    stat_add(c, 1, 1ull);
-    stat_add(c, 0, 2ull * (unsigned long long)uw * uh);
-    stat_add(c, 10, (unsigned long long)n);
-  }
+  union_pair_box<N>(c, r, np, nq, x0, y0, x1, y1, t);
   return true;
 }
-// Extent and |shoelace|/2 of a ring held in registers (Section 3.2's area
-// formula; one or two chunks, lanes past the end holding the last vertex
-// again).  Twice the signed area is summed modulo 2^64 and its magnitude
-// taken unsigned, which is exact while it stays within 2^63.  A ring with a
-// coordinate beyond 2^30 comes back empty, with area 0 and `bad` set.
+
+// Extent of a ring held in registers (one or more chunks, lanes past the end
+// holding the last vertex again): pixels [x0, x1) x [y0, y1) of its vertices.
+// An empty ring, or one with a coordinate beyond 2^30 (returns true), comes
+// back as the empty extent {INT_MAX, INT_MAX, INT_MIN, INT_MIN}.
 template <int N>
-__device__ __forceinline__ void ring_meta_regs(const int2 (&d)[N], int nr, int lane, Meta& m, int64_t& area,
-                                               bool& bad) {
+__device__ __forceinline__ bool ring_extent_regs(const int2 (&d)[N], int nr, Meta& m) {
   m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};
-  area = 0;
-  bad = false;
-  if (nr <= 0) return;
+  if (nr <= 0) return false;
   const int nc = (nr + kWave - 1) / kWave;
   int mnx = d[0].x, mny = d[0].y, mxx = mnx, mxy = mny;
 #pragma unroll
@@ -1370,16 +1397,29 @@ __device__ __forceinline__ void ring_meta_regs(const int2 (&d)[N], int nr, int l
     }
   }
   const Meta e{wave_min_i32(mnx), wave_min_i32(mny), wave_max_i32(mxx), wave_max_i32(mxy)};
-  if (e.x0 < -kMaxCoord || e.y0 < -kMaxCoord || e.x1 > kMaxCoord || e.y1 > kMaxCoord) {
-    bad = true;
-    return;
-  }
+  if (e.x0 < -kMaxCoord || e.y0 < -kMaxCoord || e.x1 > kMaxCoord || e.y1 > kMaxCoord) return true;
   m = e;
+  return false;
+}
+
+// |shoelace|/2 of a non-empty ring held in registers whose extent e is in
+// range (Section 3.2's area formula).  Twice the signed area is summed modulo
+// 2^32 for a ring at most 32767 pixels on a side, else modulo 2^64, and its
+// magnitude taken, which is exact while it stays within 2^31 (2^63).
+template <int N>
+__device__ __forceinline__ int64_t ring_area_regs(const int2 (&d)[N], int nr, int lane, const Meta& e) {
+  const int nc = (nr + kWave - 1) / kWave;
+  // A simple ring at most 32767 pixels wide and tall has |twice its area|
+  // below 2^31: summed from coordinates relative to its first vertex (the
+  // sum does not depend on the origin) it is exact modulo 2^32 in 32-bit
+  // lanes.
+  const bool narrow = side_u(e.x0, e.x1) <= (uint32_t)kMaxSide && side_u(e.y0, e.y1) <= (uint32_t)kMaxSide;
   // each vertex's successor: the next lane, the next chunk's first lane, and
   // the first vertex after the last
   const int le = (nr - 1) & (kWave - 1);
   const int2 f = lane_value(d[0], 0);
   uint64_t tw = 0;
+  uint32_t tn = 0;
 #pragma unroll
   for (int c = 0; c < N; ++c) {
     if (c < nc) {
@@ -1391,12 +1431,33 @@ __device__ __forceinline__ void ring_meta_regs(const int2 (&d)[N], int nr, int l
         sx = f.x;
         sy = f.y;
       }
-      if (!last_chunk || lane <= le)
-        tw += (uint64_t)((int64_t)d[c].x * sy) - (uint64_t)((int64_t)sx * d[c].y);
+      if (!last_chunk || lane <= le) {
+        if (narrow) {
+          const uint32_t ux = (uint32_t)d[c].x - (uint32_t)f.x, uy = (uint32_t)d[c].y - (uint32_t)f.y;
+          const uint32_t vx = (uint32_t)sx - (uint32_t)f.x, vy = (uint32_t)sy - (uint32_t)f.y;
+          tn += ux * vy - vx * uy;
+        } else {
+          tw += (uint64_t)((int64_t)d[c].x * sy) - (uint64_t)((int64_t)sx * d[c].y);
+        }
+      }
     }
   }
+  if (narrow) {
+    const int32_t t = (int32_t)wave_sum_u32(tn);
+    return (t < 0 ? -(int64_t)t : (int64_t)t) / 2;
+  }
   const uint64_t t = wave_sum_u64(tw);
-  area = (int64_t)(((int64_t)t < 0 ? 0 - t : t) / 2);
+  return (int64_t)(((int64_t)t < 0 ? 0 - t : t) / 2);
+}
+
+// Extent and area of a ring held in registers (see ring_extent_regs and
+// ring_area_regs); an empty or rejected ring has area 0, and a rejected one
+// sets `bad`.
+template <int N>
+__device__ __forceinline__ void ring_meta_regs(const int2 (&d)[N], int nr, int lane, Meta& m, int64_t& area,
+                                               bool& bad) {
+  bad = ring_extent_regs(d, nr, m);
+  area = nr > 0 && !bad ? ring_area_regs(d, nr, lane, m) : 0;
 }
 
 // Count of a pair box [bx0, bx1) x [by0, by1) at most kSweepRowTiles leaf
@@ -1483,11 +1544,9 @@ __device__ __forceinline__ uint64_t sweep_rows(Ctx& c, const PairRegs<N>& r, int
 // out of range: I and U are final), or small / large (the pair is to be
 // listed for the persistent kernel with `box`, I = 0 and U = |p| + |q|, or 0
 // when the union is counted directly, as the values its boxes add to).
-// small_only: a pair that would be large is returned as large with nothing
-// counted in the statistics (another pass takes it and counts it).
 template <int N>
 __device__ __forceinline__ uint8_t sweep_meta(Ctx& c, const PairRegs<N>& r, int np, int nq, int64_t& I, int64_t& U,
-                                              Meta& box, bool small_only = false) {
+                                              Meta& box) {
   const BatchArgs& a = *c.a;
   Meta mp, mq;
   int64_t ap, aq;
@@ -1513,7 +1572,6 @@ __device__ __forceinline__ uint8_t sweep_meta(Ctx& c, const PairRegs<N>& r, int 
     return kClsDone;
   }
   const bool small = bw <= (uint32_t)kTile && bh <= (uint32_t)kTile;
-  if (small_only && !small) return kClsLarge;
   stat_add(c, 12, (unsigned long long)(np + nq));
   stat_add(c, small ? 5 : 6, 1ull);
   stat_add(c, 11, (unsigned long long)bw * bh);
@@ -1609,36 +1667,33 @@ __device__ __forceinline__ void sweep_load(const BatchArgs& a, const SweepRec& s
   }
 }
 
-// A sweep pair that its union tile did not take, from its rings in
-// registers: MBRs and areas, and when the pair box MBR(p) ∩ MBR(q) is empty
-// or fits one leaf tile, I over that box and U = |p| + |q| - I (Section 3.2),
-// written out at once, and true.  A larger pair box is left, with nothing
-// written or counted, to the medium sweep (false).
-__device__ __forceinline__ bool pair_tile(Ctx& c, const SweepRec& s, const PairRegs<kUnionChunks>& r, int64_t i) {
-  int64_t I = 0, U = 0;
-  Meta box{0, 0, 0, 0};
-  const uint8_t cls = sweep_meta(c, r, s.np, s.nq, I, U, box, true);
-  if (cls == kClsLarge) return false;
-  if (cls == kClsSmall) {
-    I = (int64_t)sweep_rows<kUnionChunks, kWave>(c, r, s.np, s.nq, box);
-    U -= I;
+// I of a pair whose pair box fits one leaf tile, counted on that box (see
+// union_counts with clipping): its columns in one half of the wave when it
+// is at most 32 wide, 32-bit rows when it is at most 32 tall.
+template <int N>
+__device__ __forceinline__ uint32_t pair_box_count(Ctx& c, const PairRegs<N>& r, int np, int nq, const Meta& box) {
+  const int bw = box.x1 - box.x0, bh = box.y1 - box.y0;
+  uint32_t t;
+  if (bw <= 32)
+    t = bh <= 32 ? union_counts<true, uint32_t, N, true>(c, r, np, nq, box.x0, box.y0)
+                 : union_counts<true, uint64_t, N, true>(c, r, np, nq, box.x0, box.y0);
+  else
+    t = bh <= 32 ? union_counts<false, uint32_t, N, true>(c, r, np, nq, box.x0, box.y0)
+                 : union_counts<false, uint64_t, N, true>(c, r, np, nq, box.x0, box.y0);
+  if (c.a->stats_on) {
+    stat_add(c, 1, 1ull);
+    stat_add(c, 0, 2ull * (unsigned long long)bw * bh);
+    stat_add(c, 10, (unsigned long long)(np + nq));
   }
-  if (c.lane == 0) {
-    c.a->inter[i] = I;
-    c.a->uni[i] = U;
-  }
-  return true;
+  return t & 0xffffu;
 }
 
-// Pair j of the chunk (a sweep pair, index i0 + j): counted on its union
-// tile, leaving I | U << 16 in lane j of `packed` and bit j in `wmask`
-// (written out with the chunk); else, with kPairBox and the union not being
-// counted directly, counted on its pair box when that fits one leaf tile,
-// written out at once, with bit j in `dmask`; a pair left out goes to the
-// medium list with the chunk.
-template <bool kPairBox>
-__device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairRegs<kUnionChunks>& r, int64_t i0,
-                                          int j, bool union_ok, uint32_t& packed, uint64_t& wmask, uint64_t& dmask) {
+// Pair j of the chunk (a sweep pair): counted on its union tile, leaving
+// I | U << 16 in lane j of `packed` and bit j in `wmask` (written out with
+// the chunk); a pair left out (union box larger than a leaf tile) goes to
+// the medium list with the chunk.
+__device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairRegs<kUnionChunks>& r, int j,
+                                          bool union_ok, uint32_t& packed, uint64_t& wmask) {
   if (s.cls != kClsSweep) return;  // another class, or a bad index
   const int lane = c.lane;
   uint32_t t = 0;
@@ -1650,9 +1705,86 @@ __device__ __forceinline__ void sweep_one(Ctx& c, const SweepRec& s, const PairR
   if (done) {
     if (lane == j) packed = t;
     wmask |= 1ull << j;
-  } else if (kPairBox && !direct_union(*c.a) && pair_tile(c, s, r, i0 + j)) {
-    dmask |= 1ull << j;
   }
+}
+
+// Extent and area of a ring held wave-uniform; area < 0 until it is needed.
+struct RingInfo {
+  Meta m;
+  int64_t area;
+  bool bad;
+};
+
+// Pair j of the chunk (a sweep pair, index i0 + j) when the union sweep also
+// counts pair boxes.  Both rings' extents come first, q's carried over from
+// the previous pair of the wave when it is the same ring (a join's output
+// grouped by one side repeats it).  When their union fits one leaf tile the
+// pair is counted there, as in sweep_one; else, the union not being counted
+// directly, the pair box MBR(p) ∩ MBR(q) decides as in the medium sweep: an
+// empty box (nothing in common) or one that fits a leaf tile gives I and
+// U = |p| + |q| - I (Section 3.2), written out at once with bit j in
+// `dmask`; a box side out of range latches the error and gives I = U = 0; a
+// larger box goes, with nothing counted, to the medium list with the chunk.
+__device__ __forceinline__ void sweep_one_pb(Ctx& c, const SweepRec& s, const PairRegs<kUnionChunks>& r, int64_t i0,
+                                             int j, bool union_ok, uint32_t& packed, uint64_t& wmask, uint64_t& dmask,
+                                             int64_t& q_off, int& q_n, RingInfo& qi) {
+  if (s.cls != kClsSweep) return;  // another class, or a bad index
+  const BatchArgs& a = *c.a;
+  const int lane = c.lane;
+  if (s.np + s.nq == 0) {  // two empty rings: nothing in either
+    stat_add(c, 7, 1ull);
+    if (lane == j) packed = 0;
+    wmask |= 1ull << j;
+    return;
+  }
+  RingInfo pi;
+  pi.bad = ring_extent_regs(r.p, s.np, pi.m);
+  pi.area = -1;
+  if (s.oq != q_off || s.nq != q_n) {
+    qi.bad = ring_extent_regs(r.q, s.nq, qi.m);
+    qi.area = -1;
+    q_off = s.oq;
+    q_n = s.nq;
+  }
+  const bool ok = !pi.bad && !qi.bad;
+  const Meta u = union_box(pi.m, qi.m);  // an empty ring's extent drops out
+  if (union_ok && ok && side_u(u.x0, u.x1) <= (uint32_t)kTile && side_u(u.y0, u.y1) <= (uint32_t)kTile) {
+    uint32_t t;
+    if (s.np <= kWave && s.nq <= kWave)
+      union_small_box(c, r.p[0], s.np, r.q[0], s.nq, u.x0, u.y0, u.x1, u.y1, t);
+    else
+      union_pair_box<kUnionChunks>(c, r, s.np, s.nq, u.x0, u.y0, u.x1, u.y1, t);
+    if (lane == j) packed = t;
+    wmask |= 1ull << j;
+    return;
+  }
+  if (direct_union(a)) return;
+  const Meta box = pair_box(pi.m, qi.m);  // empty when a ring is empty or rejected
+  const bool empty = box.x0 >= box.x1 || box.y0 >= box.y1;
+  const uint32_t bw = side_u(box.x0, box.x1), bh = side_u(box.y0, box.y1);
+  const bool wide = !empty && (bw > (uint32_t)kMaxSide || bh > (uint32_t)kMaxSide);
+  const bool small = !empty && !wide && bw <= (uint32_t)kTile && bh <= (uint32_t)kTile;
+  if (!empty && !wide && !small) return;
+  if (lane == 0 && !ok) latch_error(a.err, kErrCoord);
+  if (lane == 0 && wide) latch_error(a.err, kErrSide);
+  stat_add(c, 12, (unsigned long long)(s.np + s.nq));
+  stat_add(c, small ? 5 : 7, 1ull);
+  if (small) stat_add(c, 11, (unsigned long long)bw * bh);
+  int64_t I = 0, U = 0;
+  if (!wide) {
+    if (pi.area < 0) pi.area = s.np > 0 && !pi.bad ? ring_area_regs(r.p, s.np, lane, pi.m) : 0;
+    if (qi.area < 0) qi.area = s.nq > 0 && !qi.bad ? ring_area_regs(r.q, s.nq, lane, qi.m) : 0;
+    U = pi.area + qi.area;
+    if (small) {
+      I = (int64_t)pair_box_count(c, r, s.np, s.nq, box);
+      U -= I;
+    }
+  }
+  if (lane == 0) {
+    a.inter[i0 + j] = I;
+    a.uni[i0 + j] = U;
+  }
+  dmask |= 1ull << j;
 }
 
 // The prepass of the pairs the setup pass listed: per pair, one wave
@@ -1719,7 +1851,8 @@ __global__ void __launch_bounds__(256) k_batch_prepass(BatchArgs args) {
 // loading the rings again); a separate instance keeps the extra registers
 // off the plain sweep, which most mixes run.
 template <bool kPairBox>
-__global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_waves_per_eu(SCCG_SWEEP_WAVES_PER_EU)))
+__global__ void __launch_bounds__(kSweepWaves* kWave)
+    __attribute__((amdgpu_waves_per_eu(kPairBox ? SCCG_SWEEP_PB_WAVES_PER_EU : SCCG_SWEEP_WAVES_PER_EU)))
 k_batch_sweep(BatchArgs args) {
   __shared__ __align__(16) uint64_t sweep_slots[kSweepWaves * kLeafSlots];
   Ctx c;
@@ -1739,6 +1872,10 @@ k_batch_sweep(BatchArgs args) {
   // that running dry costs it one claim, not one per stream (a grid too
   // small to give every stream a workgroup claims from all of them)
   uint32_t s_empty = kSweepSteal || gridDim.x < (unsigned)kStreams ? 0u : (0xffu & ~(1u << c.xcd));
+  // kPairBox: the last q ring whose extent (and area, once needed) is held
+  int64_t q_off = -1;
+  int q_n = -1;
+  RingInfo qi{Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN}, 0, false};
   for (;;) {
     const int64_t i0 = claim_chunk(a.st->s_next, a.n_pairs, a.chunk, c.xcd, lane, s_empty);
     if (i0 < 0) break;
@@ -1759,7 +1896,10 @@ k_batch_sweep(BatchArgs args) {
     }
 #pragma unroll 1
     for (int j = 0; j < cnt; ++j) {
-      sweep_one<kPairBox>(c, s[0], r[0], i0, j, union_ok, packed, wmask, dmask);
+      if (kPairBox)
+        sweep_one_pb(c, s[0], r[0], i0, j, union_ok, packed, wmask, dmask, q_off, q_n, qi);
+      else
+        sweep_one(c, s[0], r[0], j, union_ok, packed, wmask);
 #pragma unroll
       for (int k = 0; k < kSweepAhead; ++k) {
         s[k] = s[k + 1];
@@ -1810,7 +1950,11 @@ __device__ __forceinline__ void medium_one(Ctx& c, const SweepRec& s, const Pair
   uint8_t cls = sweep_meta(c, r, s.np, s.nq, I, U, box);
   if (cls != kClsDone && !direct_union(a)) {
     const int gx = (box.x1 - box.x0 + kTile - 1) / kTile, gy = (box.y1 - box.y0 + kTile - 1) / kTile;
-    if (gx <= kSweepRowTiles && gy <= kMaxGrid && (gx * gy == 1 || gx * gy < a.min_classify_cells)) {
+    if (gx * gy == 1) {
+      I = (int64_t)pair_box_count(c, r, s.np, s.nq, box);
+      U -= I;
+      cls = kClsDone;
+    } else if (gx <= kSweepRowTiles && gy <= kMaxGrid && gx * gy < a.min_classify_cells) {
       I = (int64_t)sweep_rows(c, r, s.np, s.nq, box);
       U -= I;
       cls = kClsDone;
@@ -2094,27 +2238,29 @@ int batch_occupancy(int waves_per_wg) {
   return n > 0 ? n : 1;
 }
 
-int batch_sweep_occupancy() {
-  int n = 0, m = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep<false>, kSweepWaves * kWave, 0) != hipSuccess)
-    return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_batch_sweep<true>, kSweepWaves * kWave, 0) != hipSuccess)
-    return 1;
-  n = n < m ? n : m;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, k_batch_medium, kSweepWaves * kWave, 0) != hipSuccess) return 1;
-  n = n < m ? n : m;
-  return n > 0 ? n : 1;
+int batch_sweep_occupancy(bool pair_box) {
+  int n = 0;
+  const hipError_t e =
+      pair_box ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep<true>, kSweepWaves * kWave, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep<false>, kSweepWaves * kWave, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+
+int batch_medium_occupancy() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_medium, kSweepWaves * kWave, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
 }
 
 int batch_sweep_waves_per_wg() { return kSweepWaves; }
 
-hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, bool pair_box, hipStream_t s) {
+hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, int medium_grid, bool pair_box, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
   if (pair_box)
     hipLaunchKernelGGL(k_batch_sweep<true>, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
   else
     hipLaunchKernelGGL(k_batch_sweep<false>, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
-  hipLaunchKernelGGL(k_batch_medium, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
+  hipLaunchKernelGGL(k_batch_medium, dim3(medium_grid), dim3(kSweepWaves * kWave), 0, s, a);
   return hipGetLastError();
 }
 

@@ -478,19 +478,19 @@ __global__ void k_zero_stats(unsigned long long* s) {
 // the prepass of listed pairs, the two sweeps, the persistent kernel.  (A
 // prepass on a second stream beside the sweeps measured no faster: it takes
 // the sweeps' issue slots.)
-static int launch_batch_sequence(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int grid) {
+static int launch_batch_sequence(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int medium_grid, int grid) {
   hipError_t e;
   if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
   if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
   if ((e = launch_batch_prepass(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch prepass");
-  if ((e = launch_batch_sweeps(ba, sweep_grid, c->p.sweep_pair_box == 2, c->stream)) != hipSuccess)
+  if ((e = launch_batch_sweeps(ba, sweep_grid, medium_grid, c->p.sweep_pair_box == 2, c->stream)) != hipSuccess)
     return hip_fail(c, e, "batch sweeps");
   if ((e = launch_batch_persistent(ba, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)
     return hip_fail(c, e, "batch persistent kernel");
   return SCCG_OK;
 }
 
-static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int grid) {
+static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int medium_grid, int grid) {
   hipError_t e;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (c->timing_on) {
@@ -498,7 +498,7 @@ static int launch_batched(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int 
     if (r) return r;
     HIP_TRY(c, hipEventRecord(t0, c->stream));
   }
-  if (int r = launch_batch_sequence(c, ba, sweep_grid, grid)) return r;
+  if (int r = launch_batch_sequence(c, ba, sweep_grid, medium_grid, grid)) return r;
   if (c->timing_on) HIP_TRY(c, hipEventRecord(t1, c->stream));
   return SCCG_OK;
 }
@@ -583,12 +583,14 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
   ba.stats_on = c->stats_on;
   int grid = c->p.grid;
   if (grid == 0) grid = c->cu_count * batch_occupancy(c->p.waves_per_wg);
-  const int sweep_grid = c->cu_count * batch_sweep_occupancy();
+  const int sweep_grid = c->cu_count * batch_sweep_occupancy(c->p.sweep_pair_box == 2);
+  const int medium_grid = c->cu_count * batch_medium_occupancy();
   if (c->stamps_on) {
     // every wave of the sweeps and of the persistent kernel stamps its start and end
     const int64_t sweep_waves = (int64_t)sweep_grid * batch_sweep_waves_per_wg();
+    const int64_t medium_waves = (int64_t)medium_grid * batch_sweep_waves_per_wg();
     const int64_t run_waves = (int64_t)grid * c->p.waves_per_wg;
-    const int64_t want = std::max(sweep_waves, run_waves);
+    const int64_t want = std::max(std::max(sweep_waves, medium_waves), run_waves);
     if (want > c->wave_cap) {
       (void)hipStreamSynchronize(c->stream);
       drop_graph(c);
@@ -600,11 +602,12 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
     }
     ba.wave_t = c->wave_t;
     ba.wave_cap = (int32_t)c->wave_cap;
-    c->wave_n[0] = c->wave_n[1] = sweep_waves;
+    c->wave_n[0] = sweep_waves;
+    c->wave_n[1] = medium_waves;
     c->wave_n[2] = run_waves;
   }
   const bool use_graph = c->stream != nullptr && !(c->p.flags & SCCG_F_NO_GRAPH) && !c->timing_on;
-  if (!use_graph) return launch_batched(c, ba, sweep_grid, grid);
+  if (!use_graph) return launch_batched(c, ba, sweep_grid, medium_grid, grid);
   // the graph is keyed on every launch argument
   char key[512];
   snprintf(key, sizeof(key), "%lld/%p/%p|%lld/%p/%p|%lld/%p/%p/%p/%p|%d/%d/%d/%d/%d/%d/%u/%d/%d/%d",
@@ -617,7 +620,7 @@ int sccg_area_pairs(sccg_ctx* c, const sccg_polys* A, const sccg_polys* B, int64
     drop_graph(c);
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    r = launch_batched(c, ba, sweep_grid, grid);
+    r = launch_batched(c, ba, sweep_grid, medium_grid, grid);
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (r) {
       if (g) (void)hipGraphDestroy(g);
@@ -696,8 +699,9 @@ int sccg_area_pairs_noalloc(sccg_ctx* c, const sccg_polys* A, const sccg_polys* 
   ba.stats_on = 0;
   int grid = c->p.grid;
   if (grid == 0) grid = c->cu_count * batch_occupancy(c->p.waves_per_wg);
-  const int sweep_grid = c->cu_count * batch_sweep_occupancy();
-  return launch_batch_sequence(c, ba, sweep_grid, grid);
+  const int sweep_grid = c->cu_count * batch_sweep_occupancy(c->p.sweep_pair_box == 2);
+  const int medium_grid = c->cu_count * batch_medium_occupancy();
+  return launch_batch_sequence(c, ba, sweep_grid, medium_grid, grid);
 }
 
 int sccg_jaccard_sets(sccg_ctx* c, int64_t n_sets, const int64_t* set_pair_off, const int64_t* inter,

@@ -146,15 +146,18 @@ hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s);
 // The prepass of the pairs the setup pass listed.
 hipError_t launch_batch_prepass(const BatchArgs& a, hipStream_t s);
-// The union sweep then the medium sweep (sweep_grid workgroups each);
+// The union sweep (sweep_grid workgroups) then the medium sweep (medium_grid);
 // pair_box: the union sweep also counts the pairs whose pair box fits a leaf
 // tile (else the medium sweep does).
-hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, bool pair_box, hipStream_t s);
+hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, int medium_grid, bool pair_box, hipStream_t s);
 // The persistent kernel (grid workgroups).
 hipError_t launch_batch_persistent(const BatchArgs& a, int grid, int waves_per_wg, hipStream_t s);
 int batch_lds_bytes_per_wave();
 int batch_occupancy(int waves_per_wg);
-int batch_sweep_occupancy();
+// Workgroups per CU of the union sweep (the instance that counts pair boxes
+// or the one that does not) and of the medium sweep.
+int batch_sweep_occupancy(bool pair_box);
+int batch_medium_occupancy();
 int batch_sweep_waves_per_wg();
 
 // Set-level Jaccard: per-set accumulators (a cache line each), a chunk
