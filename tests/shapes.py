@@ -120,7 +120,8 @@ def limit_cases():
     largest accepted, where a coordinate minus a box side reaches 2^31.  In
     every pair q lies inside p, so I = |q| and U = |p|.  The pair boxes cover
     one leaf tile, a split into a few tiles, and a split that classifies
-    cells; the last pair's p has twice its area equal to 2^63."""
+    cells; the last two pairs' p has twice its area equal to 2^63 (and the
+    last one's pair box fits one leaf tile at the top corner of the range)."""
     M = 1 << 30
     return [
         ((0, -M, 10, M), (0, -M, 10, -M + 5)),
@@ -130,6 +131,7 @@ def limit_cases():
         ((-M, 0, M, 100), (-M, 0, -M + 100, 100)),
         ((0, -M, 600, M), (0, -M, 600, -M + 600)),
         ((-M, -M, M, M), (M - 70, M - 70, M, M)),
+        ((-M, -M, M, M), (M - 40, M - 30, M, M)),
     ]
 
 

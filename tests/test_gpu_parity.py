@@ -221,6 +221,18 @@ def test_plain_tuning_invariance(wl3s, params):
     assert_exact(gI, gU, eI[sel], eU[sel], f"plain {params}")
 
 
+def with_pair_box_sweep(ctx, mode):
+    """ctx, then for BATCHED a context whose union sweep also counts pair
+    boxes (closed when the caller's loop ends)."""
+    yield ctx
+    if mode == sccg.SCCG_BATCHED:
+        c = sccg.Context(0, sweep_pair_box=2)
+        try:
+            yield c
+        finally:
+            c.close()
+
+
 BATCH_TUNINGS = [
     dict(queue_cap=1), dict(queue_cap=3, min_queue_cells=1), dict(min_queue_cells=1), dict(min_queue_cells=65),
     dict(flags=sccg.SCCG_F_NO_SPLIT_QUEUE), dict(flags=sccg.SCCG_F_NO_KNOWN_INSIDE),
@@ -559,10 +571,11 @@ def test_wide_rings_exact_areas(ctx, mode):
         expect.append((i, rects_area(ra) + rects_area(rb) - i))
     A, B = concat(rings_a), concat(rings_b)
     idx = np.arange(len(cases), dtype=np.int32)
-    I, U = ctx.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
-    assert ctx.sync_code() == sccg.SCCG_OK
-    got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
-    assert got == expect
+    for c in with_pair_box_sweep(ctx, mode):
+        I, U = c.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
+        assert c.sync_code() == sccg.SCCG_OK
+        got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
+        assert got == expect, f"params {c.get_params()}"
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -575,10 +588,11 @@ def test_coordinates_at_the_limit(ctx, mode):
     A, B = concat([rect_ring(p) for p, _ in cases]), concat([rect_ring(q) for _, q in cases])
     area = lambda r: (r[2] - r[0]) * (r[3] - r[1])
     idx = np.arange(len(cases), dtype=np.int32)
-    I, U = ctx.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
-    assert ctx.sync_code() == sccg.SCCG_OK
-    got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
-    assert got == [(area(q), area(p)) for p, q in cases]
+    for c in with_pair_box_sweep(ctx, mode):
+        I, U = c.area_pairs(*device_workload(A, B, idx, idx), mode=mode)
+        assert c.sync_code() == sccg.SCCG_OK
+        got = list(zip(I.cpu().numpy().tolist(), U.cpu().numpy().tolist()))
+        assert got == [(area(q), area(p)) for p, q in cases], f"params {c.get_params()}"
 
 
 @pytest.mark.parametrize("mode", MODES)
