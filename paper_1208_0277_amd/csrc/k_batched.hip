@@ -116,6 +116,7 @@ __device__ __forceinline__ int clamp_to(int x, int lo, int hi) { return min(max(
 // ----------------------------------------------------------------- context
 struct Ctx {
   const BatchArgs* a;
+  bool stats;       // work counters on (a compile-time false in the sweeps' plain instances)
   int lane;
   uint64_t* slots;  // per-wave leaf slots (kLeafSlots; in the persistent kernel, two band rows' worth)
   uint64_t* local;  // per-wave inline stack, kLocalCap entries
@@ -148,7 +149,7 @@ __device__ __forceinline__ void wave_stamps(const BatchArgs& a, int kernel, unsi
 }
 
 __device__ __forceinline__ void stat_add(const Ctx& c, int k, unsigned long long v) {
-  if (c.a->stats_on && c.lane == 0 && v) atomicAdd(&c.a->st->stats[k], v);
+  if (c.stats && c.lane == 0 && v) atomicAdd(&c.a->st->stats[k], v);
 }
 
 // What a wave needs to work on one pair.
@@ -518,7 +519,7 @@ __device__ __forceinline__ void scatter_ring(Ctx& c, const int2* xy, int64_t o, 
       else
         slot_xor(slots, base + slot, rr);
     }
-    if (c.a->stats_on) kept += (uint32_t)__popcll(ballot(keep));
+    if (c.stats) kept += (uint32_t)__popcll(ballot(keep));
   };
   int b0 = 0;
   int2 first;
@@ -538,7 +539,7 @@ __device__ __forceinline__ void scatter_ring(Ctx& c, const int2* xy, int64_t o, 
       one(rs.cur, w, rs.valid());
     } while (rs.next());
   }
-  if (c.a->stats_on) {
+  if (c.stats) {
     stat_add(c, 8, (unsigned long long)kept);
     stat_add(c, 10, (unsigned long long)nv);
   }
@@ -604,7 +605,7 @@ __device__ __forceinline__ int64_t leaf_small(Ctx& c, const PairInfo& pi, const 
     }
   }
   wave_sync_lds();
-  if (a.stats_on) {
+  if (c.stats) {
     stat_add(c, 1, 1ull);
     stat_add(c, 0, 2ull * (unsigned long long)tw * th);
   }
@@ -632,7 +633,7 @@ __device__ __forceinline__ uint64_t leaf_count(Ctx& c, const PairInfo& pi, int t
   const bool in_tile = kWave - 1 - lane < tw;
   const uint32_t n = in_tile ? (uint32_t)__popcll(mp & mq) : 0u;
   const uint32_t nu = in_tile ? (uint32_t)__popcll(mp | mq) : 0u;
-  if (a.stats_on) {
+  if (c.stats) {
     stat_add(c, 1, 1ull);
     stat_add(c, 0, (unsigned long long)tw * th * ((kp ? 0 : 1) + (kq ? 0 : 1)));
   }
@@ -667,9 +668,9 @@ __device__ __forceinline__ void scatter_row(Ctx& c, const int2* xy, int64_t o, i
     uint64_t rr = 0;
     const bool keep = rs.valid() && leaf_edge(rs.cur, w, bx0, ry0, th, wpad, slot, rr);
     if (keep) slot_xor(slots, slot, rr);
-    if (c.a->stats_on) kept += (uint32_t)__popcll(ballot(keep));
+    if (c.stats) kept += (uint32_t)__popcll(ballot(keep));
   } while (rs.next());
-  if (c.a->stats_on) {
+  if (c.stats) {
     stat_add(c, 8, (unsigned long long)kept);
     stat_add(c, 10, (unsigned long long)n);
   }
@@ -738,7 +739,7 @@ __device__ __forceinline__ void leaf_rows(Ctx& c, const PairInfo& pi, int bx0, i
   }
   const uint64_t si = wave_sum_u32(ni);
   acc += direct ? (si | ((uint64_t)wave_sum_u32(nu) << 32)) : si;
-  if (a.stats_on) {
+  if (c.stats) {
     stat_add(c, 1, n_leaf);
     stat_add(c, 0, n_tests);
   }
@@ -878,7 +879,7 @@ __device__ __forceinline__ void emit_children(Ctx& c, const PairInfo& pi, uint64
       const unsigned long long prev = atomicCAS(slot, 0ull, (unsigned long long)word);
       keep = prev != 0ull;  // skip-marked: the box stays here
     }
-    if (a.stats_on) {
+    if (c.stats) {
       const int kept = __popcll(ballot(keep));
       stat_add(c, 3, (unsigned long long)(n - kept));
       stat_add(c, 4, (unsigned long long)kept);
@@ -1304,7 +1305,7 @@ __device__ __forceinline__ void union_small_box(Ctx& c, int2 vp, int np, int2 vq
   else
     t = uh <= 32 ? union_tile_count<false, false>(slots, lane) : union_tile_count<false, true>(slots, lane);
   wave_sync_lds();
-  if (c.a->stats_on) {
+  if (c.stats) {
     const int n = np + nq;
     stat_add(c, 14, (unsigned long long)kept);
     stat_add(c, 5, 1ull);
@@ -1339,7 +1340,7 @@ __device__ __forceinline__ void union_pair_box(Ctx& c, const PairRegs<N>& r, int
   else
     t = uh <= 32 ? union_counts<false, uint32_t, N>(c, r, np, nq, x0, y0)
                  : union_counts<false, uint64_t, N>(c, r, np, nq, x0, y0);
-  if (c.a->stats_on) {
+  if (c.stats) {
     const int n = np + nq;
     stat_add(c, 5, 1ull);
     stat_add(c, 11, (unsigned long long)uw * uh);
@@ -1530,7 +1531,7 @@ __device__ __forceinline__ uint64_t sweep_rows(Ctx& c, const PairRegs<N>& r, int
     }
     wave_sync_lds();
   }
-  if (c.a->stats_on) {
+  if (c.stats) {
     stat_add(c, 1, (unsigned long long)gx * gy);
     stat_add(c, 0, 2ull * (unsigned long long)bw * bh);
     stat_add(c, 10, (unsigned long long)(np + nq) * gy);
@@ -1680,7 +1681,7 @@ __device__ __forceinline__ uint32_t pair_box_count(Ctx& c, const PairRegs<N>& r,
   else
     t = bh <= 32 ? union_counts<false, uint32_t, N, true>(c, r, np, nq, box.x0, box.y0)
                  : union_counts<false, uint64_t, N, true>(c, r, np, nq, box.x0, box.y0);
-  if (c.a->stats_on) {
+  if (c.stats) {
     stat_add(c, 1, 1ull);
     stat_add(c, 0, 2ull * (unsigned long long)bw * bh);
     stat_add(c, 10, (unsigned long long)(np + nq));
@@ -1849,14 +1850,16 @@ __global__ void __launch_bounds__(256) k_batch_prepass(BatchArgs args) {
 // kPairBox: pairs whose union box exceeds a leaf tile are counted on their
 // pair box when it fits one (the same counts as the medium sweep's, without
 // loading the rings again); a separate instance keeps the extra registers
-// off the plain sweep, which most mixes run.
-template <bool kPairBox>
+// off the plain sweep, which most mixes run.  kStats: the work counters are
+// kept (an instance of its own, so that the others carry no test for them).
+template <bool kPairBox, bool kStats>
 __global__ void __launch_bounds__(kSweepWaves* kWave)
     __attribute__((amdgpu_waves_per_eu(kPairBox ? SCCG_SWEEP_PB_WAVES_PER_EU : SCCG_SWEEP_WAVES_PER_EU)))
 k_batch_sweep(BatchArgs args) {
   __shared__ __align__(16) uint64_t sweep_slots[kSweepWaves * kLeafSlots];
   Ctx c;
   c.a = &args;
+  c.stats = kStats;
   c.lane = lane_id();
   c.slots = sweep_slots + (threadIdx.x / kWave) * kLeafSlots;
   c.local = nullptr;
@@ -1973,11 +1976,13 @@ __device__ __forceinline__ void medium_one(Ctx& c, const SweepRec& s, const Pair
   }
 }
 
+template <bool kStats>
 __global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs args) {
   constexpr int kMediumSlots = 2 * kSweepRowTiles * kWave;
   __shared__ __align__(16) uint64_t medium_slots[kSweepWaves * kMediumSlots];
   Ctx c;
   c.a = &args;
+  c.stats = kStats;
   c.lane = lane_id();
   c.slots = medium_slots + (threadIdx.x / kWave) * kMediumSlots;
   c.local = nullptr;
@@ -2030,6 +2035,7 @@ __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args)
   const int wave = threadIdx.x / kWave;
   Ctx c;
   c.a = &args;
+  c.stats = args.stats_on != 0;
   c.lane = lane_id();
   unsigned char* lds = smem + (size_t)wave * kLdsPerWave;
   c.slots = reinterpret_cast<uint64_t*>(lds);
@@ -2241,14 +2247,14 @@ int batch_occupancy(int waves_per_wg) {
 int batch_sweep_occupancy(bool pair_box) {
   int n = 0;
   const hipError_t e =
-      pair_box ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep<true>, kSweepWaves * kWave, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep<false>, kSweepWaves * kWave, 0);
+      pair_box ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep<true, false>, kSweepWaves * kWave, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_sweep<false, false>, kSweepWaves * kWave, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
 int batch_medium_occupancy() {
   int n = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_medium, kSweepWaves * kWave, 0);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_medium<false>, kSweepWaves * kWave, 0);
   return e == hipSuccess && n > 0 ? n : 1;
 }
 
@@ -2256,11 +2262,22 @@ int batch_sweep_waves_per_wg() { return kSweepWaves; }
 
 hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, int medium_grid, bool pair_box, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
-  if (pair_box)
-    hipLaunchKernelGGL(k_batch_sweep<true>, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
+  // the instances with counters run the same grids as those without (a
+  // workgroup the device cannot hold yet waits its turn; no wave waits on
+  // another)
+  const dim3 b(kSweepWaves * kWave);
+  if (pair_box && a.stats_on)
+    hipLaunchKernelGGL((k_batch_sweep<true, true>), dim3(sweep_grid), b, 0, s, a);
+  else if (pair_box)
+    hipLaunchKernelGGL((k_batch_sweep<true, false>), dim3(sweep_grid), b, 0, s, a);
+  else if (a.stats_on)
+    hipLaunchKernelGGL((k_batch_sweep<false, true>), dim3(sweep_grid), b, 0, s, a);
   else
-    hipLaunchKernelGGL(k_batch_sweep<false>, dim3(sweep_grid), dim3(kSweepWaves * kWave), 0, s, a);
-  hipLaunchKernelGGL(k_batch_medium, dim3(medium_grid), dim3(kSweepWaves * kWave), 0, s, a);
+    hipLaunchKernelGGL((k_batch_sweep<false, false>), dim3(sweep_grid), b, 0, s, a);
+  if (a.stats_on)
+    hipLaunchKernelGGL(k_batch_medium<true>, dim3(medium_grid), b, 0, s, a);
+  else
+    hipLaunchKernelGGL(k_batch_medium<false>, dim3(medium_grid), b, 0, s, a);
   return hipGetLastError();
 }
 
