@@ -2030,12 +2030,13 @@ __global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs a
 // first, then the sweep's pairs whose box is larger than a leaf tile), each
 // with its box from the prepass or the sweep.  Waves claim, in this order:
 // boxes from their queue, listed pairs, boxes from any queue.
+template <bool kStats>
 __global__ void __launch_bounds__(512) SCCG_RUN_ATTR k_batch_run(BatchArgs args) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int wave = threadIdx.x / kWave;
   Ctx c;
   c.a = &args;
-  c.stats = args.stats_on != 0;
+  c.stats = kStats;
   c.lane = lane_id();
   unsigned char* lds = smem + (size_t)wave * kLdsPerWave;
   c.slots = reinterpret_cast<uint64_t*>(lds);
@@ -2239,7 +2240,7 @@ hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s) {
 int batch_occupancy(int waves_per_wg) {
   int n = 0;
   const size_t lds = (size_t)waves_per_wg * batch_lds_bytes_per_wave();
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_run, waves_per_wg * kWave, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_run<false>, waves_per_wg * kWave, lds) != hipSuccess)
     return 1;
   return n > 0 ? n : 1;
 }
@@ -2284,7 +2285,10 @@ hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, int medium_gr
 hipError_t launch_batch_persistent(const BatchArgs& a, int grid, int waves_per_wg, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
   const size_t lds = (size_t)waves_per_wg * batch_lds_bytes_per_wave();
-  hipLaunchKernelGGL(k_batch_run, dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
+  if (a.stats_on)
+    hipLaunchKernelGGL(k_batch_run<true>, dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_batch_run<false>, dim3(grid), dim3(waves_per_wg * kWave), lds, s, a);
   if (a.stats_on)
     hipLaunchKernelGGL(k_batch_stats_empty, dim3((unsigned)((a.n_pairs + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
