@@ -739,13 +739,17 @@ def test_jaccard_sets_layouts(ctx, wl3s, layout):
     assert np.array_equal(j.cpu().numpy(), oj) and np.array_equal(jp.cpu().numpy(), ojp)
 
 
-def test_batched_stats(wl3s):
-    wl, _, _ = wl3s
-    c = sccg.Context(0, min_classify_cells=1)
+@pytest.mark.parametrize("spb", [1, 2])
+def test_batched_stats(wl3s, spb):
+    """The kernel instances that keep work counters give the oracle's counts
+    too, and the counters add up (each pair is small, large or empty)."""
+    wl, eI, eU = wl3s
+    c = sccg.Context(0, min_classify_cells=1, sweep_pair_box=spb)
     c.set_stats(True)
-    run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
+    gI, gU = run(c, device_workload(wl.A, wl.B, wl.pa, wl.pb), sccg.SCCG_BATCHED)
     s = c.get_stats()
     c.close()
+    assert_exact(gI, gU, eI, eU, f"counters on, sweep_pair_box {spb}")
     assert s["small_pairs"] + s["large_pairs"] + s["empty_pairs"] == wl.n_pairs
     assert s["leaf_pixel_tests"] > 0 and s["leaf_boxes"] >= s["small_pairs"]
     assert s["large_pairs"] > 0 and s["split_boxes"] >= s["large_pairs"]
