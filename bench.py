@@ -663,7 +663,7 @@ def main(argv=None):
     prof = profile_summary(args.workload, tuned)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s",
                 "frac": achieved / VALU_PEAK_OPS, "traffic": prof["bytes_per_launch"] if prof else None,
-                "kernel": "batched call: k_batch_clear_*, k_batch_setup, k_batch_prepass, k_batch_sweep, "
+                "kernel": "batched call: k_batch_clear_*, k_batch_setup, k_batch_sweep, "
                           "k_batch_medium, k_batch_run (one HIP event bracket)", "kernel_ms": k_avg_ms,
                 "algorithmic_ops_per_launch": algo_ops, "algorithmic_bytes_per_launch": algo_bytes,
                 "hbm_frac_algorithmic": (algo_bytes / (k_avg_ms / 1e3)) / HBM_PEAK}

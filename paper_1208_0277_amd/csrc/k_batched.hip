@@ -35,8 +35,9 @@
 //   - The pair's MBRs and shoelace areas are reduced by the wave that takes
 //     the pair, from the same coalesced ring loads it needs anyway; only the
 //     pairs with many vertices ("heavy", claimed first: a largest-first
-//     order) get them from a prepass, so that any wave can take one of their
-//     boxes.
+//     order) get them from a prepass, run by half the medium sweep's waves
+//     beside the other half's computation, so that any wave can take one of
+//     their boxes.
 //   - One persistent grid.  Waves claim, in this order: boxes from their
 //     queue, heavy pairs, chunks of the other pairs, boxes from any queue.
 //     Claims go through per-stream counters (one stream per XCD) on cache
@@ -354,8 +355,10 @@ __device__ __forceinline__ void ring_extent(const int2* xy, int64_t o, int64_t n
 
 // The same extent and area for the prepass of listed (long) rings: each
 // lane loads its vertices and their successors directly, kScanBatch chunks
-// of 64 per round trip, so that a long ring costs few memory latencies.
-constexpr int kScanBatch = 8;
+// of 64 per round trip, so that a long ring costs few memory latencies (four:
+// the prepass shares its kernel with the medium sweep, whose computation
+// hides them).
+constexpr int kScanBatch = 4;
 __device__ __forceinline__ void ring_scan(const int2* xy, int64_t o, int64_t nv64, int lane, Meta& m, int64_t& area) {
   const int nv = uniform((int)nv64);
   m = Meta{INT_MAX, INT_MAX, INT_MIN, INT_MIN};  // covers nothing
@@ -1788,63 +1791,51 @@ __device__ __forceinline__ void sweep_one_pb(Ctx& c, const SweepRec& s, const Pa
   dmask |= 1ull << j;
 }
 
-// The prepass of the pairs the setup pass listed: per pair, one wave
-// reduces the MBRs and areas of both rings and records the pair box and the
-// pair's class; the outputs start at I = 0, U = |p| + |q| (boxes add to I and
-// subtract from U atomically).  Wave w takes entries w, w + waves, ... of
-// the buckets laid end to end, largest first.
-__global__ void __launch_bounds__(256) k_batch_prepass(BatchArgs args) {
-  const BatchArgs& a = args;
-  const int lane = lane_id();
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  int64_t nb[kLptBuckets], n = 0;
+// The prepass of a pair the setup pass listed (entry k of its buckets laid
+// end to end, largest first, nb[b] entries in bucket b): one wave reduces
+// the MBRs and areas of both rings and records the pair box and the pair's
+// class; the outputs start at I = 0, U = |p| + |q| (boxes add to I and
+// subtract from U atomically).
+__device__ __forceinline__ void prepass_one(const BatchArgs& a, int64_t k, const int64_t (&nb)[kLptBuckets], int lane,
+                                            bool stats) {
+  int64_t kk = k;
+  int bk = kLptBuckets - 1;
 #pragma unroll
-  for (int b = 0; b < kLptBuckets; ++b) {
-    nb[b] = (int64_t)a.st->l_count[b].v;
-    n += nb[b];
-  }
-  for (int64_t k = wave; k < n; k += waves) {
-    // entry k of the buckets laid end to end, largest first
-    int64_t kk = k;
-    int bk = kLptBuckets - 1;
-#pragma unroll
-    for (int b = kLptBuckets - 1; b > 0; --b) {
-      if (bk == b && kk >= nb[b]) {
-        kk -= nb[b];
-        bk = b - 1;
-      }
+  for (int b = kLptBuckets - 1; b > 0; --b) {
+    if (bk == b && kk >= nb[b]) {
+      kk -= nb[b];
+      bk = b - 1;
     }
-    const int64_t i = a.l_list[(int64_t)bk * a.n_pairs + kk];
-    const int64_t ia = a.pa[i], ib = a.pb[i];
-    const int64_t op = a.A.off[ia], oq = a.B.off[ib];
-    Meta mp, mq;
-    int64_t ap, aq;
-    ring_scan(a.A.xy, op, a.A.off[ia + 1] - op, lane, mp, ap);
-    ring_scan(a.B.xy, oq, a.B.off[ib + 1] - oq, lane, mq, aq);
-    if (lane != 0) continue;
-    if (a.stats_on) atomicAdd(&a.st->stats[12], (unsigned long long)(a.A.off[ia + 1] - op + a.B.off[ib + 1] - oq));
-    if (coords_bad(mp, a.A.off[ia + 1] - op) || coords_bad(mq, a.B.off[ib + 1] - oq)) latch_error(a.err, kErrCoord);
-    const Meta b = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
-    *reinterpret_cast<int4*>(a.hbox + i) = make_int4(b.x0, b.y0, b.x1, b.y1);
-    const int64_t w = (int64_t)b.x1 - b.x0, h = (int64_t)b.y1 - b.y0;
-    uint8_t cls = kClsDone;
-    a.inter[i] = 0;
-    a.uni[i] = direct_union(a) ? 0 : ap + aq;
-    if (b.x0 >= b.x1 || b.y0 >= b.y1) {
-      cls = kClsDone;
-    } else if (w > kMaxSide || h > kMaxSide) {
-      latch_error(a.err, kErrSide);
-      a.uni[i] = 0;
-    } else {
-      cls = (w <= kTile && h <= kTile) ? kClsSmall : kClsLarge;
-      if (a.stats_on) {
-        atomicAdd(&a.st->stats[cls == kClsSmall ? 5 : 6], 1ull);
-        atomicAdd(&a.st->stats[11], (unsigned long long)(w * h));
-      }
-    }
-    a.cls[i] = cls;
   }
+  const int64_t i = a.l_list[(int64_t)bk * a.n_pairs + kk];
+  const int64_t ia = a.pa[i], ib = a.pb[i];
+  const int64_t op = a.A.off[ia], oq = a.B.off[ib];
+  Meta mp, mq;
+  int64_t ap, aq;
+  ring_scan(a.A.xy, op, a.A.off[ia + 1] - op, lane, mp, ap);
+  ring_scan(a.B.xy, oq, a.B.off[ib + 1] - oq, lane, mq, aq);
+  if (lane != 0) return;
+  if (stats) atomicAdd(&a.st->stats[12], (unsigned long long)(a.A.off[ia + 1] - op + a.B.off[ib + 1] - oq));
+  if (coords_bad(mp, a.A.off[ia + 1] - op) || coords_bad(mq, a.B.off[ib + 1] - oq)) latch_error(a.err, kErrCoord);
+  const Meta b = direct_union(a) ? union_box(mp, mq) : pair_box(mp, mq);
+  *reinterpret_cast<int4*>(a.hbox + i) = make_int4(b.x0, b.y0, b.x1, b.y1);
+  const int64_t w = (int64_t)b.x1 - b.x0, h = (int64_t)b.y1 - b.y0;
+  uint8_t cls = kClsDone;
+  a.inter[i] = 0;
+  a.uni[i] = direct_union(a) ? 0 : ap + aq;
+  if (b.x0 >= b.x1 || b.y0 >= b.y1) {
+    cls = kClsDone;
+  } else if (w > kMaxSide || h > kMaxSide) {
+    latch_error(a.err, kErrSide);
+    a.uni[i] = 0;
+  } else {
+    cls = (w <= kTile && h <= kTile) ? kClsSmall : kClsLarge;
+    if (stats) {
+      atomicAdd(&a.st->stats[cls == kClsSmall ? 5 : 6], 1ull);
+      atomicAdd(&a.st->stats[11], (unsigned long long)(w * h));
+    }
+  }
+  a.cls[i] = cls;
 }
 
 // kPairBox: pairs whose union box exceeds a leaf tile are counted on their
@@ -1870,6 +1861,9 @@ k_batch_sweep(BatchArgs args) {
   const int lane = c.lane;
   const bool union_ok = direct_union(a) || !(a.flags & SCCG_F_NO_UNION_TILE);
   const unsigned long long t_start = wave_stamp(a);
+  // the prepass (run beside the medium sweep) takes the pairs the setup pass
+  // listed: their counts, taken here, before the medium sweep lists more
+  if (blockIdx.x == 0 && threadIdx.x < kLptBuckets) a.st->p_count[threadIdx.x].v = a.st->l_count[threadIdx.x].v;
   // claim streams found exhausted (wave-uniform); a wave claims only from
   // its own XCD's stream (the streams hold equal interleaved shares), so
   // that running dry costs it one claim, not one per stream (a grid too
@@ -1932,6 +1926,12 @@ k_batch_sweep(BatchArgs args) {
 // rings in registers; a pair box at most kSweepRowTiles tiles wide is
 // pixelized at once (a box the persistent kernel would not classify), a
 // larger one is listed with its box.  A claim takes 64 consecutive entries.
+// The same kernel runs the prepass of the pairs the setup pass listed: its
+// ring scans wait on memory while the medium pairs compute, so half the
+// waves start with it and half with the medium list, each turning to the
+// other list when its own runs dry.  (Six waves per SIMD, a few registers
+// spilled: at the unconstrained register count only four fit.)
+//
 // Every chunk of both rings of a medium pair (clamped to each ring's last
 // vertex), or for no pair reads of `dummy`.
 __device__ __forceinline__ void medium_load(const BatchArgs& a, const SweepRec& s, const int2* dummy, int lane,
@@ -1977,7 +1977,7 @@ __device__ __forceinline__ void medium_one(Ctx& c, const SweepRec& s, const Pair
 }
 
 template <bool kStats>
-__global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs args) {
+__global__ void __launch_bounds__(kSweepWaves* kWave) __attribute__((amdgpu_waves_per_eu(6))) k_batch_medium(BatchArgs args) {
   constexpr int kMediumSlots = 2 * kSweepRowTiles * kWave;
   __shared__ __align__(16) uint64_t medium_slots[kSweepWaves * kMediumSlots];
   Ctx c;
@@ -1992,34 +1992,60 @@ __global__ void __launch_bounds__(kSweepWaves* kWave) k_batch_medium(BatchArgs a
   const BatchArgs& a = args;
   const int lane = c.lane;
   const unsigned long long t_start = wave_stamp(a);
+  // the prepass entries (the setup pass's listed pairs, counted by the union
+  // sweep), one per claim
+  int64_t nb[kLptBuckets], n_pre = 0;
+#pragma unroll
+  for (int b = 0; b < kLptBuckets; ++b) {
+    nb[b] = (int64_t)a.st->p_count[b].v;
+    n_pre += nb[b];
+  }
   const int64_t n_med = (int64_t)a.st->m_count.v;
   // entries per claim: 64, or fewer when the list gives the grid's waves
   // less than 8 claims each
   const int64_t per_wave = n_med / ((int64_t)gridDim.x * kSweepWaves * 8);
   const int chunk = (int)max((int64_t)1, min((int64_t)kWave, per_wave));
-  uint32_t m_empty = kSweepSteal || gridDim.x < (unsigned)kStreams ? 0u : (0xffu & ~(1u << c.xcd));
-  for (;;) {
-    const int64_t e0 = claim_chunk(a.st->m_next, n_med, chunk, c.xcd, lane, m_empty);
-    if (e0 < 0) break;
-    const int cnt = uniform((int)min((int64_t)chunk, n_med - e0));
-    // lane j: pair index and record of entry e0 + j
-    const int idx = lane < cnt ? a.m_list[e0 + lane] : 0;
-    const ChunkRecs cr = gather_recs(a, idx, lane < cnt);
-    const int2* dummy = reinterpret_cast<const int2*>(a.rec + __builtin_amdgcn_readfirstlane(idx));
-    // the pair in hand (sc, rc) and the next one (sn, rn), whose loads are in
-    // flight while the pair in hand is processed: every chunk of both rings,
-    // loaded the same way whatever the pair, so that the compiler waits only
-    // for the pair in hand's loads
-    PairRegs<kMediumChunks> rc, rn;
-    SweepRec sc = sweep_rec(cr, 0);
-    medium_load(a, sc, dummy, lane, rc);
+  const uint32_t own = kSweepSteal || gridDim.x < (unsigned)kStreams ? 0u : (0xffu & ~(1u << c.xcd));
+  uint32_t m_empty = own, p_empty = own;
+  // half the waves start with the prepass, which waits on memory, the other
+  // half with the medium list, which computes; each turns to the other list
+  // when its own runs dry
+  const bool pre_first = ((threadIdx.x / kWave) & 1) == 0;
 #pragma unroll 1
-    for (int j = 0; j < cnt; ++j) {
-      const SweepRec sn = j + 1 < cnt ? sweep_rec(cr, j + 1) : SweepRec{0, 0, 0, 0, kClsDone};
-      medium_load(a, sn, dummy, lane, rn);
-      medium_one(c, sc, rc, (int64_t)__builtin_amdgcn_readlane(idx, j));
-      sc = sn;
-      rc = rn;
+  for (int phase = 0; phase < 2; ++phase) {
+    if ((phase == 0) == pre_first) {
+#pragma unroll 1
+      for (;;) {
+        const int64_t k = claim_chunk(a.st->p_next, n_pre, 1, c.xcd, lane, p_empty);
+        if (k < 0) break;
+        prepass_one(a, k, nb, lane, kStats);
+      }
+      continue;
+    }
+#pragma unroll 1
+    for (;;) {
+      const int64_t e0 = claim_chunk(a.st->m_next, n_med, chunk, c.xcd, lane, m_empty);
+      if (e0 < 0) break;
+      const int cnt = uniform((int)min((int64_t)chunk, n_med - e0));
+      // lane j: pair index and record of entry e0 + j
+      const int idx = lane < cnt ? a.m_list[e0 + lane] : 0;
+      const ChunkRecs cr = gather_recs(a, idx, lane < cnt);
+      const int2* dummy = reinterpret_cast<const int2*>(a.rec + __builtin_amdgcn_readfirstlane(idx));
+      // the pair in hand (sc, rc) and the next one (sn, rn), whose loads are in
+      // flight while the pair in hand is processed: every chunk of both rings,
+      // loaded the same way whatever the pair, so that the compiler waits only
+      // for the pair in hand's loads
+      PairRegs<kMediumChunks> rc, rn;
+      SweepRec sc = sweep_rec(cr, 0);
+      medium_load(a, sc, dummy, lane, rc);
+#pragma unroll 1
+      for (int j = 0; j < cnt; ++j) {
+        const SweepRec sn = j + 1 < cnt ? sweep_rec(cr, j + 1) : SweepRec{0, 0, 0, 0, kClsDone};
+        medium_load(a, sn, dummy, lane, rn);
+        medium_one(c, sc, rc, (int64_t)__builtin_amdgcn_readlane(idx, j));
+        sc = sn;
+        rc = rn;
+      }
     }
   }
   wave_stamps(a, 1, t_start, lane);
@@ -2218,12 +2244,6 @@ __global__ void k_batch_stats_empty(BatchArgs a) {
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_clear_slots, dim3(1024), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_batch_clear_counters, dim3(1), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_prepass(const BatchArgs& a, hipStream_t s) {
-  if (a.n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_prepass, dim3(2048), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

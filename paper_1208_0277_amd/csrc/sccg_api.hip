@@ -475,14 +475,13 @@ __global__ void k_zero_stats(unsigned long long* s) {
 }
 
 // The launches of one BATCHED call on the context's stream: reset, setup,
-// the prepass of listed pairs, the two sweeps, the persistent kernel.  (A
-// prepass on a second stream beside the sweeps measured no faster: it takes
-// the sweeps' issue slots.)
+// the union sweep, the medium sweep with the prepass of the listed pairs,
+// the persistent kernel.  (A prepass on a second stream beside the sweeps
+// measured no faster: the union sweep holds every wave slot.)
 static int launch_batch_sequence(sccg_ctx* c, const BatchArgs& ba, int sweep_grid, int medium_grid, int grid) {
   hipError_t e;
   if ((e = launch_batch_reset(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch reset");
   if ((e = launch_batch_setup(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch setup");
-  if ((e = launch_batch_prepass(ba, c->stream)) != hipSuccess) return hip_fail(c, e, "batch prepass");
   if ((e = launch_batch_sweeps(ba, sweep_grid, medium_grid, c->p.sweep_pair_box == 2, c->stream)) != hipSuccess)
     return hip_fail(c, e, "batch sweeps");
   if ((e = launch_batch_persistent(ba, grid, c->p.waves_per_wg, c->stream)) != hipSuccess)

@@ -97,6 +97,8 @@ struct BatchState {
   Counter s_next[kStreams];   // per-stream claim counters over pair chunks (the sweep)
   Counter m_count;            // medium pairs listed (by the setup pass and the sweep)
   Counter m_next[kStreams];   // per-stream claim counters over chunks of the medium list
+  Counter p_count[kLptBuckets];  // pairs the setup pass listed per bucket (the prepass's share)
+  Counter p_next[kStreams];      // per-stream claim counters over the prepass's entries
   Counter q_head[kMaxGrid];   // per-queue ticket counters
   Counter q_tail[kMaxGrid];   // per-queue reservation counters
   unsigned long long stats[kNumStats];
@@ -144,9 +146,8 @@ struct BatchArgs {
 constexpr int kStampedKernels = 3;
 hipError_t launch_batch_reset(const BatchArgs& a, hipStream_t s);
 hipError_t launch_batch_setup(const BatchArgs& a, hipStream_t s);
-// The prepass of the pairs the setup pass listed.
-hipError_t launch_batch_prepass(const BatchArgs& a, hipStream_t s);
-// The union sweep (sweep_grid workgroups) then the medium sweep (medium_grid);
+// The union sweep (sweep_grid workgroups) then the medium sweep with the
+// prepass of the pairs the setup pass listed (medium_grid);
 // pair_box: the union sweep also counts the pairs whose pair box fits a leaf
 // tile (else the medium sweep does).
 hipError_t launch_batch_sweeps(const BatchArgs& a, int sweep_grid, int medium_grid, bool pair_box, hipStream_t s);
